@@ -1,0 +1,207 @@
+/*
+ * mcinv -- correlated-chains Monte Carlo estimation of entries, the diagonal
+ * and the trace of C^-1 for a sparse, possibly non-hermitian matrix C, on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Method: Garcia-Cortes & Cabrillo, "A Monte Carlo algorithm for efficient
+ * large matrix inversion".  Two vectors z, w are updated row by row with the
+ * SAME noise draw phi (Sec. 2, eqs 4 and 5; noise law eqs 5a, 5b):
+ *
+ *   z_i <- phi_i a_i - (1/c_ii)      [ sum_{j<i} c_ij z_j^(k) + sum_{j>i} c_ij z_j^(k-1) ]
+ *   w_i <- phi_i b_i - (1/conj c_ii) [ sum_{j<i} conj(c_ji) w_j^(k) + sum_{j>i} conj(c_ji) w_j^(k-1) ]
+ *
+ * so that after burn-in E[z w^dagger] = C^-1 (eq 1/C) and E[w^dagger z] =
+ * tr C^-1 (eq tr).  The library runs many independent chain pairs at once.
+ *
+ * Conventions used by every entry point:
+ *   - Rows are swept in a greedy multicolour order: a symmetric permutation
+ *     P C P^T of the matrix, so one sweep is still eqs 4-5 on the permuted
+ *     matrix (Sec. 4 notes that row/column reordering is allowed).  All inputs
+ *     and outputs use the caller's ORIGINAL row indices.
+ *   - Noise scales satisfy a_i conj(b_i) = 1/c_ii: real c_ii: a = 1/sqrt|c_ii|,
+ *     b = sign(c_ii) a; complex: a = 1/sqrt(c_ii) (principal), b = conj(a).
+ *   - Noise for (row i, sweep k, pair p) is output (p mod 4) of Philox4x32-10
+ *     with key (seed lo, seed hi) and counter (i, k, p div 4, stream_id), turned
+ *     into N(0,1) by Box-Muller on u = ((x >> 9) + 1/2) 2^-23, or into +-1 (Z2
+ *     noise: the sign bit), or 0 (the noiseless Gauss-Seidel of eq 12).
+ *   - Complex values are interleaved (re, im) pairs of the stated precision.
+ *   - Estimates of entry (i,j) are means of z_i conj(w_j); the trace estimate
+ *     is the mean of sum_i z_i conj(w_i) per pair.
+ *   - Standard errors: clusters of samples -- chain groups (n_groups >= 16) or
+ *     groups x time batches (fewer groups; at most 64 batches, batch length a
+ *     power of two) -- with the ratio estimator; the trace uses Geyer's
+ *     initial positive sequence on the per-sweep series (Sec. 2.3).
+ *
+ * Ownership: the caller owns every host pointer it passes; the library copies
+ * inputs before returning and writes outputs into caller-allocated memory.  A
+ * context owns all of its device memory.  A context is not thread-safe; calls
+ * on one context must not overlap.
+ *
+ * Every function returns an mcinv_status: 0 on success, a negative code on
+ * failure (the message is available from mcinv_last_error).
+ */
+#ifndef MCINV_H
+#define MCINV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mcinv_status;
+
+#define MCINV_OK          0
+#define MCINV_EINVAL     -1  /* bad argument: shape, order, duplicate, range    */
+#define MCINV_ESINGULAR  -2  /* a row has no stored or a zero diagonal (Sec 2.2) */
+#define MCINV_ESTATE     -3  /* call out of order (e.g. sample before load_csr)  */
+#define MCINV_ENOMEM     -4  /* device or host allocation failed                 */
+#define MCINV_EDEVICE    -5  /* a HIP runtime error                              */
+#define MCINV_EDIVERGED  -6  /* non-finite or runaway chain state: sp(T) or sp(S)
+                                is not below one (Sec. 2.2)                      */
+
+/* Sweep (state) precision. */
+#define MCINV_R32   0   /* real, float32 state            */
+#define MCINV_R64   1   /* real, float64 state            */
+#define MCINV_C64   2   /* complex, 2 x float32 state     */
+#define MCINV_C128  3   /* complex, 2 x float64 state     */
+
+/* Noise law (eqs 5a, 5b). */
+#define MCINV_NOISE_NORMAL     0
+#define MCINV_NOISE_RADEMACHER 1
+#define MCINV_NOISE_NONE       2
+
+/* Dense-block moment arithmetic. */
+#define MCINV_MOMENTS_FP64   0   /* fp64 products and sums                        */
+#define MCINV_MOMENTS_BF16X3 1   /* fp32 state split into bf16 hi+lo, three MFMA
+                                    products with fp32 accumulation, fp64 sums   */
+
+/* Requested quantities (bit flags). */
+#define MCINV_REQ_DIAG    1u
+#define MCINV_REQ_TRACE   2u
+#define MCINV_REQ_BLOCK   4u
+#define MCINV_REQ_ENTRIES 8u
+
+typedef struct mcinv_ctx mcinv_ctx;
+
+typedef struct {
+    int32_t  device;       /* HIP device ordinal                                     */
+    int32_t  sweep_dtype;  /* MCINV_R32 .. MCINV_C128; real dtypes need a real C     */
+    int32_t  moments;      /* MCINV_MOMENTS_*                                        */
+    int32_t  noise;        /* MCINV_NOISE_*                                          */
+    int64_t  n_pairs;      /* P >= 1 independent (z, w) chain pairs                  */
+    int32_t  n_groups;     /* G >= 1 chain groups for error estimates; P % G == 0 and
+                              P/G is 1 (only with G == P... see below), a power of two
+                              >= 4 up to 256, or a multiple of 256; G == 1 always ok  */
+    uint32_t stream_id;    /* fourth Philox counter word (distinct problems)        */
+    uint64_t seed;         /* Philox key                                             */
+    void*    stream;       /* hipStream_t to launch on, or NULL for a library stream */
+    int32_t  profile;      /* nonzero: time every sweep launch with HIP events       */
+    int32_t  reserved;
+} mcinv_config;
+
+typedef struct {
+    int64_t n, nnz, n_pairs, ld;      /* ld: padded pairs per state row           */
+    int32_t n_colors, n_groups;
+    int64_t sweeps_done, samples_done;
+    int64_t batch_len, n_batches;     /* time batching of the error clusters       */
+    int64_t offdiag_entries;          /* merged symmetric-pattern entries stored   */
+    double  sweep_kernel_ms;          /* profile: summed sweep-kernel time         */
+    int64_t sweep_kernel_launches;    /* profile: number of sweep launches timed   */
+    double  moment_kernel_ms;         /* profile: block/entry moment kernels       */
+    int64_t moment_kernel_launches;
+} mcinv_info;
+
+/* Create a context on cfg->device.  *out receives the handle.
+ * EINVAL: bad dtype, noise, pairs or group layout.  EDEVICE: HIP failure. */
+mcinv_status mcinv_create(const mcinv_config* cfg, mcinv_ctx** out);
+
+/* Release every resource of ctx (NULL is allowed). */
+void mcinv_destroy(mcinv_ctx* ctx);
+
+/* Load C (Sec. 2: the matrix to invert) from host CSR arrays.
+ * row_ptr int64[n+1] (row_ptr[0] == 0, non-decreasing), col_idx int32[nnz]
+ * (strictly increasing within a row, 0 <= col < n), values[nnz] of value_dtype
+ * (MCINV_R64 or MCINV_C128, interleaved complex).  Every row must hold a
+ * nonzero diagonal entry (ESINGULAR otherwise, Sec. 2.2).  Builds the transpose
+ * (eq 5 reads column i of C), the per-row constants in float64 (rounded to the
+ * sweep precision), the multicolour order, and uploads everything.  Resets the
+ * chain state to z = w = 0 (Algorithm 1, step 1) and clears all moments. */
+mcinv_status mcinv_load_csr(mcinv_ctx* ctx, int64_t n, int64_t nnz, const int64_t* row_ptr,
+                            const int32_t* col_idx, const void* values, int32_t value_dtype);
+
+/* Choose what to estimate (eq 1/C, eq tr): flags of MCINV_REQ_*; a dense block
+ * rows x cols (original indices, any order, may repeat); and a list of entries
+ * (entry_i[e], entry_j[e]).  Clears every moment accumulator and the sample
+ * count (the chain state is kept).  EINVAL on an index out of range. */
+mcinv_status mcinv_set_requested(mcinv_ctx* ctx, uint32_t flags,
+                                 const int64_t* block_rows, int64_t n_block_rows,
+                                 const int64_t* block_cols, int64_t n_block_cols,
+                                 const int64_t* entry_i, const int64_t* entry_j, int64_t n_entries);
+
+/* Run `sweeps` sweeps without accumulating (the burn-in period of Sec. 2.3).
+ * EDIVERGED if the state became non-finite or exceeded 1e30 in magnitude. */
+mcinv_status mcinv_burn_in(mcinv_ctx* ctx, int64_t sweeps);
+
+/* Run `sweeps` sweeps, each adding one sample per chain pair to every
+ * requested moment (eq 1/C, eq tr).  ESTATE before mcinv_set_requested. */
+mcinv_status mcinv_sample(mcinv_ctx* ctx, int64_t sweeps);
+
+/* Sample in chunks of check_every sweeps until the largest relative standard
+ * error max_i SE_i/|est_i| over the diagonal is <= rel_se, or max_sweeps were
+ * run.  Needs MCINV_REQ_DIAG.  *sweeps_done (may be NULL) receives the count,
+ * *achieved (may be NULL) the last max relative SE. */
+mcinv_status mcinv_sample_until(mcinv_ctx* ctx, double rel_se, int64_t max_sweeps,
+                                int64_t check_every, int64_t* sweeps_done, double* achieved);
+
+/* Estimates and standard errors in original indexing, caller-allocated.
+ * quantity: one of MCINV_REQ_DIAG (n values), MCINV_REQ_BLOCK (rows x cols,
+ * row-major), MCINV_REQ_ENTRIES (n_entries), MCINV_REQ_TRACE (1 value).
+ * est receives 1 double per value for a real C, 2 (re, im) for a complex C;
+ * stderr_ receives 1 double per value (sqrt(SE_re^2 + SE_im^2)); either may be
+ * NULL.  capacity = number of values the arrays can hold (EINVAL if short).
+ * SE is NaN while fewer than two clusters hold samples. */
+mcinv_status mcinv_read_estimates(mcinv_ctx* ctx, uint32_t quantity, double* est,
+                                  double* stderr_, int64_t capacity);
+
+/* Copy chain state z (which = 0) or w (which = 1) to host as [n][P] in the
+ * sweep precision, original row order.  bytes must be >= n * P * elem size. */
+mcinv_status mcinv_read_state(mcinv_ctx* ctx, int32_t which, void* host, int64_t bytes);
+
+/* Overwrite chain state z or w from a host [n][P] array (sweep precision,
+ * original order), e.g. to start from other initial values (Algorithm 1). */
+mcinv_status mcinv_write_state(mcinv_ctx* ctx, int32_t which, const void* host, int64_t bytes);
+
+/* The sweep order: perm[q] = original row swept at position q (int64[n]);
+ * color_of_row[i] = colour of original row i (int32[n]).  Either may be NULL. */
+mcinv_status mcinv_get_permutation(mcinv_ctx* ctx, int64_t* perm, int32_t* color_of_row);
+
+/* Noiseless sweeps from x_i = i (Algorithm 1's second start) on C x = 0 and
+ * C^dagger y = 0: the Gauss-Seidel iterations eq 12 shows the chain
+ * difference obeys.  Returns the observed contraction rates, which tend to
+ * sp(T) and sp(S) (Sec. 2.3).  Does not touch the chain state.  iters >= 2. */
+mcinv_status mcinv_check_convergence(mcinv_ctx* ctx, int64_t iters, double* rho_T, double* rho_S);
+
+/* Sizes, counters and (when profiling) kernel times. */
+mcinv_status mcinv_get_info(mcinv_ctx* ctx, mcinv_info* out);
+
+/* Zero the profiling counters of mcinv_get_info. */
+mcinv_status mcinv_reset_profile(mcinv_ctx* ctx);
+
+/* Noise values phi(row[t], sweep[t], pair[t]) as the sweep kernels draw them,
+ * generated on the device in the given precision (MCINV_R32 or MCINV_R64) and
+ * copied to out[count] (double).  For checking the generator. */
+mcinv_status mcinv_noise_values(int32_t device, uint64_t seed, uint32_t stream_id,
+                                int32_t noise, int32_t dtype, int64_t count,
+                                const int64_t* row, const int64_t* sweep, const int64_t* pair,
+                                double* out);
+
+/* Message of the last failing call on ctx (or of the last failing call that
+ * had no context, when ctx is NULL). */
+const char* mcinv_last_error(const mcinv_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCINV_H */

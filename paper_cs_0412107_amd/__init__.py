@@ -1,0 +1,119 @@
+"""mcinv on MI355X: correlated-chains Monte Carlo estimation of entries, the
+diagonal and the trace of C^-1 (Garcia-Cortes & Cabrillo), hand-written HIP
+kernels for gfx950 behind the C-ABI of ``include/mcinv.h``.
+
+``Sampler`` is a thin object wrapper over the ``mcinv_*`` binding; PyTorch is
+used only (optionally) to hand the library its current HIP stream.
+"""
+
+from ._binding import *  # noqa: F401,F403
+from ._binding import (DTYPES, MCINV_MOMENTS_BF16X3, MCINV_MOMENTS_FP64, MCINV_NOISE_NORMAL,
+                       MCINV_REQ_BLOCK, MCINV_REQ_DIAG, MCINV_REQ_ENTRIES, MCINV_REQ_TRACE, McinvError, lib,
+                       mcinv_burn_in, mcinv_check_convergence, mcinv_create, mcinv_destroy, mcinv_get_info,
+                       mcinv_get_permutation, mcinv_load_csr, mcinv_read_estimates, mcinv_read_state,
+                       mcinv_reset_profile, mcinv_sample, mcinv_sample_until, mcinv_set_requested,
+                       mcinv_write_state)
+
+__all__ = ["Sampler", "McinvError", "lib"]
+
+
+def torch_stream():
+    """The current torch HIP stream handle (or None when torch has no GPU)."""
+    try:
+        import torch
+    except ImportError:
+        return None
+    if not torch.cuda.is_available():
+        return None
+    return torch.cuda.current_stream().cuda_stream
+
+
+class Sampler:
+    """One context: a matrix, its chain pairs and the requested moments."""
+
+    def __init__(self, matrix, pairs, groups=1, dtype="f32", seed=0, noise=MCINV_NOISE_NORMAL,
+                 moments="fp64", device=0, stream_id=0, use_torch_stream=False, profile=False):
+        self.dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
+        self.is_complex = self.dtype in (DTYPES["c64"], DTYPES["c128"])
+        mom = MCINV_MOMENTS_BF16X3 if moments == "bf16x3" else MCINV_MOMENTS_FP64
+        stream = torch_stream() if use_torch_stream else None
+        self.ctx = mcinv_create(device=device, sweep_dtype=self.dtype, moments=mom, noise=noise,
+                                n_pairs=pairs, n_groups=groups, stream_id=stream_id, seed=seed,
+                                stream=stream, profile=profile)
+        self.n = matrix.n
+        self.P = pairs
+        self.nI = self.nJ = self.ne = 0
+        try:
+            mcinv_load_csr(self.ctx, matrix.n, matrix.nnz, matrix.row_ptr, matrix.col, matrix.val)
+        except Exception:
+            self.close()
+            raise
+
+    def close(self):
+        if getattr(self, "ctx", None) is not None:
+            mcinv_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def request(self, diag=True, trace=True, block_rows=None, block_cols=None, entries=None):
+        flags = (MCINV_REQ_DIAG if diag else 0) | (MCINV_REQ_TRACE if trace else 0)
+        ei = ej = None
+        if block_rows is not None and block_cols is not None and len(block_rows) and len(block_cols):
+            flags |= MCINV_REQ_BLOCK
+            self.nI, self.nJ = len(block_rows), len(block_cols)
+        if entries is not None and len(entries):
+            import numpy as np
+            e = np.asarray(entries, dtype=np.int64).reshape(-1, 2)
+            ei, ej = e[:, 0], e[:, 1]
+            flags |= MCINV_REQ_ENTRIES
+            self.ne = e.shape[0]
+        mcinv_set_requested(self.ctx, flags, block_rows, block_cols, ei, ej)
+
+    def burn_in(self, sweeps):
+        mcinv_burn_in(self.ctx, sweeps)
+
+    def sample(self, sweeps):
+        mcinv_sample(self.ctx, sweeps)
+
+    def sample_until(self, rel_se, max_sweeps, check_every=10):
+        return mcinv_sample_until(self.ctx, rel_se, max_sweeps, check_every)
+
+    def diag(self):
+        return mcinv_read_estimates(self.ctx, MCINV_REQ_DIAG, self.n, self.is_complex)
+
+    def block(self):
+        est, se = mcinv_read_estimates(self.ctx, MCINV_REQ_BLOCK, self.nI * self.nJ, self.is_complex)
+        return est.reshape(self.nI, self.nJ), se.reshape(self.nI, self.nJ)
+
+    def entries(self):
+        return mcinv_read_estimates(self.ctx, MCINV_REQ_ENTRIES, self.ne, self.is_complex)
+
+    def trace(self):
+        est, se = mcinv_read_estimates(self.ctx, MCINV_REQ_TRACE, 1, self.is_complex)
+        return est[0], se[0]
+
+    def state(self, which):
+        return mcinv_read_state(self.ctx, which, self.n, self.P, self.dtype)
+
+    def set_state(self, which, values):
+        mcinv_write_state(self.ctx, which, values, self.dtype)
+
+    def permutation(self):
+        return mcinv_get_permutation(self.ctx, self.n)
+
+    def check_convergence(self, iters=200):
+        return mcinv_check_convergence(self.ctx, iters)
+
+    def info(self):
+        return mcinv_get_info(self.ctx)
+
+    def reset_profile(self):
+        mcinv_reset_profile(self.ctx)

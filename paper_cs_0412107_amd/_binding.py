@@ -1,0 +1,238 @@
+"""ctypes binding of ``libmcinv.so`` (declared in ``include/mcinv.h``).
+
+Every ``mcinv_*`` function here has the name and the argument order of the
+C entry point; it converts NumPy arrays to pointers, raises
+:class:`McinvError` on a negative status and returns outputs as arrays.  No
+step of the method runs in Python.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmcinv.so")
+
+MCINV_OK = 0
+MCINV_EINVAL = -1
+MCINV_ESINGULAR = -2
+MCINV_ESTATE = -3
+MCINV_ENOMEM = -4
+MCINV_EDEVICE = -5
+MCINV_EDIVERGED = -6
+
+MCINV_R32, MCINV_R64, MCINV_C64, MCINV_C128 = 0, 1, 2, 3
+MCINV_NOISE_NORMAL, MCINV_NOISE_RADEMACHER, MCINV_NOISE_NONE = 0, 1, 2
+MCINV_MOMENTS_FP64, MCINV_MOMENTS_BF16X3 = 0, 1
+MCINV_REQ_DIAG, MCINV_REQ_TRACE, MCINV_REQ_BLOCK, MCINV_REQ_ENTRIES = 1, 2, 4, 8
+
+DTYPES = {"f32": MCINV_R32, "f64": MCINV_R64, "c64": MCINV_C64, "c128": MCINV_C128}
+NP_STATE = {MCINV_R32: np.float32, MCINV_R64: np.float64, MCINV_C64: np.complex64,
+            MCINV_C128: np.complex128}
+
+
+class McinvError(RuntimeError):
+    def __init__(self, code, message):
+        super().__init__(f"mcinv error {code}: {message}")
+        self.code = code
+
+
+class mcinv_config(ctypes.Structure):
+    _fields_ = [
+        ("device", ctypes.c_int32),
+        ("sweep_dtype", ctypes.c_int32),
+        ("moments", ctypes.c_int32),
+        ("noise", ctypes.c_int32),
+        ("n_pairs", ctypes.c_int64),
+        ("n_groups", ctypes.c_int32),
+        ("stream_id", ctypes.c_uint32),
+        ("seed", ctypes.c_uint64),
+        ("stream", ctypes.c_void_p),
+        ("profile", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class mcinv_info(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("n_pairs", ctypes.c_int64), ("ld", ctypes.c_int64),
+        ("n_colors", ctypes.c_int32), ("n_groups", ctypes.c_int32),
+        ("sweeps_done", ctypes.c_int64), ("samples_done", ctypes.c_int64),
+        ("batch_len", ctypes.c_int64), ("n_batches", ctypes.c_int64),
+        ("offdiag_entries", ctypes.c_int64),
+        ("sweep_kernel_ms", ctypes.c_double), ("sweep_kernel_launches", ctypes.c_int64),
+        ("moment_kernel_ms", ctypes.c_double), ("moment_kernel_launches", ctypes.c_int64),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int32
+_U32 = ctypes.c_uint32
+_U64 = ctypes.c_uint64
+_D = ctypes.c_double
+SIGNATURES = {
+    "mcinv_create": (_I32, [ctypes.POINTER(mcinv_config), ctypes.POINTER(_P)]),
+    "mcinv_destroy": (None, [_P]),
+    "mcinv_load_csr": (_I32, [_P, _I64, _I64, _P, _P, _P, _I32]),
+    "mcinv_set_requested": (_I32, [_P, _U32, _P, _I64, _P, _I64, _P, _P, _I64]),
+    "mcinv_burn_in": (_I32, [_P, _I64]),
+    "mcinv_sample": (_I32, [_P, _I64]),
+    "mcinv_sample_until": (_I32, [_P, _D, _I64, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_D)]),
+    "mcinv_read_estimates": (_I32, [_P, _U32, _P, _P, _I64]),
+    "mcinv_read_state": (_I32, [_P, _I32, _P, _I64]),
+    "mcinv_write_state": (_I32, [_P, _I32, _P, _I64]),
+    "mcinv_get_permutation": (_I32, [_P, _P, _P]),
+    "mcinv_check_convergence": (_I32, [_P, _I64, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+    "mcinv_get_info": (_I32, [_P, ctypes.POINTER(mcinv_info)]),
+    "mcinv_reset_profile": (_I32, [_P]),
+    "mcinv_noise_values": (_I32, [_I32, _U64, _U32, _I32, _I32, _I64, _P, _P, _P, _P]),
+    "mcinv_last_error": (ctypes.c_char_p, [_P]),
+}
+
+
+def lib():
+    """Load ``libmcinv.so``.  There is no fallback: a missing library is an error."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "(python -c 'import __graft_entry__ as g; g.build()')")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check(ctx, status):
+    if status != MCINV_OK:
+        msg = lib().mcinv_last_error(ctx)
+        raise McinvError(status, msg.decode() if msg else "")
+    return status
+
+
+def mcinv_last_error(ctx=None):
+    m = lib().mcinv_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def mcinv_create(device=0, sweep_dtype=MCINV_R32, moments=MCINV_MOMENTS_FP64, noise=MCINV_NOISE_NORMAL,
+                 n_pairs=1, n_groups=1, stream_id=0, seed=0, stream=None, profile=False):
+    cfg = mcinv_config(device, sweep_dtype, moments, noise, n_pairs, n_groups, stream_id,
+                       seed & 0xFFFFFFFFFFFFFFFF, stream, 1 if profile else 0, 0)
+    h = ctypes.c_void_p()
+    _check(None, lib().mcinv_create(ctypes.byref(cfg), ctypes.byref(h)))
+    return h
+
+
+def mcinv_destroy(ctx):
+    lib().mcinv_destroy(ctx)
+
+
+def mcinv_load_csr(ctx, n, nnz, row_ptr, col_idx, values):
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    if np.iscomplexobj(values):
+        v = np.ascontiguousarray(values, dtype=np.complex128)
+        vd = MCINV_C128
+    else:
+        v = np.ascontiguousarray(values, dtype=np.float64)
+        vd = MCINV_R64
+    _check(ctx, lib().mcinv_load_csr(ctx, int(n), int(nnz), _ptr(rp), _ptr(ci), _ptr(v), vd))
+
+
+def _idx(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.int64)
+
+
+def mcinv_set_requested(ctx, flags, block_rows=None, block_cols=None, entry_i=None, entry_j=None):
+    br, bc, ei, ej = _idx(block_rows), _idx(block_cols), _idx(entry_i), _idx(entry_j)
+    _check(ctx, lib().mcinv_set_requested(ctx, flags, _ptr(br), 0 if br is None else br.size, _ptr(bc),
+                                          0 if bc is None else bc.size, _ptr(ei), _ptr(ej),
+                                          0 if ei is None else ei.size))
+
+
+def mcinv_burn_in(ctx, sweeps):
+    _check(ctx, lib().mcinv_burn_in(ctx, int(sweeps)))
+
+
+def mcinv_sample(ctx, sweeps):
+    _check(ctx, lib().mcinv_sample(ctx, int(sweeps)))
+
+
+def mcinv_sample_until(ctx, rel_se, max_sweeps, check_every):
+    done = ctypes.c_int64(0)
+    ach = ctypes.c_double(0)
+    _check(ctx, lib().mcinv_sample_until(ctx, float(rel_se), int(max_sweeps), int(check_every),
+                                         ctypes.byref(done), ctypes.byref(ach)))
+    return done.value, ach.value
+
+
+def mcinv_read_estimates(ctx, quantity, count, is_complex):
+    est = np.empty(count * (2 if is_complex else 1), dtype=np.float64)
+    se = np.empty(count, dtype=np.float64)
+    _check(ctx, lib().mcinv_read_estimates(ctx, quantity, _ptr(est), _ptr(se), int(count)))
+    if is_complex:
+        est = est.view(np.complex128)
+    return est, se
+
+
+def mcinv_read_state(ctx, which, n, P, sweep_dtype):
+    out = np.empty((n, P), dtype=NP_STATE[sweep_dtype])
+    _check(ctx, lib().mcinv_read_state(ctx, which, _ptr(out), out.nbytes))
+    return out
+
+
+def mcinv_write_state(ctx, which, state, sweep_dtype):
+    a = np.ascontiguousarray(state, dtype=NP_STATE[sweep_dtype])
+    _check(ctx, lib().mcinv_write_state(ctx, which, _ptr(a), a.nbytes))
+
+
+def mcinv_get_permutation(ctx, n):
+    perm = np.empty(n, dtype=np.int64)
+    color = np.empty(n, dtype=np.int32)
+    _check(ctx, lib().mcinv_get_permutation(ctx, _ptr(perm), _ptr(color)))
+    return perm, color
+
+
+def mcinv_check_convergence(ctx, iters):
+    rt = ctypes.c_double(0)
+    rs = ctypes.c_double(0)
+    _check(ctx, lib().mcinv_check_convergence(ctx, int(iters), ctypes.byref(rt), ctypes.byref(rs)))
+    return rt.value, rs.value
+
+
+def mcinv_get_info(ctx):
+    info = mcinv_info()
+    _check(ctx, lib().mcinv_get_info(ctx, ctypes.byref(info)))
+    return info.as_dict()
+
+
+def mcinv_reset_profile(ctx):
+    _check(ctx, lib().mcinv_reset_profile(ctx))
+
+
+def mcinv_noise_values(device, seed, stream_id, noise, dtype, row, sweep, pair):
+    r = np.ascontiguousarray(row, dtype=np.int64).ravel()
+    k = np.ascontiguousarray(sweep, dtype=np.int64).ravel()
+    p = np.ascontiguousarray(pair, dtype=np.int64).ravel()
+    out = np.empty(r.size, dtype=np.float64)
+    _check(None, lib().mcinv_noise_values(device, seed & 0xFFFFFFFFFFFFFFFF, stream_id, noise, dtype, r.size,
+                                          _ptr(r), _ptr(k), _ptr(p), _ptr(out)))
+    return out

@@ -1,0 +1,1101 @@
+// Host runtime and C-ABI of the mcinv library (declared in include/mcinv.h).
+//
+// load_csr prepares everything the sweep kernels read:
+//   - validation (sorted columns, nonzero diagonal: Sec. 2.2 needs D regular),
+//   - the transpose of C (eq 5 walks column i of C),
+//   - one merged off-diagonal pattern per row (the union of row i and column i)
+//     holding both coefficients u = c_ij/c_ii (eq 4) and
+//     v = conj(c_ji)/conj(c_ii) (eq 5), so a neighbour is visited once,
+//   - a greedy first-fit colouring of that pattern in natural row order and the
+//     position order (colour, row): a symmetric permutation of C,
+//   - noise scales a, b with a conj(b) = 1/c_ii, computed in fp64 and rounded
+//     to the sweep precision.
+// burn_in / sample enqueue one kernel per colour per sweep on the context's
+// stream; moments are fused into the sweep (diagonal, trace) or follow it
+// (block, entries, per-sweep trace reduction).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mcinv.h"
+#include "device_common.h"
+#include "sweep.h"
+
+using namespace mcinv;
+using cd = std::complex<double>;
+
+namespace {
+
+thread_local std::string g_error;
+
+constexpr int64_t kSlotsSmallG = 64;     // time batches when there are < 16 groups
+constexpr double kGuardThreshold = 1e30;
+
+}  // namespace
+
+struct mcinv_ctx {
+    mcinv_config cfg{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool cplx = false;
+    size_t elem = 0;
+    int comps = 1;
+
+    int64_t P = 0, ld = 0, G = 1, gs = 1, lg_shift = 6, A = 1, ntiles = 1, pairs_per_col = 256;
+
+    // matrix
+    bool loaded = false;
+    bool real_values = true;
+    int64_t n = 0, nnz = 0, n_off = 0;
+    int32_t ncolors = 0;
+    std::vector<int64_t> perm, pos, color_ptr, tpart_off;
+    std::vector<int32_t> color;
+    int64_t npart = 0;
+
+    // device: matrix and state
+    RowRec* d_rows = nullptr;
+    void* d_ent = nullptr;
+    void* d_sc = nullptr;
+    void* d_z = nullptr;
+    void* d_w = nullptr;
+    int64_t* d_perm = nullptr;
+    int32_t* d_flag = nullptr;
+
+    // requests
+    uint32_t flags = 0;
+    bool requested = false;
+    int64_t nI = 0, nJ = 0, ne = 0;
+    int64_t* d_I = nullptr;
+    int64_t* d_J = nullptr;
+    int64_t* d_ei = nullptr;
+    int64_t* d_ej = nullptr;
+
+    // accumulators
+    int64_t nslots = 1, batch_len = 1, samples = 0, sweeps = 0;
+    std::vector<double> slot_len;
+    double* d_slot_len = nullptr;
+    double* d_diag = nullptr;
+    double* d_block = nullptr;
+    double* d_entries = nullptr;
+    double* d_tpart = nullptr;
+    double* d_partial = nullptr;
+    uint32_t* d_counter = nullptr;
+    double* d_series = nullptr;
+    int64_t series_cap = 0;
+    double* d_est = nullptr;
+    double* d_se = nullptr;
+    int64_t est_cap = 0;
+    unsigned long long* d_maxrel = nullptr;
+    double* d_geyer = nullptr;
+
+    // profiling
+    std::vector<hipEvent_t> events;
+    double sweep_ms = 0.0, moment_ms = 0.0;
+    int64_t sweep_launches = 0, moment_launches = 0;
+
+    std::string err;
+
+    int64_t diag_slot_stride() const { return n * A * comps; }
+    int64_t block_slot_stride() const { return G * nI * nJ * comps; }
+    int64_t entry_slot_stride() const { return G * ne * comps; }
+};
+
+namespace {
+
+mcinv_status fail(mcinv_ctx* c, mcinv_status code, const std::string& msg)
+{
+    if (c)
+        c->err = msg;
+    else
+        g_error = msg;
+    return code;
+}
+
+#define HIP_TRY(c, expr)                                                                        \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return fail((c), e_ == hipErrorOutOfMemory ? MCINV_ENOMEM : MCINV_EDEVICE,          \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));                     \
+    } while (0)
+
+#define MC_TRY(expr)                    \
+    do {                                \
+        mcinv_status s_ = (expr);       \
+        if (s_ != MCINV_OK) return s_;  \
+    } while (0)
+
+template <typename T>
+void dfree(T*& p)
+{
+    if (p) (void)hipFree((void*)p);
+    p = nullptr;
+}
+
+void free_requests(mcinv_ctx* c)
+{
+    dfree(c->d_I);
+    dfree(c->d_J);
+    dfree(c->d_ei);
+    dfree(c->d_ej);
+    dfree(c->d_diag);
+    dfree(c->d_block);
+    dfree(c->d_entries);
+    dfree(c->d_tpart);
+    dfree(c->d_series);
+    dfree(c->d_slot_len);
+    c->series_cap = 0;
+    c->requested = false;
+    c->flags = 0;
+    c->nI = c->nJ = c->ne = 0;
+}
+
+void free_matrix(mcinv_ctx* c)
+{
+    free_requests(c);
+    dfree(c->d_rows);
+    dfree(c->d_ent);
+    dfree(c->d_sc);
+    dfree(c->d_z);
+    dfree(c->d_w);
+    dfree(c->d_perm);
+    dfree(c->d_est);
+    dfree(c->d_se);
+    c->est_cap = 0;
+    c->loaded = false;
+}
+
+mcinv_status set_device(mcinv_ctx* c)
+{
+    HIP_TRY(c, hipSetDevice(c->cfg.device));
+    return MCINV_OK;
+}
+
+template <typename T>
+mcinv_status dalloc(mcinv_ctx* c, T** p, size_t count)
+{
+    *p = nullptr;
+    if (count == 0) count = 1;
+    HIP_TRY(c, hipMalloc((void**)p, count * sizeof(T)));
+    return MCINV_OK;
+}
+
+template <typename T>
+mcinv_status upload(mcinv_ctx* c, T** p, const std::vector<T>& h)
+{
+    MC_TRY(dalloc(c, p, h.size()));
+    if (!h.empty()) HIP_TRY(c, hipMemcpyAsync(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    return MCINV_OK;
+}
+
+// ---------------------------------------------------- precision dispatch --
+template <typename V> V cast_val(cd x);
+template <> float cast_val<float>(cd x) { return (float)x.real(); }
+template <> double cast_val<double>(cd x) { return x.real(); }
+template <> Cx<float> cast_val<Cx<float>>(cd x) { return Cx<float>{(float)x.real(), (float)x.imag()}; }
+template <> Cx<double> cast_val<Cx<double>>(cd x) { return Cx<double>{x.real(), x.imag()}; }
+
+struct MergedEntry {
+    int64_t col;   // position of neighbour
+    cd u, v;
+};
+
+// Host layout of the merged pattern in position order.
+struct Prepared {
+    std::vector<RowRec> rows;
+    std::vector<MergedEntry> ent;
+    std::vector<cd> a, b;
+};
+
+template <typename V>
+mcinv_status upload_matrix(mcinv_ctx* c, const Prepared& h)
+{
+    std::vector<Entry<V>> ent(h.ent.size());
+    for (size_t e = 0; e < ent.size(); ++e) {
+        ent[e].col = (int32_t)h.ent[e].col;
+        ent[e].pad = 0;
+        ent[e].u = cast_val<V>(h.ent[e].u);
+        ent[e].v = cast_val<V>(h.ent[e].v);
+    }
+    std::vector<Scales<V>> sc(h.a.size());
+    for (size_t q = 0; q < sc.size(); ++q) {
+        sc[q].a = cast_val<V>(h.a[q]);
+        sc[q].b = cast_val<V>(h.b[q]);
+    }
+    Entry<V>* d_ent = nullptr;
+    Scales<V>* d_sc = nullptr;
+    MC_TRY(upload(c, &c->d_rows, h.rows));
+    MC_TRY(upload(c, &d_ent, ent));
+    c->d_ent = d_ent;
+    MC_TRY(upload(c, &d_sc, sc));
+    c->d_sc = d_sc;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return MCINV_OK;
+}
+
+// ------------------------------------------------------------ the sweeps --
+mcinv_status grow_series(mcinv_ctx* c, int64_t need)
+{
+    if (need <= c->series_cap) return MCINV_OK;
+    int64_t cap = std::max<int64_t>(4096, c->series_cap);
+    while (cap < need) cap *= 2;
+    double* nb = nullptr;
+    MC_TRY(dalloc(c, &nb, (size_t)(cap * c->comps)));
+    if (c->d_series && c->samples > 0)
+        HIP_TRY(c, hipMemcpyAsync(nb, c->d_series, sizeof(double) * c->samples * c->comps, hipMemcpyDeviceToDevice,
+                                  c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    dfree(c->d_series);
+    c->d_series = nb;
+    c->series_cap = cap;
+    return MCINV_OK;
+}
+
+hipEvent_t take_event(mcinv_ctx* c, size_t& next)
+{
+    if (next >= c->events.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        c->events.push_back(e);
+    }
+    return c->events[next++];
+}
+
+// Merge the time-batch clusters pairwise when all slots are full.
+mcinv_status advance_slot(mcinv_ctx* c, int64_t* slot)
+{
+    int64_t b = c->samples / c->batch_len;
+    if (c->nslots > 1 && b >= c->nslots) {
+        const int64_t half = c->nslots / 2;
+        if (c->d_diag) HIP_TRY(c, launch_merge_slots(c->d_diag, c->diag_slot_stride(), half, c->stream));
+        if (c->d_block) HIP_TRY(c, launch_merge_slots(c->d_block, c->block_slot_stride(), half, c->stream));
+        if (c->d_entries) HIP_TRY(c, launch_merge_slots(c->d_entries, c->entry_slot_stride(), half, c->stream));
+        for (int64_t m = 0; m < half; ++m) c->slot_len[m] = c->slot_len[2 * m] + c->slot_len[2 * m + 1];
+        for (int64_t m = half; m < c->nslots; ++m) c->slot_len[m] = 0.0;
+        c->batch_len *= 2;
+        b = c->samples / c->batch_len;
+    }
+    if (c->nslots == 1) b = 0;
+    *slot = b;
+    return MCINV_OK;
+}
+
+template <typename V>
+mcinv_status run_sweeps(mcinv_ctx* c, int64_t nsw, bool sample, V* z, V* w, int64_t ld, int64_t P,
+                        int32_t noise, int32_t* flag, bool use_counters)
+{
+    SweepArgs<V> a{};
+    a.rows = c->d_rows;
+    a.ent = (const Entry<V>*)c->d_ent;
+    a.sc = (const Scales<V>*)c->d_sc;
+    a.z = z;
+    a.w = w;
+    a.ld = ld;
+    a.P = P;
+    a.key0 = (uint32_t)(c->cfg.seed & 0xffffffffu);
+    a.key1 = (uint32_t)(c->cfg.seed >> 32);
+    a.stream = c->cfg.stream_id;
+    a.noise = noise;
+    a.lg_shift = (int32_t)c->lg_shift;
+    a.A = c->A;
+    a.flag = flag;
+    a.thresh = (typename Real<V>::type)kGuardThreshold;
+
+    const bool prof = c->cfg.profile != 0 && use_counters;
+    size_t next_ev = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> sweep_ev, mom_ev;
+
+    for (int64_t s = 0; s < nsw; ++s) {
+        const int64_t k = use_counters ? c->sweeps + s : s;
+        int64_t slot = 0;
+        if (sample) MC_TRY(advance_slot(c, &slot));
+        a.sweep = (uint32_t)k;
+        const bool want_diag = sample && (c->flags & MCINV_REQ_DIAG);
+        const bool want_trace = sample && (c->flags & MCINV_REQ_TRACE);
+        a.diag = want_diag ? c->d_diag + slot * c->diag_slot_stride() : nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (prof) {
+            e0 = take_event(c, next_ev);
+            e1 = take_event(c, next_ev);
+            if (e0) HIP_TRY(c, hipEventRecord(e0, c->stream));
+        }
+        for (int32_t col = 0; col < c->ncolors; ++col) {
+            a.row_begin = c->color_ptr[col];
+            a.row_end = c->color_ptr[col + 1];
+            a.tpart = want_trace ? c->d_tpart + c->tpart_off[col] * c->comps : nullptr;
+            HIP_TRY(c, launch_sweep<V>(a, sample, c->stream));
+        }
+        if (prof && e1) {
+            HIP_TRY(c, hipEventRecord(e1, c->stream));
+            sweep_ev.emplace_back(e0, e1);
+        }
+        if (!sample) continue;
+
+        if (want_trace) {
+            MC_TRY(grow_series(c, c->samples + 1));
+            HIP_TRY(c, launch_reduce_sum(c->d_tpart, c->npart, c->comps, c->d_partial, c->d_counter,
+                                         c->d_series + c->samples * c->comps, c->stream));
+        }
+        hipEvent_t m0 = nullptr, m1 = nullptr;
+        const bool any_moment = (c->flags & MCINV_REQ_BLOCK) || (c->flags & MCINV_REQ_ENTRIES);
+        if (prof && any_moment) {
+            m0 = take_event(c, next_ev);
+            m1 = take_event(c, next_ev);
+            if (m0) HIP_TRY(c, hipEventRecord(m0, c->stream));
+        }
+        if ((c->flags & MCINV_REQ_BLOCK) && c->nI > 0 && c->nJ > 0) {
+            BlockArgs<V> ba{};
+            ba.z = z;
+            ba.w = w;
+            ba.ld = ld;
+            ba.I = c->d_I;
+            ba.J = c->d_J;
+            ba.nI = c->nI;
+            ba.nJ = c->nJ;
+            ba.gs = c->gs;
+            ba.G = c->G;
+            ba.acc = c->d_block + slot * c->block_slot_stride();
+            if constexpr (std::is_same<V, float>::value) {
+                if (c->cfg.moments == MCINV_MOMENTS_BF16X3)
+                    HIP_TRY(c, launch_block_bf16x3(ba, c->stream));
+                else
+                    HIP_TRY(c, launch_block_fp64<V>(ba, c->stream));
+            } else {
+                HIP_TRY(c, launch_block_fp64<V>(ba, c->stream));
+            }
+        }
+        if ((c->flags & MCINV_REQ_ENTRIES) && c->ne > 0)
+            HIP_TRY(c, launch_entries<V>(z, w, ld, c->d_ei, c->d_ej, c->ne, c->gs, c->G,
+                                         c->d_entries + slot * c->entry_slot_stride(), c->stream));
+        if (prof && m1) {
+            HIP_TRY(c, hipEventRecord(m1, c->stream));
+            mom_ev.emplace_back(m0, m1);
+        }
+        c->slot_len[slot] += 1.0;
+        c->samples += 1;
+    }
+    if (prof) {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        for (auto& pr : sweep_ev) {
+            float ms = 0.f;
+            HIP_TRY(c, hipEventElapsedTime(&ms, pr.first, pr.second));
+            c->sweep_ms += ms;
+            c->sweep_launches += c->ncolors;
+        }
+        for (auto& pr : mom_ev) {
+            float ms = 0.f;
+            HIP_TRY(c, hipEventElapsedTime(&ms, pr.first, pr.second));
+            c->moment_ms += ms;
+            c->moment_launches += 1;
+        }
+    }
+    return MCINV_OK;
+}
+
+mcinv_status dispatch_sweeps(mcinv_ctx* c, int64_t nsw, bool sample)
+{
+    switch (c->cfg.sweep_dtype) {
+    case MCINV_R32:
+        return run_sweeps<float>(c, nsw, sample, (float*)c->d_z, (float*)c->d_w, c->ld, c->P, c->cfg.noise,
+                                 c->d_flag, true);
+    case MCINV_R64:
+        return run_sweeps<double>(c, nsw, sample, (double*)c->d_z, (double*)c->d_w, c->ld, c->P, c->cfg.noise,
+                                  c->d_flag, true);
+    case MCINV_C64:
+        return run_sweeps<Cx<float>>(c, nsw, sample, (Cx<float>*)c->d_z, (Cx<float>*)c->d_w, c->ld, c->P,
+                                     c->cfg.noise, c->d_flag, true);
+    default:
+        return run_sweeps<Cx<double>>(c, nsw, sample, (Cx<double>*)c->d_z, (Cx<double>*)c->d_w, c->ld, c->P,
+                                      c->cfg.noise, c->d_flag, true);
+    }
+}
+
+mcinv_status check_flag(mcinv_ctx* c)
+{
+    int32_t flag = 0;
+    HIP_TRY(c, hipMemcpyAsync(&flag, c->d_flag, sizeof(flag), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (flag) return fail(c, MCINV_EDIVERGED, "chain state became non-finite or exceeded 1e30 (sp(T) or sp(S) >= 1?)");
+    return MCINV_OK;
+}
+
+mcinv_status ensure_est(mcinv_ctx* c, int64_t values)
+{
+    if (values <= c->est_cap) return MCINV_OK;
+    dfree(c->d_est);
+    dfree(c->d_se);
+    MC_TRY(dalloc(c, &c->d_est, (size_t)(values * 2)));
+    MC_TRY(dalloc(c, &c->d_se, (size_t)values));
+    c->est_cap = values;
+    return MCINV_OK;
+}
+
+mcinv_status finalize_diag(mcinv_ctx* c, bool want_max)
+{
+    MC_TRY(ensure_est(c, c->n));
+    HIP_TRY(c, hipMemcpyAsync(c->d_slot_len, c->slot_len.data(), sizeof(double) * c->nslots,
+                              hipMemcpyHostToDevice, c->stream));
+    if (want_max) HIP_TRY(c, hipMemsetAsync(c->d_maxrel, 0, sizeof(unsigned long long), c->stream));
+    FinalizeArgs f{};
+    f.acc = c->d_diag;
+    f.nslots = c->nslots;
+    f.slot_stride = c->diag_slot_stride();
+    f.slot_len = c->d_slot_len;
+    f.G = c->G;
+    f.gs = c->gs;
+    f.M = c->n;
+    f.A = c->A;
+    f.pairs_per_col = c->pairs_per_col;
+    f.comps = c->comps;
+    f.out_index = c->d_perm;
+    f.est = c->d_est;
+    f.se = c->d_se;
+    f.max_rel = want_max ? c->d_maxrel : nullptr;
+    HIP_TRY(c, launch_finalize_diag(f, c->stream));
+    return MCINV_OK;
+}
+
+mcinv_status finalize_flat(mcinv_ctx* c, const double* acc, int64_t M, int64_t stride)
+{
+    MC_TRY(ensure_est(c, M));
+    HIP_TRY(c, hipMemcpyAsync(c->d_slot_len, c->slot_len.data(), sizeof(double) * c->nslots,
+                              hipMemcpyHostToDevice, c->stream));
+    FinalizeArgs f{};
+    f.acc = acc;
+    f.nslots = c->nslots;
+    f.slot_stride = stride;
+    f.slot_len = c->d_slot_len;
+    f.G = c->G;
+    f.gs = c->gs;
+    f.M = M;
+    f.comps = c->comps;
+    f.est = c->d_est;
+    f.se = c->d_se;
+    HIP_TRY(c, launch_finalize_flat(f, c->stream));
+    return MCINV_OK;
+}
+
+size_t elem_size(int32_t dt)
+{
+    switch (dt) {
+    case MCINV_R32: return 4;
+    case MCINV_R64: return 8;
+    case MCINV_C64: return 8;
+    case MCINV_C128: return 16;
+    default: return 0;
+    }
+}
+
+mcinv_status check_ready(mcinv_ctx* c)
+{
+    if (!c) return fail(nullptr, MCINV_EINVAL, "null context");
+    if (!c->loaded) return fail(c, MCINV_ESTATE, "no matrix loaded (call mcinv_load_csr first)");
+    return set_device(c);
+}
+
+}  // namespace
+
+// =========================================================================
+extern "C" {
+
+mcinv_status mcinv_create(const mcinv_config* cfg, mcinv_ctx** out)
+{
+    if (!cfg || !out) return fail(nullptr, MCINV_EINVAL, "null argument");
+    *out = nullptr;
+    if (elem_size(cfg->sweep_dtype) == 0) return fail(nullptr, MCINV_EINVAL, "unknown sweep dtype");
+    if (cfg->noise < 0 || cfg->noise > 2) return fail(nullptr, MCINV_EINVAL, "unknown noise kind");
+    if (cfg->moments != MCINV_MOMENTS_FP64 && cfg->moments != MCINV_MOMENTS_BF16X3)
+        return fail(nullptr, MCINV_EINVAL, "unknown moments mode");
+    if (cfg->moments == MCINV_MOMENTS_BF16X3 && cfg->sweep_dtype != MCINV_R32)
+        return fail(nullptr, MCINV_EINVAL, "bf16x3 block moments need a real fp32 sweep");
+    if (cfg->n_pairs < 1 || cfg->n_pairs > (int64_t)1 << 30) return fail(nullptr, MCINV_EINVAL, "n_pairs out of range");
+    const int64_t P = cfg->n_pairs, G = cfg->n_groups;
+    if (G < 1 || P % G != 0) return fail(nullptr, MCINV_EINVAL, "n_groups must divide n_pairs");
+    const int64_t gs = P / G;
+    if (G > 1) {
+        const bool pow2 = (gs & (gs - 1)) == 0;
+        if (gs % 4 != 0 || (gs <= 256 && !pow2) || (gs > 256 && gs % 256 != 0))
+            return fail(nullptr, MCINV_EINVAL,
+                        "pairs per group must be a power of two in [4, 256] or a multiple of 256");
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev)
+        return fail(nullptr, MCINV_EDEVICE, "no such HIP device");
+
+    mcinv_ctx* c = new mcinv_ctx();
+    c->cfg = *cfg;
+    c->cplx = cfg->sweep_dtype == MCINV_C64 || cfg->sweep_dtype == MCINV_C128;
+    c->comps = c->cplx ? 2 : 1;
+    c->elem = elem_size(cfg->sweep_dtype);
+    c->P = P;
+    c->ld = (P + 3) / 4 * 4;
+    c->G = G;
+    c->gs = gs;
+    const int64_t lanes = G == 1 ? kWave : std::min<int64_t>(gs / 4, kWave);
+    int64_t sh = 0;
+    while ((int64_t)1 << sh < lanes) ++sh;
+    c->lg_shift = sh;
+    c->pairs_per_col = lanes * kPairsPerLane;
+    c->A = (c->ld + c->pairs_per_col - 1) / c->pairs_per_col;
+    c->ntiles = (c->ld + kPairsPerWave - 1) / kPairsPerWave;
+    c->nslots = G >= 16 ? 1 : kSlotsSmallG;
+    c->slot_len.assign(c->nslots, 0.0);
+
+    auto bail = [&](mcinv_status s) {
+        g_error = c->err;
+        mcinv_destroy(c);
+        return s;
+    };
+    mcinv_status s = set_device(c);
+    if (s != MCINV_OK) return bail(s);
+    if (cfg->stream) {
+        c->stream = (hipStream_t)cfg->stream;
+    } else {
+        if (hipStreamCreate(&c->stream) != hipSuccess) return bail(fail(c, MCINV_EDEVICE, "hipStreamCreate failed"));
+        c->own_stream = true;
+    }
+    if ((s = dalloc(c, &c->d_flag, 1)) != MCINV_OK) return bail(s);
+    if ((s = dalloc(c, &c->d_partial, 2 * 128)) != MCINV_OK) return bail(s);
+    if ((s = dalloc(c, &c->d_counter, 1)) != MCINV_OK) return bail(s);
+    if ((s = dalloc(c, &c->d_maxrel, 1)) != MCINV_OK) return bail(s);
+    if ((s = dalloc(c, &c->d_geyer, 8)) != MCINV_OK) return bail(s);
+    if ((s = dalloc(c, &c->d_slot_len, (size_t)c->nslots)) != MCINV_OK) return bail(s);
+    if (hipMemsetAsync(c->d_flag, 0, sizeof(int32_t), c->stream) != hipSuccess ||
+        hipMemsetAsync(c->d_counter, 0, sizeof(uint32_t), c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return bail(fail(c, MCINV_EDEVICE, "initial memset failed"));
+    *out = c;
+    return MCINV_OK;
+}
+
+void mcinv_destroy(mcinv_ctx* c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->cfg.device);
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    free_matrix(c);
+    dfree(c->d_flag);
+    dfree(c->d_partial);
+    dfree(c->d_counter);
+    dfree(c->d_maxrel);
+    dfree(c->d_geyer);
+    dfree(c->d_slot_len);
+    for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+mcinv_status mcinv_load_csr(mcinv_ctx* c, int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
+                            const void* values, int32_t value_dtype)
+{
+    if (!c) return fail(nullptr, MCINV_EINVAL, "null context");
+    MC_TRY(set_device(c));
+    if (n < 1 || n > INT32_MAX || nnz < n || !row_ptr || !col_idx || !values)
+        return fail(c, MCINV_EINVAL, "bad sizes or null arrays");
+    if (value_dtype != MCINV_R64 && value_dtype != MCINV_C128)
+        return fail(c, MCINV_EINVAL, "values must be float64 (MCINV_R64) or complex128 (MCINV_C128)");
+    if (value_dtype == MCINV_C128 && !c->cplx)
+        return fail(c, MCINV_EINVAL, "a complex matrix needs a complex sweep dtype");
+    if (row_ptr[0] != 0 || row_ptr[n] != nnz) return fail(c, MCINV_EINVAL, "row_ptr[0] must be 0 and row_ptr[n] nnz");
+    for (int64_t i = 0; i < n; ++i) {
+        if (row_ptr[i + 1] < row_ptr[i]) return fail(c, MCINV_EINVAL, "row_ptr is decreasing");
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            if (col_idx[e] < 0 || col_idx[e] >= n) return fail(c, MCINV_EINVAL, "column index out of range");
+            if (e > row_ptr[i] && col_idx[e] <= col_idx[e - 1])
+                return fail(c, MCINV_EINVAL, "columns must be strictly increasing within a row");
+        }
+    }
+    const double* vd = (const double*)values;
+    auto val = [&](int64_t e) { return value_dtype == MCINV_C128 ? cd(vd[2 * e], vd[2 * e + 1]) : cd(vd[e], 0.0); };
+
+    // Diagonal and per-row constants (fp64).
+    std::vector<cd> diag(n);
+    for (int64_t i = 0; i < n; ++i) {
+        bool found = false;
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
+            if (col_idx[e] == i) {
+                diag[i] = val(e);
+                found = true;
+            }
+        if (!found || diag[i] == cd(0.0, 0.0))
+            return fail(c, MCINV_ESINGULAR, "row " + std::to_string(i) + " has no nonzero diagonal entry");
+    }
+
+    // Transpose: column i lists (row j, c_ji), rows ascending.
+    std::vector<int64_t> tptr(n + 1, 0);
+    for (int64_t e = 0; e < nnz; ++e) tptr[col_idx[e] + 1]++;
+    for (int64_t i = 0; i < n; ++i) tptr[i + 1] += tptr[i];
+    std::vector<int64_t> trow(nnz), tsrc(nnz);
+    {
+        std::vector<int64_t> fill(tptr.begin(), tptr.end() - 1);
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+                const int64_t slot = fill[col_idx[e]]++;
+                trow[slot] = i;
+                tsrc[slot] = e;
+            }
+    }
+
+    // Merged off-diagonal pattern per original row: union of row i and column i.
+    std::vector<int64_t> mptr(n + 1, 0);
+    std::vector<int64_t> mcol;
+    std::vector<cd> mu, mv;
+    mcol.reserve(2 * nnz);
+    mu.reserve(2 * nnz);
+    mv.reserve(2 * nnz);
+    for (int64_t i = 0; i < n; ++i) {
+        const cd inv = 1.0 / diag[i];
+        int64_t e = row_ptr[i], t = tptr[i];
+        const int64_t e_end = row_ptr[i + 1], t_end = tptr[i + 1];
+        while (e < e_end || t < t_end) {
+            const int64_t je = e < e_end ? col_idx[e] : INT64_MAX;
+            const int64_t jt = t < t_end ? trow[t] : INT64_MAX;
+            const int64_t j = std::min(je, jt);
+            cd u(0.0, 0.0), v(0.0, 0.0);
+            if (je == j) u = inv * val(e++);
+            if (jt == j) v = std::conj(inv) * std::conj(val(tsrc[t++]));
+            if (j == i) continue;
+            mcol.push_back(j);
+            mu.push_back(u);
+            mv.push_back(v);
+        }
+        mptr[i + 1] = (int64_t)mcol.size();
+    }
+
+    // Greedy first-fit colouring in natural order over the merged pattern.
+    std::vector<int32_t> color(n, 0);
+    std::vector<int64_t> mark(n + 1, -1);
+    int32_t ncolors = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t e = mptr[i]; e < mptr[i + 1]; ++e)
+            if (mcol[e] < i) mark[color[mcol[e]]] = i;
+        int32_t k = 0;
+        while (mark[k] == i) ++k;
+        color[i] = k;
+        ncolors = std::max(ncolors, k + 1);
+    }
+    std::vector<int64_t> color_ptr(ncolors + 1, 0);
+    for (int64_t i = 0; i < n; ++i) color_ptr[color[i] + 1]++;
+    for (int32_t k = 0; k < ncolors; ++k) color_ptr[k + 1] += color_ptr[k];
+    std::vector<int64_t> perm(n), pos(n);
+    {
+        std::vector<int64_t> fill(color_ptr.begin(), color_ptr.end() - 1);
+        for (int64_t i = 0; i < n; ++i) {
+            const int64_t q = fill[color[i]]++;
+            perm[q] = i;
+            pos[i] = q;
+        }
+    }
+
+    // Position-space layout.
+    Prepared h;
+    h.rows.resize(n);
+    h.a.resize(n);
+    h.b.resize(n);
+    h.ent.reserve(mcol.size());
+    const bool real_values = value_dtype == MCINV_R64;
+    for (int64_t q = 0; q < n; ++q) {
+        const int64_t i = perm[q];
+        h.rows[q].begin = (int64_t)h.ent.size();
+        h.rows[q].count = (int32_t)(mptr[i + 1] - mptr[i]);
+        h.rows[q].orig = (uint32_t)i;
+        const size_t first = h.ent.size();
+        for (int64_t e = mptr[i]; e < mptr[i + 1]; ++e) h.ent.push_back(MergedEntry{pos[mcol[e]], mu[e], mv[e]});
+        std::sort(h.ent.begin() + first, h.ent.end(),
+                  [](const MergedEntry& x, const MergedEntry& y) { return x.col < y.col; });
+        const cd d = diag[i];
+        if (real_values) {
+            const double s = 1.0 / std::sqrt(std::fabs(d.real()));
+            h.a[q] = cd(s, 0.0);
+            h.b[q] = cd(d.real() > 0 ? s : -s, 0.0);
+        } else {
+            h.a[q] = 1.0 / std::sqrt(d);
+            h.b[q] = std::conj(h.a[q]);
+        }
+    }
+
+    free_matrix(c);
+    c->n = n;
+    c->nnz = nnz;
+    c->n_off = (int64_t)h.ent.size();
+    c->ncolors = ncolors;
+    c->perm = perm;
+    c->pos = pos;
+    c->color = color;
+    c->color_ptr = color_ptr;
+    c->real_values = real_values;
+    c->tpart_off.assign(ncolors + 1, 0);
+    for (int32_t k = 0; k < ncolors; ++k) {
+        const int64_t rows = color_ptr[k + 1] - color_ptr[k];
+        c->tpart_off[k + 1] = c->tpart_off[k] + (rows + 3) / 4 * c->ntiles;
+    }
+    c->npart = c->tpart_off[ncolors];
+
+    mcinv_status s;
+    switch (c->cfg.sweep_dtype) {
+    case MCINV_R32: s = upload_matrix<float>(c, h); break;
+    case MCINV_R64: s = upload_matrix<double>(c, h); break;
+    case MCINV_C64: s = upload_matrix<Cx<float>>(c, h); break;
+    default: s = upload_matrix<Cx<double>>(c, h); break;
+    }
+    if (s != MCINV_OK) return s;
+    MC_TRY(upload(c, &c->d_perm, perm));
+    const size_t state_bytes = (size_t)n * c->ld * c->elem;
+    HIP_TRY(c, hipMalloc(&c->d_z, state_bytes));
+    HIP_TRY(c, hipMalloc(&c->d_w, state_bytes));
+    HIP_TRY(c, hipMemsetAsync(c->d_z, 0, state_bytes, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->d_w, 0, state_bytes, c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->d_flag, 0, sizeof(int32_t), c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->sweeps = 0;
+    c->samples = 0;
+    c->batch_len = 1;
+    c->slot_len.assign(c->nslots, 0.0);
+    c->loaded = true;
+    return MCINV_OK;
+}
+
+mcinv_status mcinv_set_requested(mcinv_ctx* c, uint32_t flags, const int64_t* block_rows, int64_t n_block_rows,
+                                 const int64_t* block_cols, int64_t n_block_cols, const int64_t* entry_i,
+                                 const int64_t* entry_j, int64_t n_entries)
+{
+    MC_TRY(check_ready(c));
+    if (flags & ~(MCINV_REQ_DIAG | MCINV_REQ_TRACE | MCINV_REQ_BLOCK | MCINV_REQ_ENTRIES))
+        return fail(c, MCINV_EINVAL, "unknown request flag");
+    const bool want_block = (flags & MCINV_REQ_BLOCK) && n_block_rows > 0 && n_block_cols > 0;
+    const bool want_entries = (flags & MCINV_REQ_ENTRIES) && n_entries > 0;
+    if (want_block && (!block_rows || !block_cols)) return fail(c, MCINV_EINVAL, "null block index arrays");
+    if (want_entries && (!entry_i || !entry_j)) return fail(c, MCINV_EINVAL, "null entry arrays");
+    auto to_pos = [&](const int64_t* idx, int64_t m, std::vector<int64_t>& out) -> bool {
+        out.resize(m);
+        for (int64_t k = 0; k < m; ++k) {
+            if (idx[k] < 0 || idx[k] >= c->n) return false;
+            out[k] = c->pos[idx[k]];
+        }
+        return true;
+    };
+    std::vector<int64_t> I, J, ei, ej;
+    if (want_block && (!to_pos(block_rows, n_block_rows, I) || !to_pos(block_cols, n_block_cols, J)))
+        return fail(c, MCINV_EINVAL, "block index out of range");
+    if (want_entries && (!to_pos(entry_i, n_entries, ei) || !to_pos(entry_j, n_entries, ej)))
+        return fail(c, MCINV_EINVAL, "entry index out of range");
+
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    free_requests(c);
+    c->flags = flags;
+    c->nI = want_block ? n_block_rows : 0;
+    c->nJ = want_block ? n_block_cols : 0;
+    c->ne = want_entries ? n_entries : 0;
+    if (!want_block) c->flags &= ~MCINV_REQ_BLOCK;
+    if (!want_entries) c->flags &= ~MCINV_REQ_ENTRIES;
+    MC_TRY(dalloc(c, &c->d_slot_len, (size_t)c->nslots));
+    if (c->flags & MCINV_REQ_DIAG) {
+        const size_t cnt = (size_t)(c->nslots * c->diag_slot_stride());
+        MC_TRY(dalloc(c, &c->d_diag, cnt));
+        HIP_TRY(c, hipMemsetAsync(c->d_diag, 0, cnt * sizeof(double), c->stream));
+    }
+    if (c->flags & MCINV_REQ_TRACE) {
+        MC_TRY(dalloc(c, &c->d_tpart, (size_t)(c->npart * c->comps)));
+        MC_TRY(grow_series(c, 4096));
+    }
+    if (c->flags & MCINV_REQ_BLOCK) {
+        MC_TRY(upload(c, &c->d_I, I));
+        MC_TRY(upload(c, &c->d_J, J));
+        const size_t cnt = (size_t)(c->nslots * c->block_slot_stride());
+        MC_TRY(dalloc(c, &c->d_block, cnt));
+        HIP_TRY(c, hipMemsetAsync(c->d_block, 0, cnt * sizeof(double), c->stream));
+    }
+    if (c->flags & MCINV_REQ_ENTRIES) {
+        MC_TRY(upload(c, &c->d_ei, ei));
+        MC_TRY(upload(c, &c->d_ej, ej));
+        const size_t cnt = (size_t)(c->nslots * c->entry_slot_stride());
+        MC_TRY(dalloc(c, &c->d_entries, cnt));
+        HIP_TRY(c, hipMemsetAsync(c->d_entries, 0, cnt * sizeof(double), c->stream));
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->samples = 0;
+    c->batch_len = 1;
+    c->slot_len.assign(c->nslots, 0.0);
+    c->requested = true;
+    return MCINV_OK;
+}
+
+mcinv_status mcinv_burn_in(mcinv_ctx* c, int64_t sweeps)
+{
+    MC_TRY(check_ready(c));
+    if (sweeps < 0) return fail(c, MCINV_EINVAL, "negative sweep count");
+    MC_TRY(dispatch_sweeps(c, sweeps, false));
+    c->sweeps += sweeps;
+    return check_flag(c);
+}
+
+mcinv_status mcinv_sample(mcinv_ctx* c, int64_t sweeps)
+{
+    MC_TRY(check_ready(c));
+    if (!c->requested) return fail(c, MCINV_ESTATE, "call mcinv_set_requested before sampling");
+    if (sweeps < 0) return fail(c, MCINV_EINVAL, "negative sweep count");
+    MC_TRY(dispatch_sweeps(c, sweeps, true));
+    c->sweeps += sweeps;
+    return check_flag(c);
+}
+
+mcinv_status mcinv_sample_until(mcinv_ctx* c, double rel_se, int64_t max_sweeps, int64_t check_every,
+                                int64_t* sweeps_done, double* achieved)
+{
+    MC_TRY(check_ready(c));
+    if (!c->requested || !(c->flags & MCINV_REQ_DIAG))
+        return fail(c, MCINV_ESTATE, "sample_until needs MCINV_REQ_DIAG requested");
+    if (check_every < 1 || max_sweeps < 0) return fail(c, MCINV_EINVAL, "bad sweep counts");
+    int64_t done = 0;
+    double maxrel = INFINITY;
+    while (done < max_sweeps) {
+        const int64_t chunk = std::min(check_every, max_sweeps - done);
+        MC_TRY(dispatch_sweeps(c, chunk, true));
+        c->sweeps += chunk;
+        done += chunk;
+        MC_TRY(finalize_diag(c, true));
+        unsigned long long bits = 0;
+        HIP_TRY(c, hipMemcpyAsync(&bits, c->d_maxrel, sizeof(bits), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        std::memcpy(&maxrel, &bits, sizeof(double));
+        MC_TRY(check_flag(c));
+        if (maxrel <= rel_se) break;
+    }
+    if (sweeps_done) *sweeps_done = done;
+    if (achieved) *achieved = maxrel;
+    return MCINV_OK;
+}
+
+mcinv_status mcinv_read_estimates(mcinv_ctx* c, uint32_t quantity, double* est, double* stderr_, int64_t capacity)
+{
+    MC_TRY(check_ready(c));
+    if (!c->requested || !(c->flags & quantity)) return fail(c, MCINV_ESTATE, "quantity was not requested");
+    int64_t M = 0;
+    if (quantity == MCINV_REQ_DIAG) {
+        M = c->n;
+        if (capacity < M) return fail(c, MCINV_EINVAL, "capacity too small");
+        MC_TRY(finalize_diag(c, false));
+    } else if (quantity == MCINV_REQ_BLOCK) {
+        M = c->nI * c->nJ;
+        if (capacity < M) return fail(c, MCINV_EINVAL, "capacity too small");
+        MC_TRY(finalize_flat(c, c->d_block, M, c->block_slot_stride()));
+    } else if (quantity == MCINV_REQ_ENTRIES) {
+        M = c->ne;
+        if (capacity < M) return fail(c, MCINV_EINVAL, "capacity too small");
+        MC_TRY(finalize_flat(c, c->d_entries, M, c->entry_slot_stride()));
+    } else if (quantity == MCINV_REQ_TRACE) {
+        if (capacity < 1) return fail(c, MCINV_EINVAL, "capacity too small");
+        if (c->samples < 1) return fail(c, MCINV_ESTATE, "no samples yet");
+        HIP_TRY(c, launch_geyer(c->d_series, c->samples, c->comps, 1.0 / (double)c->P, c->d_geyer, c->stream));
+        double g[6];
+        HIP_TRY(c, hipMemcpyAsync(g, c->d_geyer, sizeof(g), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        if (est) {
+            est[0] = g[0];
+            if (c->comps == 2) est[1] = g[1];
+        }
+        if (stderr_) stderr_[0] = g[5];
+        return MCINV_OK;
+    } else {
+        return fail(c, MCINV_EINVAL, "quantity must be exactly one MCINV_REQ_* flag");
+    }
+    if (est)
+        HIP_TRY(c, hipMemcpyAsync(est, c->d_est, sizeof(double) * M * c->comps, hipMemcpyDeviceToHost, c->stream));
+    if (stderr_) HIP_TRY(c, hipMemcpyAsync(stderr_, c->d_se, sizeof(double) * M, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return MCINV_OK;
+}
+
+mcinv_status mcinv_read_state(mcinv_ctx* c, int32_t which, void* host, int64_t bytes)
+{
+    MC_TRY(check_ready(c));
+    if (which != 0 && which != 1) return fail(c, MCINV_EINVAL, "which must be 0 (z) or 1 (w)");
+    if (!host || bytes < c->n * c->P * (int64_t)c->elem) return fail(c, MCINV_EINVAL, "host buffer too small");
+    std::vector<char> tmp((size_t)(c->n * c->ld * c->elem));
+    HIP_TRY(c, hipMemcpyAsync(tmp.data(), which ? c->d_w : c->d_z, tmp.size(), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    char* out = (char*)host;
+    const size_t row_bytes = (size_t)c->P * c->elem;
+    for (int64_t i = 0; i < c->n; ++i)
+        std::memcpy(out + (size_t)i * row_bytes, tmp.data() + (size_t)c->pos[i] * c->ld * c->elem, row_bytes);
+    return MCINV_OK;
+}
+
+mcinv_status mcinv_write_state(mcinv_ctx* c, int32_t which, const void* host, int64_t bytes)
+{
+    MC_TRY(check_ready(c));
+    if (which != 0 && which != 1) return fail(c, MCINV_EINVAL, "which must be 0 (z) or 1 (w)");
+    if (!host || bytes < c->n * c->P * (int64_t)c->elem) return fail(c, MCINV_EINVAL, "host buffer too small");
+    std::vector<char> tmp((size_t)(c->n * c->ld * c->elem), 0);
+    const char* in = (const char*)host;
+    const size_t row_bytes = (size_t)c->P * c->elem;
+    for (int64_t i = 0; i < c->n; ++i)
+        std::memcpy(tmp.data() + (size_t)c->pos[i] * c->ld * c->elem, in + (size_t)i * row_bytes, row_bytes);
+    HIP_TRY(c, hipMemcpyAsync(which ? c->d_w : c->d_z, tmp.data(), tmp.size(), hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return MCINV_OK;
+}
+
+mcinv_status mcinv_get_permutation(mcinv_ctx* c, int64_t* perm, int32_t* color_of_row)
+{
+    MC_TRY(check_ready(c));
+    if (perm) std::memcpy(perm, c->perm.data(), sizeof(int64_t) * c->n);
+    if (color_of_row) std::memcpy(color_of_row, c->color.data(), sizeof(int32_t) * c->n);
+    return MCINV_OK;
+}
+
+mcinv_status mcinv_check_convergence(mcinv_ctx* c, int64_t iters, double* rho_T, double* rho_S)
+{
+    MC_TRY(check_ready(c));
+    if (iters < 2) return fail(c, MCINV_EINVAL, "iters must be >= 2");
+    const int64_t ld = 4;
+    const size_t bytes = (size_t)c->n * ld * c->elem;
+    void *zc = nullptr, *wc = nullptr;
+    int32_t* fl = nullptr;
+    HIP_TRY(c, hipMalloc(&zc, bytes));
+    HIP_TRY(c, hipMalloc(&wc, bytes));
+    HIP_TRY(c, hipMalloc((void**)&fl, sizeof(int32_t)));
+    HIP_TRY(c, hipMemsetAsync(fl, 0, sizeof(int32_t), c->stream));
+    // x_i = i (1-based, Algorithm 1's second start) in every lane.
+    std::vector<char> init(bytes, 0);
+    for (int64_t q = 0; q < c->n; ++q)
+        for (int64_t p = 0; p < ld; ++p) {
+            const double x = (double)(c->perm[q] + 1);
+            char* dst = init.data() + ((size_t)q * ld + p) * c->elem;
+            if (c->cfg.sweep_dtype == MCINV_R32 || c->cfg.sweep_dtype == MCINV_C64) {
+                const float xf = (float)x;
+                std::memcpy(dst, &xf, sizeof(float));
+            } else {
+                std::memcpy(dst, &x, sizeof(double));
+            }
+        }
+    HIP_TRY(c, hipMemcpyAsync(zc, init.data(), bytes, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(wc, init.data(), bytes, hipMemcpyHostToDevice, c->stream));
+    std::vector<char> host(bytes);
+    auto norms = [&](double* nz, double* nw) -> mcinv_status {
+        double m[2] = {0.0, 0.0};
+        for (int which = 0; which < 2; ++which) {
+            HIP_TRY(c, hipMemcpyAsync(host.data(), which ? wc : zc, bytes, hipMemcpyDeviceToHost, c->stream));
+            HIP_TRY(c, hipStreamSynchronize(c->stream));
+            const int comps = c->comps;
+            const bool f32 = c->cfg.sweep_dtype == MCINV_R32 || c->cfg.sweep_dtype == MCINV_C64;
+            for (int64_t q = 0; q < c->n; ++q) {
+                double re = 0, im = 0;
+                const char* src = host.data() + (size_t)q * ld * c->elem;
+                if (f32) {
+                    re = ((const float*)src)[0];
+                    if (comps == 2) im = ((const float*)src)[1];
+                } else {
+                    re = ((const double*)src)[0];
+                    if (comps == 2) im = ((const double*)src)[1];
+                }
+                m[which] = std::max(m[which], std::sqrt(re * re + im * im));
+            }
+        }
+        *nz = m[0];
+        *nw = m[1];
+        return MCINV_OK;
+    };
+    const int64_t half = iters / 2;
+    double z1 = 0, w1 = 0, z2 = 0, w2 = 0;
+    mcinv_status s = MCINV_OK;
+    auto sweep = [&](int64_t k) -> mcinv_status {
+        switch (c->cfg.sweep_dtype) {
+        case MCINV_R32: return run_sweeps<float>(c, k, false, (float*)zc, (float*)wc, ld, 1, MCINV_NOISE_NONE, fl, false);
+        case MCINV_R64: return run_sweeps<double>(c, k, false, (double*)zc, (double*)wc, ld, 1, MCINV_NOISE_NONE, fl, false);
+        case MCINV_C64:
+            return run_sweeps<Cx<float>>(c, k, false, (Cx<float>*)zc, (Cx<float>*)wc, ld, 1, MCINV_NOISE_NONE, fl, false);
+        default:
+            return run_sweeps<Cx<double>>(c, k, false, (Cx<double>*)zc, (Cx<double>*)wc, ld, 1, MCINV_NOISE_NONE, fl,
+                                          false);
+        }
+    };
+    if ((s = sweep(half)) == MCINV_OK && (s = norms(&z1, &w1)) == MCINV_OK && (s = sweep(iters - half)) == MCINV_OK)
+        s = norms(&z2, &w2);
+    (void)hipFree(zc);
+    (void)hipFree(wc);
+    (void)hipFree(fl);
+    if (s != MCINV_OK) return s;
+    const double m = (double)(iters - half);
+    auto rate = [&](double a, double b) -> double {
+        if (!(a > 0.0) || !(b > 0.0)) return 0.0;
+        if (!std::isfinite(a) || !std::isfinite(b)) return INFINITY;
+        return std::pow(b / a, 1.0 / m);
+    };
+    if (rho_T) *rho_T = rate(z1, z2);
+    if (rho_S) *rho_S = rate(w1, w2);
+    return MCINV_OK;
+}
+
+mcinv_status mcinv_get_info(mcinv_ctx* c, mcinv_info* out)
+{
+    if (!c || !out) return fail(c, MCINV_EINVAL, "null argument");
+    std::memset(out, 0, sizeof(*out));
+    out->n = c->n;
+    out->nnz = c->nnz;
+    out->n_pairs = c->P;
+    out->ld = c->ld;
+    out->n_colors = c->ncolors;
+    out->n_groups = (int32_t)c->G;
+    out->sweeps_done = c->sweeps;
+    out->samples_done = c->samples;
+    out->batch_len = c->nslots > 1 ? c->batch_len : c->samples;
+    out->n_batches = c->nslots > 1 ? (c->samples + c->batch_len - 1) / c->batch_len : 1;
+    out->offdiag_entries = c->n_off;
+    out->sweep_kernel_ms = c->sweep_ms;
+    out->sweep_kernel_launches = c->sweep_launches;
+    out->moment_kernel_ms = c->moment_ms;
+    out->moment_kernel_launches = c->moment_launches;
+    return MCINV_OK;
+}
+
+mcinv_status mcinv_reset_profile(mcinv_ctx* c)
+{
+    if (!c) return fail(nullptr, MCINV_EINVAL, "null context");
+    c->sweep_ms = c->moment_ms = 0.0;
+    c->sweep_launches = c->moment_launches = 0;
+    return MCINV_OK;
+}
+
+mcinv_status mcinv_noise_values(int32_t device, uint64_t seed, uint32_t stream_id, int32_t noise, int32_t dtype,
+                                int64_t count, const int64_t* row, const int64_t* sweep, const int64_t* pair,
+                                double* out)
+{
+    if (count < 0 || (count > 0 && (!row || !sweep || !pair || !out)))
+        return fail(nullptr, MCINV_EINVAL, "bad arguments");
+    if (dtype != MCINV_R32 && dtype != MCINV_R64) return fail(nullptr, MCINV_EINVAL, "dtype must be R32 or R64");
+    if (noise < 0 || noise > 2) return fail(nullptr, MCINV_EINVAL, "unknown noise kind");
+    if (count == 0) return MCINV_OK;
+    HIP_TRY(nullptr, hipSetDevice(device));
+    int64_t *dr = nullptr, *dk = nullptr, *dp = nullptr;
+    double* dout = nullptr;
+    const size_t b = sizeof(int64_t) * count;
+    HIP_TRY(nullptr, hipMalloc((void**)&dr, b));
+    HIP_TRY(nullptr, hipMalloc((void**)&dk, b));
+    HIP_TRY(nullptr, hipMalloc((void**)&dp, b));
+    HIP_TRY(nullptr, hipMalloc((void**)&dout, sizeof(double) * count));
+    hipError_t e = hipMemcpy(dr, row, b, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dk, sweep, b, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dp, pair, b, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_noise_values(dtype == MCINV_R64, seed, stream_id, noise, count, dr, dk, dp, dout, nullptr);
+    if (e == hipSuccess) e = hipMemcpy(out, dout, sizeof(double) * count, hipMemcpyDeviceToHost);
+    (void)hipFree(dr);
+    (void)hipFree(dk);
+    (void)hipFree(dp);
+    (void)hipFree(dout);
+    if (e != hipSuccess) return fail(nullptr, MCINV_EDEVICE, std::string("noise kernel: ") + hipGetErrorString(e));
+    return MCINV_OK;
+}
+
+const char* mcinv_last_error(const mcinv_ctx* c)
+{
+    return c ? c->err.c_str() : g_error.c_str();
+}
+
+}  // extern "C"

@@ -1,0 +1,412 @@
+// Moment accumulation and finalisation kernels (eq 1/C, eq tr, Sec. 2.3).
+//
+//  - k_block_fp64: dense requested block, sum over each chain group of
+//    z[I_r][p] conj(w[J_t][p]) in fp64, 32 x 32 output tile per workgroup with
+//    LDS-staged z and w tiles.
+//  - k_entries: an arbitrary list of (i, j) entries.
+//  - k_merge_slots: doubles the time-batch length of the error clusters.
+//  - k_reduce_sum: deterministic two-stage sum (per-sweep trace value).
+//  - k_finalize_*: cluster ratio estimator -> estimate and standard error.
+//  - k_geyer: Geyer's initial positive sequence on the trace series.
+#include "device_common.h"
+#include "sweep.h"
+
+namespace mcinv {
+
+template <typename V> struct Wide;
+template <> struct Wide<float> { using type = double; };
+template <> struct Wide<double> { using type = double; };
+template <> struct Wide<Cx<float>> { using type = Cx<double>; };
+template <> struct Wide<Cx<double>> { using type = Cx<double>; };
+
+__device__ inline double widen(float x) { return x; }
+__device__ inline double widen(double x) { return x; }
+__device__ inline Cx<double> widen(Cx<float> x) { return Cx<double>{x.re, x.im}; }
+__device__ inline Cx<double> widen(Cx<double> x) { return x; }
+
+// acc + x conj(y)
+__device__ inline double conj_fma(double x, double y, double acc) { return __builtin_fma(x, y, acc); }
+__device__ inline Cx<double> conj_fma(Cx<double> x, Cx<double> y, Cx<double> acc)
+{
+    acc.re = __builtin_fma(x.re, y.re, acc.re);
+    acc.re = __builtin_fma(x.im, y.im, acc.re);
+    acc.im = __builtin_fma(x.im, y.re, acc.im);
+    acc.im = __builtin_fma(-x.re, y.im, acc.im);
+    return acc;
+}
+
+__device__ inline void add_to(double* p, double v) { p[0] += v; }
+__device__ inline void add_to(double* p, Cx<double> v)
+{
+    p[0] += v.re;
+    p[1] += v.im;
+}
+
+// ------------------------------------------------------------------ block --
+constexpr int kBT = 32;  // output tile edge
+constexpr int kBK = 32;  // pairs per LDS stage
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_block_fp64(const BlockArgs<V> a)
+{
+    using W = typename Wide<V>::type;
+    constexpr int comps = IsCx<V>::value ? 2 : 1;
+    __shared__ W zs[kBT][kBK + 1];
+    __shared__ W ws[kBT][kBK + 1];
+
+    const int tid = threadIdx.x;
+    const int tx = tid & 15, ty = tid >> 4;
+    const int64_t r0 = (int64_t)blockIdx.y * kBT;
+    const int64_t t0 = (int64_t)blockIdx.x * kBT;
+    const int64_t g = blockIdx.z;
+    const int64_t pbeg = g * a.gs, pend = pbeg + a.gs;
+
+    W acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = vzero<W>();
+
+    const int lr = tid >> 3;         // row of the tile this thread loads
+    const int lk = (tid & 7) * 4;    // first pair of the four it loads
+    const int64_t zrow = (r0 + lr < a.nI) ? a.I[r0 + lr] : -1;
+    const int64_t wrow = (t0 + lr < a.nJ) ? a.J[t0 + lr] : -1;
+
+    for (int64_t kb = pbeg; kb < pend; kb += kBK) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t p = kb + lk + e;
+            const bool ok = p < pend;
+            zs[lr][lk + e] = (ok && zrow >= 0) ? widen(a.z[zrow * a.ld + p]) : vzero<W>();
+            ws[lr][lk + e] = (ok && wrow >= 0) ? widen(a.w[wrow * a.ld + p]) : vzero<W>();
+        }
+        __syncthreads();
+#pragma unroll 8
+        for (int k = 0; k < kBK; ++k) {
+            const W z0 = zs[ty][k], z1 = zs[ty + 16][k];
+            const W w0 = ws[tx][k], w1 = ws[tx + 16][k];
+            acc[0][0] = conj_fma(z0, w0, acc[0][0]);
+            acc[0][1] = conj_fma(z0, w1, acc[0][1]);
+            acc[1][0] = conj_fma(z1, w0, acc[1][0]);
+            acc[1][1] = conj_fma(z1, w1, acc[1][1]);
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int64_t r = r0 + ty + 16 * i;
+        if (r >= a.nI) continue;
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+            const int64_t t = t0 + tx + 16 * j;
+            if (t >= a.nJ) continue;
+            add_to(a.acc + comps * ((g * a.nI + r) * a.nJ + t), acc[i][j]);
+        }
+    }
+}
+
+template <typename V>
+hipError_t launch_block_fp64(const BlockArgs<V>& a, hipStream_t stream)
+{
+    if (a.nI <= 0 || a.nJ <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((a.nJ + kBT - 1) / kBT), (unsigned)((a.nI + kBT - 1) / kBT), (unsigned)a.G);
+    k_block_fp64<V><<<grid, dim3(256), 0, stream>>>(a);
+    return hipGetLastError();
+}
+template hipError_t launch_block_fp64<float>(const BlockArgs<float>&, hipStream_t);
+template hipError_t launch_block_fp64<double>(const BlockArgs<double>&, hipStream_t);
+template hipError_t launch_block_fp64<Cx<float>>(const BlockArgs<Cx<float>>&, hipStream_t);
+template hipError_t launch_block_fp64<Cx<double>>(const BlockArgs<Cx<double>>&, hipStream_t);
+
+// ---------------------------------------------------------------- entries --
+template <typename V>
+__global__ __launch_bounds__(256) void k_entries(const V* z, const V* w, int64_t ld, const int64_t* ei,
+                                                 const int64_t* ej, int64_t ne, int64_t gs, int64_t G,
+                                                 double* acc)
+{
+    using W = typename Wide<V>::type;
+    constexpr int comps = IsCx<V>::value ? 2 : 1;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= ne * G) return;
+    const int64_t e = t % ne, g = t / ne;
+    const V* zr = z + ei[e] * ld;
+    const V* wr = w + ej[e] * ld;
+    W s = vzero<W>();
+    for (int64_t p = g * gs; p < (g + 1) * gs; ++p) s = conj_fma(widen(zr[p]), widen(wr[p]), s);
+    add_to(acc + comps * (g * ne + e), s);
+}
+
+template <typename V>
+hipError_t launch_entries(const V* z, const V* w, int64_t ld, const int64_t* ei, const int64_t* ej, int64_t ne,
+                          int64_t gs, int64_t G, double* acc, hipStream_t stream)
+{
+    if (ne <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((ne * G + 255) / 256);
+    k_entries<V><<<dim3(blocks), dim3(256), 0, stream>>>(z, w, ld, ei, ej, ne, gs, G, acc);
+    return hipGetLastError();
+}
+template hipError_t launch_entries<float>(const float*, const float*, int64_t, const int64_t*, const int64_t*,
+                                          int64_t, int64_t, int64_t, double*, hipStream_t);
+template hipError_t launch_entries<double>(const double*, const double*, int64_t, const int64_t*,
+                                           const int64_t*, int64_t, int64_t, int64_t, double*, hipStream_t);
+template hipError_t launch_entries<Cx<float>>(const Cx<float>*, const Cx<float>*, int64_t, const int64_t*,
+                                              const int64_t*, int64_t, int64_t, int64_t, double*, hipStream_t);
+template hipError_t launch_entries<Cx<double>>(const Cx<double>*, const Cx<double>*, int64_t, const int64_t*,
+                                               const int64_t*, int64_t, int64_t, int64_t, double*, hipStream_t);
+
+// ------------------------------------------------------------ slot merge --
+// One thread per element walks the slots upwards: slot m is written only
+// after slots 2m and 2m+1 (both >= m) were read, so the update is in place.
+__global__ __launch_bounds__(256) void k_merge_slots(double* acc, int64_t slot_elems, int64_t half)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= slot_elems) return;
+    for (int64_t m = 0; m < half; ++m)
+        acc[m * slot_elems + e] = acc[(2 * m) * slot_elems + e] + acc[(2 * m + 1) * slot_elems + e];
+    for (int64_t m = half; m < 2 * half; ++m) acc[m * slot_elems + e] = 0.0;
+}
+
+hipError_t launch_merge_slots(double* acc, int64_t slot_elems, int64_t half, hipStream_t stream)
+{
+    if (slot_elems <= 0 || half <= 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((slot_elems + 255) / 256);
+    k_merge_slots<<<dim3(blocks), dim3(256), 0, stream>>>(acc, slot_elems, half);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ reductions --
+template <int NT>
+__device__ inline double block_sum(double v, double* lds)
+{
+    lds[threadIdx.x] = v;
+    __syncthreads();
+#pragma unroll
+    for (int s = NT / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) lds[threadIdx.x] += lds[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double r = lds[0];
+    __syncthreads();
+    return r;
+}
+
+constexpr int kRedBlocks = 128;
+
+// Stage 1: block b sums a fixed contiguous chunk; the last block to finish
+// (atomic ticket) sums the kRedBlocks partials in order.  Deterministic.
+__global__ __launch_bounds__(256) void k_reduce_sum(const double* x, int64_t count, int comps,
+                                                     double* partial, uint32_t* counter, double* out)
+{
+    __shared__ double lds[256];
+    __shared__ bool last;
+    const int64_t chunk = (count + gridDim.x - 1) / gridDim.x;
+    const int64_t beg = (int64_t)blockIdx.x * chunk;
+    const int64_t end = beg + chunk < count ? beg + chunk : count;
+    for (int c = 0; c < comps; ++c) {
+        double s = 0.0;
+        for (int64_t i = beg + threadIdx.x; i < end; i += 256) s += x[i * comps + c];
+        s = block_sum<256>(s, lds);
+        if (threadIdx.x == 0) partial[blockIdx.x * comps + c] = s;
+    }
+    __threadfence();
+    if (threadIdx.x == 0) {
+        const uint32_t ticket = atomicAdd(counter, 1u);
+        last = ticket == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    for (int c = 0; c < comps; ++c) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < (int)gridDim.x; b += 256)
+            s += __hip_atomic_load(&partial[b * comps + c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s = block_sum<256>(s, lds);
+        if (threadIdx.x == 0) out[c] = s;
+    }
+    if (threadIdx.x == 0) *counter = 0u;
+}
+
+hipError_t launch_reduce_sum(const double* x, int64_t count, int comps, double* partial, uint32_t* counter,
+                             double* out, hipStream_t stream)
+{
+    k_reduce_sum<<<dim3(kRedBlocks), dim3(256), 0, stream>>>(x, count, comps, partial, counter, out);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------- finalize --
+// Ratio estimator over clusters c = (slot b, group g) with n_c = slot_len[b] gs
+// terms and sum S_c:  est = sum S_c / sum n_c,
+// Var = nc/(nc-1) sum_c (S_c - n_c est)^2 / (sum n_c)^2  (per real component).
+
+// Diagonal: one thread per position; groups gather their columns.
+__global__ __launch_bounds__(64) void k_finalize_diag(const FinalizeArgs f)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= f.M) return;
+    const int64_t ncl = f.nslots * f.G;
+    const int64_t cols_per_group = f.G > 1 ? f.gs / f.pairs_per_col : f.A;
+    // Sums are formed on the fly per cluster (two passes).
+    double wsum = 0.0, er = 0.0, ei = 0.0;
+    int64_t nc = 0;
+    for (int64_t c = 0; c < ncl; ++c) {
+        const int64_t b = c / f.G, g = c % f.G;
+        const double wt = f.slot_len[b] * (double)f.gs;
+        if (wt <= 0.0) continue;
+        const double* row = f.acc + b * f.slot_stride + q * f.A * f.comps;
+        double sr = 0.0, si = 0.0;
+        for (int64_t k = g * cols_per_group; k < (g + 1) * cols_per_group && k < f.A; ++k) {
+            sr += row[k * f.comps];
+            if (f.comps == 2) si += row[k * 2 + 1];
+        }
+        wsum += wt;
+        er += sr;
+        ei += si;
+        ++nc;
+    }
+    const int64_t out = f.out_index[q];
+    if (wsum <= 0.0) {
+        f.est[out * f.comps] = __builtin_nan("");
+        if (f.comps == 2) f.est[out * 2 + 1] = __builtin_nan("");
+        f.se[out] = __builtin_nan("");
+        if (f.max_rel) atomicMax(f.max_rel, (unsigned long long)__double_as_longlong(__builtin_inf()));
+        return;
+    }
+    er /= wsum;
+    ei /= wsum;
+    double vr = 0.0, vi = 0.0;
+    for (int64_t c = 0; c < ncl; ++c) {
+        const int64_t b = c / f.G, g = c % f.G;
+        const double wt = f.slot_len[b] * (double)f.gs;
+        if (wt <= 0.0) continue;
+        const double* row = f.acc + b * f.slot_stride + q * f.A * f.comps;
+        double sr = 0.0, si = 0.0;
+        for (int64_t k = g * cols_per_group; k < (g + 1) * cols_per_group && k < f.A; ++k) {
+            sr += row[k * f.comps];
+            if (f.comps == 2) si += row[k * 2 + 1];
+        }
+        const double dr = sr - wt * er;
+        vr += dr * dr;
+        if (f.comps == 2) {
+            const double di = si - wt * ei;
+            vi += di * di;
+        }
+    }
+    double se = __builtin_nan("");
+    if (nc >= 2) se = sqrt((vr + vi) * ((double)nc / (double)(nc - 1))) / wsum;
+    f.est[out * f.comps] = er;
+    if (f.comps == 2) f.est[out * 2 + 1] = ei;
+    f.se[out] = se;
+    if (f.max_rel != nullptr) {
+        double rel = se / sqrt(er * er + ei * ei);
+        if (!(rel >= 0.0) || !(rel < __builtin_inf())) rel = __builtin_inf();
+        atomicMax(f.max_rel, (unsigned long long)__double_as_longlong(rel));
+    }
+}
+
+// Flat accumulators [nslots][G][M]: one thread per value.
+__global__ __launch_bounds__(64) void k_finalize_flat(const FinalizeArgs f)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= f.M) return;
+    const int64_t ncl = f.nslots * f.G;
+    double wsum = 0.0, er = 0.0, ei = 0.0;
+    int64_t nc = 0;
+    for (int64_t c = 0; c < ncl; ++c) {
+        const double wt = f.slot_len[c / f.G] * (double)f.gs;
+        if (wt <= 0.0) continue;
+        const double* v = f.acc + (c / f.G) * f.slot_stride + ((c % f.G) * f.M + m) * f.comps;
+        wsum += wt;
+        er += v[0];
+        if (f.comps == 2) ei += v[1];
+        ++nc;
+    }
+    if (wsum <= 0.0) {
+        f.est[m * f.comps] = __builtin_nan("");
+        if (f.comps == 2) f.est[m * 2 + 1] = __builtin_nan("");
+        f.se[m] = __builtin_nan("");
+        return;
+    }
+    er /= wsum;
+    ei /= wsum;
+    double vr = 0.0, vi = 0.0;
+    for (int64_t c = 0; c < ncl; ++c) {
+        const double wt = f.slot_len[c / f.G] * (double)f.gs;
+        if (wt <= 0.0) continue;
+        const double* v = f.acc + (c / f.G) * f.slot_stride + ((c % f.G) * f.M + m) * f.comps;
+        const double dr = v[0] - wt * er;
+        vr += dr * dr;
+        if (f.comps == 2) {
+            const double di = v[1] - wt * ei;
+            vi += di * di;
+        }
+    }
+    double se = __builtin_nan("");
+    if (nc >= 2) se = sqrt((vr + vi) * ((double)nc / (double)(nc - 1))) / wsum;
+    f.est[m * f.comps] = er;
+    if (f.comps == 2) f.est[m * 2 + 1] = ei;
+    f.se[m] = se;
+}
+
+hipError_t launch_finalize_diag(const FinalizeArgs& f, hipStream_t stream)
+{
+    if (f.M <= 0) return hipSuccess;
+    k_finalize_diag<<<dim3((unsigned)((f.M + 63) / 64)), dim3(64), 0, stream>>>(f);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_flat(const FinalizeArgs& f, hipStream_t stream)
+{
+    if (f.M <= 0) return hipSuccess;
+    k_finalize_flat<<<dim3((unsigned)((f.M + 63) / 64)), dim3(64), 0, stream>>>(f);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------------------- Geyer --
+// gamma_t = (1/S) sum_{k < S-t} (x_k - mean)(x_{k+t} - mean); pairs
+// Gamma_m = gamma_2m + gamma_2m+1 are summed while positive;
+// sigma^2 = -gamma_0 + 2 sum Gamma_m; SE = sqrt(sigma^2 / S).
+__global__ __launch_bounds__(1024) void k_geyer(const double* x, int64_t S, int comps, double scale,
+                                                double* out)
+{
+    __shared__ double lds[1024];
+    double g0_tot = 0.0, sig_tot = 0.0, mean[2] = {0.0, 0.0};
+    for (int c = 0; c < comps; ++c) {
+        double s = 0.0;
+        for (int64_t k = threadIdx.x; k < S; k += 1024) s += x[k * comps + c] * scale;
+        const double mu = block_sum<1024>(s, lds) / (double)S;
+        mean[c] = mu;
+        auto gamma = [&](int64_t t) {
+            double acc = 0.0;
+            for (int64_t k = threadIdx.x; k + t < S; k += 1024)
+                acc += (x[k * comps + c] * scale - mu) * (x[(k + t) * comps + c] * scale - mu);
+            return block_sum<1024>(acc, lds) / (double)S;
+        };
+        const double g0 = gamma(0);
+        double sig2 = -g0;
+        for (int64_t m = 0; 2 * m + 1 < S; ++m) {
+            const double pair_sum = gamma(2 * m) + gamma(2 * m + 1);
+            if (!(pair_sum > 0.0)) break;
+            sig2 += 2.0 * pair_sum;
+        }
+        if (!(sig2 > 0.0)) sig2 = g0;
+        g0_tot += g0;
+        sig_tot += sig2;
+    }
+    if (threadIdx.x == 0) {
+        out[0] = mean[0];
+        out[1] = mean[1];
+        out[2] = g0_tot;
+        out[3] = sig_tot;
+        out[4] = sig_tot > 0.0 ? (double)S * g0_tot / sig_tot : __builtin_nan("");
+        out[5] = S >= 2 ? sqrt(sig_tot / (double)S) : __builtin_nan("");
+    }
+}
+
+hipError_t launch_geyer(const double* series, int64_t S, int comps, double scale, double* out,
+                        hipStream_t stream)
+{
+    k_geyer<<<dim3(1), dim3(1024), 0, stream>>>(series, S, comps, scale, out);
+    return hipGetLastError();
+}
+
+}  // namespace mcinv

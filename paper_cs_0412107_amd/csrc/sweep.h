@@ -1,0 +1,99 @@
+// Kernel argument blocks and launchers of the mcinv device code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_common.h"
+
+namespace mcinv {
+
+// One colour launch of the sweep (eqs 4 and 5) over positions
+// [row_begin, row_end), all pair tiles.
+template <typename V>
+struct SweepArgs {
+    const RowRec* rows;
+    const Entry<V>* ent;
+    const Scales<V>* sc;
+    V* z;                    // state [n][ld], positions x pairs
+    V* w;
+    int64_t ld;              // padded pairs per state row (multiple of 4)
+    int64_t P;               // real pairs (pairs >= P are padding)
+    int64_t row_begin, row_end;
+    uint32_t key0, key1;     // Philox key = seed
+    uint32_t sweep;          // Philox counter word 1
+    uint32_t stream;         // Philox counter word 3
+    int32_t noise;           // NoiseKind
+    int32_t lg_shift;        // log2(lanes summed into one diagonal column)
+    int64_t A;               // diagonal columns per row
+    double* diag;            // slot accumulator [n][A] (x2 for complex) or null
+    double* tpart;           // per-workgroup trace partials of this launch, or null
+    int32_t* flag;           // divergence flag (bit 0)
+    typename Real<V>::type thresh;
+};
+
+template <typename V>
+hipError_t launch_sweep(const SweepArgs<V>& a, bool sample, hipStream_t stream);
+
+hipError_t launch_noise_values(bool fp64, uint64_t seed, uint32_t stream_id, int32_t kind, int64_t count,
+                               const int64_t* row, const int64_t* sweep, const int64_t* pair, double* out,
+                               hipStream_t stream);
+
+// ---------------------------------------------------------------- moments --
+// Dense block moments B[g][r][t] += sum_{p in group g} z[I_r][p] conj(w[J_t][p]) (eq 1/C).
+template <typename V>
+struct BlockArgs {
+    const V* z;
+    const V* w;
+    int64_t ld;
+    const int64_t* I;        // positions of the requested rows
+    const int64_t* J;        // positions of the requested columns
+    int64_t nI, nJ;
+    int64_t gs;              // pairs per group
+    int64_t G;
+    double* acc;             // slot accumulator [G][nI][nJ] (x2 complex)
+};
+
+template <typename V>
+hipError_t launch_block_fp64(const BlockArgs<V>& a, hipStream_t stream);
+hipError_t launch_block_bf16x3(const BlockArgs<float>& a, hipStream_t stream);
+
+// Entry moments E[g][e] += sum_{p in g} z[ei][p] conj(w[ej][p]).
+template <typename V>
+hipError_t launch_entries(const V* z, const V* w, int64_t ld, const int64_t* ei, const int64_t* ej,
+                          int64_t ne, int64_t gs, int64_t G, double* acc, hipStream_t stream);
+
+// acc[m] = acc[2m] + acc[2m+1] for m < half, acc[m] = 0 for half <= m < 2 half.
+hipError_t launch_merge_slots(double* acc, int64_t slot_elems, int64_t half, hipStream_t stream);
+
+// Deterministic sum of x[count][comps] into out[comps] (two stages, one launch).
+hipError_t launch_reduce_sum(const double* x, int64_t count, int comps, double* partial, uint32_t* counter,
+                             double* out, hipStream_t stream);
+
+// Cluster finalisation.  Clusters are (slot b, group g); slot b holds
+// slot_len[b] samples, each group gs pairs.
+struct FinalizeArgs {
+    const double* acc;       // diag: [nslots][n][A]; flat: [nslots][G][M]  (x comps)
+    int64_t nslots;
+    int64_t slot_stride;     // doubles per slot
+    const double* slot_len;  // samples per slot
+    int64_t G;
+    int64_t gs;
+    int64_t M;               // values (positions or flat entries)
+    int64_t A;               // diag only: columns per row
+    int64_t pairs_per_col;   // diag only
+    int comps;               // 1 real, 2 complex
+    const int64_t* out_index;  // diag only: position -> original row
+    double* est;             // [M][comps] (at out_index)
+    double* se;              // [M]
+    unsigned long long* max_rel;  // diag only, may be null: max se/|est| as bits
+};
+hipError_t launch_finalize_diag(const FinalizeArgs& f, hipStream_t stream);
+hipError_t launch_finalize_flat(const FinalizeArgs& f, hipStream_t stream);
+
+// Geyer initial-positive-sequence error of the per-sweep trace series.
+// out[0..1] = mean (re, im), out[2] = gamma_0 (var), out[3] = sigma^2, out[4] = N_eff, out[5] = SE.
+hipError_t launch_geyer(const double* series, int64_t S, int comps, double scale, double* out,
+                        hipStream_t stream);
+
+}  // namespace mcinv

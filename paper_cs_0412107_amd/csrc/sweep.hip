@@ -1,0 +1,221 @@
+// Colour sweep kernel: the coupled noisy Gauss-Seidel updates of eqs (4) and
+// (5) for every row of one colour and every chain pair, with the diagonal and
+// trace moments of eqs (1/C) and (tr) fused into the epilogue when sampling.
+//
+// Rows of one colour share no stored entry, so updating them in parallel is
+// the same as updating them one after another: earlier colours already hold
+// their sweep-k values and later colours their sweep k-1 values, exactly the
+// j<i / j>i split of eqs (4)-(5) on the permuted matrix.
+//
+// Mapping (wave64): a wave owns one row and 256 consecutive chain pairs, four
+// per lane.  The row's merged entries (column, z coefficient, w coefficient)
+// are wave-uniform and arrive through scalar loads; each neighbour costs one
+// coalesced 1-4 KiB segment of z and of w.  One Philox block per lane gives
+// the lane's four noise values.  A 256-thread workgroup holds four rows of
+// one 256-pair tile; grid = (row blocks of the colour) x (pair tiles).
+#include "device_common.h"
+#include "sweep.h"
+
+namespace mcinv {
+
+template <typename V>
+struct alignas(16) Quad {
+    V v[4];
+};
+
+template <typename V>
+__device__ inline Quad<V> load_quad(const V* p)
+{
+    return *reinterpret_cast<const Quad<V>*>(p);
+}
+
+template <typename V>
+__device__ inline void store_quad(V* p, const Quad<V>& q)
+{
+    *reinterpret_cast<Quad<V>*>(p) = q;
+}
+
+// product z * conj(w) in double
+template <typename R>
+__device__ inline void prod_acc(R z, R w, double& re, double&)
+{
+    re += (double)z * (double)w;
+}
+template <typename R>
+__device__ inline void prod_acc(Cx<R> z, Cx<R> w, double& re, double& im)
+{
+    const double zr = z.re, zi = z.im, wr = w.re, wi = w.im;
+    re += zr * wr + zi * wi;
+    im += zi * wr - zr * wi;
+}
+
+template <typename V, bool SAMPLE>
+__global__ __launch_bounds__(256) void k_sweep(const SweepArgs<V> a)
+{
+    using R = typename Real<V>::type;
+    constexpr bool CPLX = IsCx<V>::value;
+    __shared__ double lds_tr[4][2];
+
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t q = a.row_begin + (int64_t)blockIdx.x * 4 + wid;
+    const int64_t p0 = (int64_t)blockIdx.y * kPairsPerWave + lane * kPairsPerLane;
+    const bool row_ok = q < a.row_end;
+    const bool active = p0 < a.ld;
+    double tre = 0.0, tim = 0.0;
+
+    if (row_ok) {
+        const RowRec rr = a.rows[q];
+        V az[4], aw[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) az[j] = aw[j] = vzero<V>();
+
+        // Gather in chunks of U neighbours: all 2U state loads of a chunk are
+        // issued before the first multiply (memory-level parallelism per wave).
+        // A chunk's unused slots reload entry 0 with zero coefficients.
+        constexpr int U = sizeof(V) >= 16 ? 1 : (sizeof(V) >= 8 ? 2 : 4);
+        if (active) {
+            const Entry<V>* e = a.ent + rr.begin;
+            const int cnt = rr.count;
+            for (int base = 0; base < cnt; base += U) {
+                Quad<V> xs[U], ys[U];
+                V us[U], vs[U];
+#pragma unroll
+                for (int t = 0; t < U; ++t) {
+                    const bool ok = base + t < cnt;
+                    const Entry<V> en = e[ok ? base + t : 0];
+                    us[t] = ok ? en.u : vzero<V>();
+                    vs[t] = ok ? en.v : vzero<V>();
+                    const int64_t off = (int64_t)en.col * a.ld + p0;
+                    xs[t] = load_quad(a.z + off);
+                    ys[t] = load_quad(a.w + off);
+                }
+#pragma unroll
+                for (int t = 0; t < U; ++t)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        az[j] = mul_add(us[t], xs[t].v[j], az[j]);
+                        aw[j] = mul_add(vs[t], ys[t].v[j], aw[j]);
+                    }
+            }
+        }
+
+        R phi[4];
+        noise4<R>(a.key0, a.key1, rr.orig, a.sweep, (uint32_t)(p0 >> 2), a.stream, a.noise, phi);
+        const Scales<V> s = a.sc[q];
+        Quad<V> zn, wn;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            zn.v[j] = noisy_update(s.a, phi[j], az[j]);
+            wn.v[j] = noisy_update(s.b, phi[j], aw[j]);
+        }
+        if (active) {
+            store_quad(a.z + q * a.ld + p0, zn);
+            store_quad(a.w + q * a.ld + p0, wn);
+        }
+
+        // Divergence guard (Sec. 2.2): a runaway or non-finite state.
+        R mag = R(0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) mag = fmax(mag, fmax(magnitude(zn.v[j]), magnitude(wn.v[j])));
+        const bool bad = active && !(mag < a.thresh);
+        if (__any(bad) && lane == 0) atomicOr(a.flag, 1);
+
+        if constexpr (SAMPLE) {
+            if (active) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (p0 + j < a.P) prod_acc(zn.v[j], wn.v[j], tre, tim);
+            }
+            const int lg = 1 << a.lg_shift;
+            for (int off = 1; off < lg; off <<= 1) {
+                tre += __shfl_xor(tre, off);
+                if constexpr (CPLX) tim += __shfl_xor(tim, off);
+            }
+            if (a.diag != nullptr && active && (lane & (lg - 1)) == 0) {
+                const int64_t col = p0 >> (2 + a.lg_shift);
+                if constexpr (CPLX) {
+                    double* d = a.diag + 2 * (q * a.A + col);
+                    d[0] += tre;
+                    d[1] += tim;
+                } else {
+                    a.diag[q * a.A + col] += tre;
+                }
+            }
+            for (int off = lg; off < kWave; off <<= 1) {
+                tre += __shfl_xor(tre, off);
+                if constexpr (CPLX) tim += __shfl_xor(tim, off);
+            }
+        }
+    }
+
+    if constexpr (SAMPLE) {
+        if (a.tpart != nullptr) {
+            if (lane == 0) {
+                lds_tr[wid][0] = row_ok ? tre : 0.0;
+                lds_tr[wid][1] = row_ok ? tim : 0.0;
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                const int64_t slot = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+                const double r = ((lds_tr[0][0] + lds_tr[1][0]) + lds_tr[2][0]) + lds_tr[3][0];
+                if constexpr (CPLX) {
+                    const double i = ((lds_tr[0][1] + lds_tr[1][1]) + lds_tr[2][1]) + lds_tr[3][1];
+                    a.tpart[2 * slot] = r;
+                    a.tpart[2 * slot + 1] = i;
+                } else {
+                    a.tpart[slot] = r;
+                }
+            }
+        }
+    }
+}
+
+template <typename V>
+hipError_t launch_sweep(const SweepArgs<V>& a, bool sample, hipStream_t stream)
+{
+    const int64_t rows = a.row_end - a.row_begin;
+    if (rows <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((rows + 3) / 4), (unsigned)((a.ld + kPairsPerWave - 1) / kPairsPerWave));
+    if (sample)
+        k_sweep<V, true><<<grid, dim3(256), 0, stream>>>(a);
+    else
+        k_sweep<V, false><<<grid, dim3(256), 0, stream>>>(a);
+    return hipGetLastError();
+}
+
+template hipError_t launch_sweep<float>(const SweepArgs<float>&, bool, hipStream_t);
+template hipError_t launch_sweep<double>(const SweepArgs<double>&, bool, hipStream_t);
+template hipError_t launch_sweep<Cx<float>>(const SweepArgs<Cx<float>>&, bool, hipStream_t);
+template hipError_t launch_sweep<Cx<double>>(const SweepArgs<Cx<double>>&, bool, hipStream_t);
+
+// --------------------------------------------------------------------------
+// Noise values for given (row, sweep, pair) triples, as the sweep draws them.
+template <typename R>
+__global__ __launch_bounds__(256) void k_noise_values(uint32_t k0, uint32_t k1, uint32_t stream,
+                                                      int32_t kind, int64_t count, const int64_t* row,
+                                                      const int64_t* sweep, const int64_t* pair,
+                                                      double* out)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    R v[4];
+    noise4<R>(k0, k1, (uint32_t)row[t], (uint32_t)sweep[t], (uint32_t)(pair[t] >> 2), stream, kind, v);
+    out[t] = (double)v[pair[t] & 3];
+}
+
+hipError_t launch_noise_values(bool fp64, uint64_t seed, uint32_t stream_id, int32_t kind, int64_t count,
+                               const int64_t* row, const int64_t* sweep, const int64_t* pair, double* out,
+                               hipStream_t stream)
+{
+    if (count <= 0) return hipSuccess;
+    const uint32_t k0 = (uint32_t)(seed & 0xffffffffu), k1 = (uint32_t)(seed >> 32);
+    const unsigned blocks = (unsigned)((count + 255) / 256);
+    if (fp64)
+        k_noise_values<double><<<dim3(blocks), dim3(256), 0, stream>>>(k0, k1, stream_id, kind, count, row, sweep, pair, out);
+    else
+        k_noise_values<float><<<dim3(blocks), dim3(256), 0, stream>>>(k0, k1, stream_id, kind, count, row, sweep, pair, out);
+    return hipGetLastError();
+}
+
+}  // namespace mcinv

@@ -1,0 +1,354 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle on the
+same seeded inputs.  Per-sample chain states and estimates must agree to
+1e-5 normwise relative for 32-bit sweeps and 1e-12 for 64-bit sweeps."""
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from gpu_util import TOL, make_oracle, oracle_matrix, print_case, rel_err
+
+pytestmark = pytest.mark.gpu
+
+mc = pytest.importorskip("paper_cs_0412107_amd")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _sampler(m, dtype, seed, pairs, groups=1, **kw):
+    return mc.Sampler(oracle_matrix(m, dtype), pairs=pairs, groups=groups, dtype=dtype, seed=seed, **kw)
+
+
+# ------------------------------------------------------------------ noise --
+@pytest.mark.parametrize("kind", [mc.MCINV_NOISE_NORMAL, mc.MCINV_NOISE_RADEMACHER])
+@pytest.mark.parametrize("dtype", [mc.MCINV_R32, mc.MCINV_R64])
+def test_noise_matches_oracle(kind, dtype):
+    print_case(test="noise", kind=kind, dtype=dtype)
+    rng = np.random.default_rng(5)
+    cnt = 3000
+    rows = rng.integers(0, 2 ** 31, cnt)
+    sweeps = rng.integers(0, 100000, cnt)
+    pairs = rng.integers(0, 1 << 20, cnt)
+    seed, stream = 0x412107ABCDEF, 3
+    g = mc.mcinv_noise_values(0, seed, stream, kind, dtype, rows, sweeps, pairs)
+    o = np.array([oracle.lib().ora_noise(seed, stream, int(r), int(k), int(p), kind)
+                  for r, k, p in zip(rows, sweeps, pairs)])
+    if kind == mc.MCINV_NOISE_RADEMACHER:
+        assert np.array_equal(g, o)
+    else:
+        tol = 1e-13 if dtype == mc.MCINV_R64 else 2e-5
+        assert np.max(np.abs(g - o)) <= tol
+
+
+# -------------------------------------------------------------- colouring --
+@pytest.mark.parametrize("name,maker", [
+    ("random200", lambda: gen.random_dominant(200, seed=1000)),
+    ("pedigree3000", lambda: gen.pedigree(3000, seed=3)),
+    ("lattice4", lambda: gen.lattice(4, seed=2)),
+])
+def test_coloring_matches_oracle(name, maker):
+    print_case(test="coloring", matrix=name)
+    m = maker()
+    dt = "c128" if m.is_complex else "f64"
+    with _sampler(m, dt, 1, 4) as s:
+        perm, color = s.permutation()
+    ocolor, order, _ = oracle.greedy_color(m)
+    assert np.array_equal(color, ocolor)
+    assert np.array_equal(perm, order)
+
+
+# ------------------------------------------------------------ chain state --
+STATE_CASES = [
+    ("random200", "f64", 6, [1, 2, 10, 100]),
+    ("random200", "f32", 6, [1, 2, 10, 100]),
+    ("pedigree2000", "f32", 300, [1, 5, 30]),
+    ("pedigree2000", "f64", 260, [1, 5, 30]),
+    ("lattice4", "c64", 64, [1, 3, 20]),
+    ("lattice4", "c128", 68, [1, 3, 20]),
+    ("diag", "f64", 5, [1, 2]),
+    ("cdiag", "c128", 5, [1, 2]),
+]
+
+
+def _matrix(name):
+    if name == "random200":
+        return gen.random_dominant(200, seed=1000)
+    if name == "pedigree2000":
+        return gen.pedigree(2000, seed=11)
+    if name == "lattice4":
+        return gen.lattice(4, seed=7)
+    if name == "diag":
+        return gen.diag_matrix(np.array([2.0, -3.0, 0.5, 7.0, -0.25]))
+    if name == "cdiag":
+        return gen.diag_matrix(np.array([2.0, -3.0, 0.5 + 1j, -1 - 2j, 1j]))
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("name,dtype,P,checks", STATE_CASES)
+def test_state_parity(name, dtype, P, checks):
+    print_case(test="state", matrix=name, dtype=dtype, P=P)
+    m = _matrix(name)
+    seed = 0x412107 + 17
+    ora = make_oracle(m, dtype, seed, P)
+    with _sampler(m, dtype, seed, P) as s:
+        done = 0
+        for k in checks:
+            s.burn_in(k - done)
+            ora.burn_in(k - done)
+            done = k
+            for which, ref in ((0, ora.z), (1, ora.w)):
+                x = s.state(which)
+                err = rel_err(x, ref)
+                assert err <= TOL[dtype], (k, which, err)
+
+
+def test_state_parity_from_given_start():
+    """Algorithm 1 step 1 allows arbitrary starting values: both sides start
+    from z_i = w_i = i and must stay equal."""
+    m = gen.random_dominant(120, seed=4)
+    P, seed = 8, 99
+    ora = make_oracle(m, "f64", seed, P)
+    init = np.repeat(np.arange(1, m.n + 1, dtype=np.float64)[:, None], P, axis=1)
+    ora.z[:] = init
+    ora.w[:] = init
+    with _sampler(m, "f64", seed, P) as s:
+        s.set_state(0, init)
+        s.set_state(1, init)
+        for _ in range(3):
+            s.burn_in(4)
+            ora.burn_in(4)
+            assert rel_err(s.state(0), ora.z) <= 1e-12
+            assert rel_err(s.state(1), ora.w) <= 1e-12
+
+
+# -------------------------------------------------------------- estimates --
+EST_CASES = [
+    # name, dtype, P, G, burn, samples
+    ("random200", "f64", 8, 1, 50, 300),
+    ("random200", "f32", 8, 1, 50, 300),
+    ("pedigree2000", "f32", 512, 16, 10, 40),
+    ("lattice4", "c64", 128, 32, 10, 40),
+    ("lattice4", "c128", 64, 16, 10, 30),
+]
+
+
+@pytest.mark.parametrize("name,dtype,P,G,burn,samples", EST_CASES)
+def test_estimate_parity(name, dtype, P, G, burn, samples):
+    print_case(test="estimates", matrix=name, dtype=dtype, P=P, G=G)
+    m = _matrix(name)
+    n = m.n
+    seed = 0x412107 + 23
+    rows = np.r_[np.arange(0, min(n, 37)), [n - 1, 3, 3]]
+    cols = np.r_[np.arange(n - 33, n), [0, 5]]
+    ents = np.array([[0, 0], [1, 7], [n - 1, 2], [5, 5], [9, n - 3]])
+    ora = make_oracle(m, dtype, seed, P, groups=G)
+    ora.burn_in(burn)
+    ora.request(samples, diag=True, block_rows=rows, block_cols=cols, entries=ents, trace=True)
+    ora.sample(samples)
+    with _sampler(m, dtype, seed, P, groups=G) as s:
+        s.burn_in(burn)
+        s.request(diag=True, trace=True, block_rows=rows, block_cols=cols, entries=ents)
+        s.sample(samples)
+        tol = TOL[dtype]
+        setol = 1e-9 if tol < 1e-9 else 2e-3
+        d, dse = s.diag()
+        od, odse = ora.diag()
+        assert rel_err(d, od if m.is_complex else od.real) <= tol
+        assert np.nanmax(np.abs(dse - odse) / odse) <= setol
+        b, bse = s.block()
+        ob, obse = ora.block()
+        assert rel_err(b, ob if m.is_complex else ob.real) <= tol
+        assert np.nanmax(np.abs(bse - obse) / obse) <= setol
+        e, ese = s.entries()
+        oe, oese = ora.entries()
+        assert rel_err(e, oe if m.is_complex else oe.real) <= tol
+        assert np.nanmax(np.abs(ese - oese) / oese) <= setol
+        t, tse = s.trace()
+        ot = ora.trace()
+        assert abs(t - ot["mean"]) <= tol * max(1.0, abs(ot["mean"])) * 10
+        assert abs(tse - ot["se"]) <= setol * ot["se"] + 1e-12
+
+
+def test_time_batches_merge():
+    """With one group the error clusters are time batches whose length doubles
+    when 64 are full; 300 samples end with batches of 8 like the oracle's."""
+    m = gen.random_dominant(60, seed=8)
+    P, seed, S = 4, 5, 300
+    ora = make_oracle(m, "f64", seed, P)
+    ora.burn_in(20)
+    ora.request(S, diag=True, trace=False)
+    ora.sample(S)
+    with _sampler(m, "f64", seed, P) as s:
+        s.burn_in(20)
+        s.request(diag=True, trace=False)
+        s.sample(S)
+        info = s.info()
+        assert info["batch_len"] == ora.batch_len == 8
+        d, dse = s.diag()
+        od, odse = ora.diag()
+        assert rel_err(d, od.real) <= 1e-12
+        assert np.max(np.abs(dse - odse) / odse) <= 1e-9
+
+
+def test_bf16x3_block_moments_close_to_fp64():
+    """Precision form: bf16 hi/lo split products on MFMA with fp32
+    accumulation; the block estimates stay within 1e-4 of the fp64 oracle."""
+    print_case(test="bf16x3")
+    m = gen.pedigree(3000, seed=19)
+    P, G, seed = 1024, 16, 77
+    rows = np.arange(m.n - 70, m.n)
+    cols = np.r_[np.arange(m.n - 45, m.n), np.arange(0, 20)]
+    ora = make_oracle(m, "f32", seed, P, groups=G)
+    ora.burn_in(5)
+    ora.request(10, diag=False, block_rows=rows, block_cols=cols, trace=False)
+    ora.sample(10)
+    with _sampler(m, "f32", seed, P, groups=G, moments="bf16x3") as s:
+        s.burn_in(5)
+        s.request(diag=False, trace=False, block_rows=rows, block_cols=cols)
+        s.sample(10)
+        b, _ = s.block()
+    ob, _ = ora.block()
+    err = rel_err(b, ob.real)
+    print(f"bf16x3 block normwise error vs fp64 oracle: {err:.3e}")
+    assert err <= 1e-4
+
+
+# ----------------------------------------------------------------- errors --
+def test_error_paths():
+    with pytest.raises(mc.McinvError) as ei:
+        mc.Sampler(gen.from_dense(np.array([[1.0, 0.5], [0.5, 0.0]])), pairs=4, dtype="f64")
+    assert ei.value.code == mc.MCINV_ESINGULAR
+    bad = gen.random_dominant(10, seed=1)
+    bad.col = bad.col.copy()
+    bad.col[[0, 1]] = bad.col[[1, 0]]
+    with pytest.raises(mc.McinvError) as ei:
+        mc.Sampler(bad, pairs=4, dtype="f64")
+    assert ei.value.code == mc.MCINV_EINVAL
+    with pytest.raises(mc.McinvError) as ei:
+        mc.Sampler(gen.lattice(4, seed=1), pairs=4, dtype="f32")
+    assert ei.value.code == mc.MCINV_EINVAL
+    with _sampler(gen.random_dominant(10, seed=1), "f64", 1, 4) as s:
+        with pytest.raises(mc.McinvError) as ei:
+            s.sample(1)
+        assert ei.value.code == mc.MCINV_ESTATE
+        with pytest.raises(mc.McinvError) as ei:
+            s.request(block_rows=[0, 10], block_cols=[1])
+        assert ei.value.code == mc.MCINV_EINVAL
+
+
+def test_divergence_reported():
+    C = np.array([[1.0, 2.5, 0.0], [2.0, 1.0, 1.5], [0.0, 3.0, 1.0]])
+    with _sampler(gen.from_dense(C), "f32", 1, 4) as s:
+        rt, rs = s.check_convergence(40)
+        assert rt > 1.0
+        with pytest.raises(mc.McinvError) as ei:
+            s.burn_in(500)
+        assert ei.value.code == mc.MCINV_EDIVERGED
+
+
+def test_convergence_rate_is_spectral_radius():
+    from oracle import theory
+    rng = np.random.default_rng(13)
+    C = -rng.uniform(0.2, 1.0, (30, 30))
+    np.fill_diagonal(C, 0)
+    np.fill_diagonal(C, 1.05 * np.abs(C).sum(axis=1))
+    m = gen.from_dense(C)
+    with _sampler(m, "f64", 1, 4) as s:
+        perm, _ = s.permutation()
+        rt, rs = s.check_convergence(400)
+    Cp = C[np.ix_(perm, perm)]
+    T, S, _ = theory.operators(Cp)
+    assert abs(rt - theory.spectral_radius(T)) < 0.02
+    assert abs(rs - theory.spectral_radius(S)) < 0.02
+
+
+def test_degenerate_one_by_one():
+    m = gen.diag_matrix(np.array([4.0]))
+    with _sampler(m, "f64", 3, 1) as s:
+        s.request(diag=True, trace=True)
+        s.sample(200)
+        d, se = s.diag()
+        assert abs(d[0] - 0.25) < 5 * se[0]
+        z = s.state(0)
+        phi = oracle.noise(3, 0, 0, 199, 0)
+        assert abs(z[0, 0] - phi / 2.0) < 1e-15
+
+
+# -------------------------------------------------------- full-size cases --
+def _exact_diag_entries(m, rows, iters=200):
+    """(C^-1)_ii by Jacobi iterations on C X = [e_i ...] (strictly dominant C)."""
+    A = m.to_scipy().tocsr()
+    d = A.diagonal()[:, None]
+    B = np.zeros((m.n, len(rows)), dtype=A.dtype)
+    B[rows, np.arange(len(rows))] = 1.0
+    X = B / d
+    for _ in range(iters):
+        X = X + (B - A @ X) / d
+    return X[rows, np.arange(len(rows))]
+
+
+def test_pedigree_full_size_sampled_pairs():
+    """The pedigree workload in the benchmark's launch configuration
+    (n = 100000, 4096 pairs in 64 groups, fp32): sampled pair columns match the
+    oracle after 3 sweeps; diagonal estimates at sampled rows agree with an
+    exact solve within 5 standard errors."""
+    w = gen.WORKLOADS["pedigree"]
+    m = gen.pedigree(w["n"], seed=w["seed"])
+    P, G, seed = w["pairs"], w["groups"], w["noise_seed"]
+    mo = oracle_matrix(m, "f32")
+    pids = np.array([0, 1, 2, 3, 255, 256, 2047, 4095])
+    print_case(test="pedigree_full", n=m.n, P=P)
+    ora = oracle.Run(mo, seed=seed, pairs=P, groups=G, pair_ids=pids)
+    with mc.Sampler(mo, pairs=P, groups=G, dtype="f32", seed=seed) as s:
+        s.burn_in(3)
+        ora.burn_in(3)
+        for which, ref in ((0, ora.z), (1, ora.w)):
+            x = s.state(which)[:, pids]
+            assert rel_err(x, ref) <= 1e-5
+        s.burn_in(47)
+        rows = np.r_[np.arange(0, 10), np.arange(m.n - 10, m.n), np.arange(50000, 50010)]
+        s.request(diag=True, trace=True, block_rows=np.arange(m.n - 256, m.n),
+                  block_cols=np.arange(m.n - 256, m.n))
+        s.sample(20)
+        d, se = s.diag()
+        b, bse = s.block()
+    exact = _exact_diag_entries(mo, rows)
+    z = (d[rows] - exact) / se[rows]
+    assert np.max(np.abs(z)) < 5.0
+    assert np.allclose(np.diag(b), d[m.n - 256:], rtol=1e-9)
+
+
+def test_lattice_full_size_exact():
+    """16^4 lattice, complex64 sweeps, 1024 pairs: with site-independent
+    phases every diagonal entry of C^-1 equals tr(C^-1)/16^4 in closed form."""
+    from oracle import theory
+    w = gen.WORKLOADS["lattice"]
+    m = gen.lattice(w["L"], k=w["k"], seed=w["seed"], constant_phase=True)
+    pr = m.params
+    dex, trex = theory.lattice_constant_phase_inverse_diag(w["L"], pr["k"], pr["a"], pr["b"], pr["theta"],
+                                                           pr["theta_p"])
+    P, G, seed = w["pairs"], w["groups"], w["noise_seed"]
+    mo = oracle_matrix(m, "c64")
+    pids = np.array([0, 5, 511, 1023])
+    print_case(test="lattice_full", n=m.n, P=P)
+    ora = oracle.Run(mo, seed=seed, pairs=P, groups=G, pair_ids=pids)
+    with mc.Sampler(mo, pairs=P, groups=G, dtype="c64", seed=seed) as s:
+        assert s.info()["n_colors"] == 2
+        s.burn_in(3)
+        ora.burn_in(3)
+        for which, ref in ((0, ora.z), (1, ora.w)):
+            assert rel_err(s.state(which)[:, pids], ref) <= 1e-5
+        s.burn_in(27)
+        s.request(diag=True, trace=True)
+        s.sample(30)
+        d, se = s.diag()
+        t, tse = s.trace()
+    z = np.abs(d - dex) / se
+    assert np.mean(z) < 1.5 and np.max(z) < 6.0
+    assert abs(t - trex) < 5 * tse
