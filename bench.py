@@ -37,6 +37,33 @@ def algorithmic_bytes_per_sweep(n, nnz, P, s_state, s_val):
     return 2 * 2 * P * n * s_state + M
 
 
+PROFILE = {"pedigree": "profiles/k_sweep_pedigree_n100000_P4096_f32.md",
+           "lattice": "profiles/k_sweep_lattice16_P1024_c64.md"}
+KERNEL_SOURCES = ("sweep.hip", "sweep.h", "device_common.h")
+
+
+def profiled_traffic(workload):
+    """HBM bytes per sweep-kernel launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when the
+    kernel sources changed since those counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, PROFILE[workload])
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_cs_0412107_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    vals = {}
+    for line in open(path):
+        parts = line.strip().split(": ")
+        if len(parts) == 2 and parts[0] in ("traffic_bytes_per_launch", "kernel_sources_sha256"):
+            vals[parts[0]] = parts[1]
+    if vals.get("kernel_sources_sha256") != h.hexdigest():
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(m, seed, P, G, budget_s):
     """The oracle (single-threaded C, fp64) on a bounded sample of the same
     workload: a few chain pairs, as many sweeps as fit the time budget."""
@@ -57,11 +84,14 @@ def cpu_baseline(m, seed, P, G, budget_s):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", choices=["pedigree", "lattice"], default="pedigree")
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-1%% phase")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (scale for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the chain pairs would "
@@ -74,13 +104,22 @@ def main():
     import gen
     import paper_cs_0412107_amd as pkg
 
-    w = gen.WORKLOADS["pedigree"]
-    n, P, G, seed = w["n"], w["pairs"], w["groups"], w["noise_seed"]
-    m = gen.round_values(gen.pedigree(n, seed=w["seed"]), np.float32)
-    blk = np.arange(n - w["block"], n)
+    w = gen.WORKLOADS[args.workload]
+    P, G, seed, dtype = w["pairs"], w["groups"], w["noise_seed"], w["dtype"]
+    if args.workload == "pedigree":
+        m = gen.round_values(gen.pedigree(w["n"], seed=w["seed"]), np.float32)
+        desc = f"pedigree n={m.n} nnz={m.nnz}, {P} chain pairs in {G} groups, fp32 sweeps, " \
+               f"diag + {w['block']}x{w['block']} block + trace"
+    else:
+        m = gen.round_values(gen.lattice(w["L"], k=w["k"], seed=w["seed"]), np.complex64)
+        desc = f"random-phase lattice {w['L']}^4 (n={m.n}, nnz={m.nnz}), {P} chain pairs in {G} groups, " \
+               f"complex64 sweeps, diag + trace"
+    n = m.n
+    s_elem = {"f32": 4, "c64": 8}[dtype]
+    blk = np.arange(n - w["block"], n) if "block" in w else None
     torch.cuda.set_device(0)
 
-    s = pkg.Sampler(m, pairs=P, groups=G, dtype="f32", seed=seed, use_torch_stream=True, profile=True)
+    s = pkg.Sampler(m, pairs=P, groups=G, dtype=dtype, seed=seed, use_torch_stream=True, profile=True)
     info0 = s.info()
     s.burn_in(w["burn_in"])
     s.request(diag=True, trace=True, block_rows=blk, block_cols=blk)
@@ -100,10 +139,12 @@ def main():
     K = args.steps
     ups = 2.0 * m.nnz * P * K / (ms / 1e3)
 
-    B = algorithmic_bytes_per_sweep(n, m.nnz, P, 4, 4)
+    B = algorithmic_bytes_per_sweep(n, m.nnz, P, s_elem, s_elem)
     sweep_ms = info["sweep_kernel_ms"] / K
-    achieved = B / (sweep_ms / 1e3) / 1e9
     launches = info["sweep_kernel_launches"] / K
+    # per launch: algorithmic bytes of an average colour launch over its
+    # average duration (the same ratio as per sweep)
+    achieved = (B / launches) / (sweep_ms / launches / 1e3) / 1e9
     d, se = s.diag()
     rel = se / np.abs(d)
     s.close()
@@ -119,16 +160,18 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": f"pedigree n={n} nnz={m.nnz}, {P} chain pairs in {G} groups, fp32 sweeps, "
-                               f"diag + {w['block']}x{w['block']} block + trace",
+        "config": {"workload": desc,
                    "n": n, "nnz": int(m.nnz), "pairs": P, "groups": G, "colors": info0["n_colors"],
-                   "step": "one sampling sweep (all colours, fused diag/trace moments, trace reduction, "
-                           "block moments)"},
+                   "step": "one sampling sweep (all colours, fused diag/trace moments, trace reduction"
+                           + (", block moments)" if blk is not None else ")")},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_sweep<float, sample> (all colour launches of one sweep)",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(args.workload),
+                     "algorithmic_bytes_per_launch": B / launches,
+                     "avg_launch_ms": sweep_ms / launches,
+                     "kernel": f"k_sweep<{'float' if dtype == 'f32' else 'Cx<float>'}, true> "
+                               "(all colour launches of one sweep)",
                      "algorithmic_bytes_per_sweep": B, "sweep_kernel_ms": sweep_ms,
                      "launches_per_sweep": launches},
         "moments_ms_per_step": info["moment_kernel_ms"] / K,
@@ -138,7 +181,7 @@ def main():
     }
 
     if not args.no_ttt:
-        s2 = pkg.Sampler(m, pairs=P, groups=G, dtype="f32", seed=seed + 1, use_torch_stream=True)
+        s2 = pkg.Sampler(m, pairs=P, groups=G, dtype=dtype, seed=seed + 1, use_torch_stream=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         s2.burn_in(w["burn_in"])
@@ -148,7 +191,24 @@ def main():
         tt = time.perf_counter() - t0
         s2.close()
         result["time_to_1pct"] = {"seconds": tt, "burn_in": w["burn_in"], "sample_sweeps": done,
-                                  "max_rel_se": ach, "form": "plain fp32, fixed burn-in"}
+                                  "max_rel_se": ach, "form": f"plain {dtype}, fixed burn-in"}
+
+    if args.copy_calibration:
+        nbytes = 1 << 30
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        c0 = torch.cuda.Event(enable_timing=True)
+        c1 = torch.cuda.Event(enable_timing=True)
+        c0.record()
+        dst.copy_(src)
+        c1.record()
+        torch.cuda.synchronize()
+        cms = c0.elapsed_time(c1)
+        result["copy_calibration"] = {"bytes_read": nbytes, "bytes_written": nbytes, "ms": cms,
+                                      "GBps": 2 * nbytes / (cms / 1e3) / 1e9}
+        del src, dst
 
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_baseline(m, seed, P, G, args.cpu_budget)

@@ -90,14 +90,15 @@ typedef struct {
     int32_t  moments;      /* MCINV_MOMENTS_*                                        */
     int32_t  noise;        /* MCINV_NOISE_*                                          */
     int64_t  n_pairs;      /* P >= 1 independent (z, w) chain pairs                  */
-    int32_t  n_groups;     /* G >= 1 chain groups for error estimates; P % G == 0 and
-                              P/G is 1 (only with G == P... see below), a power of two
-                              >= 4 up to 256, or a multiple of 256; G == 1 always ok  */
+    int32_t  n_groups;     /* G >= 1 chain groups for error estimates; P % G == 0, and
+                              for G > 1 the group size P/G is a power of two in
+                              [4, 256] or a multiple of 256                           */
     uint32_t stream_id;    /* fourth Philox counter word (distinct problems)        */
     uint64_t seed;         /* Philox key                                             */
     void*    stream;       /* hipStream_t to launch on, or NULL for a library stream */
     int32_t  profile;      /* nonzero: time every sweep launch with HIP events       */
-    int32_t  reserved;
+    int32_t  pass_tiles;   /* 256-pair tiles swept through all colours before the
+                              next tiles start (cache residency); 0 = automatic   */
 } mcinv_config;
 
 typedef struct {

@@ -52,7 +52,7 @@ class mcinv_config(ctypes.Structure):
         ("seed", ctypes.c_uint64),
         ("stream", ctypes.c_void_p),
         ("profile", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("pass_tiles", ctypes.c_int32),
     ]
 
 
@@ -133,9 +133,9 @@ def mcinv_last_error(ctx=None):
 
 
 def mcinv_create(device=0, sweep_dtype=MCINV_R32, moments=MCINV_MOMENTS_FP64, noise=MCINV_NOISE_NORMAL,
-                 n_pairs=1, n_groups=1, stream_id=0, seed=0, stream=None, profile=False):
+                 n_pairs=1, n_groups=1, stream_id=0, seed=0, stream=None, profile=False, pass_tiles=0):
     cfg = mcinv_config(device, sweep_dtype, moments, noise, n_pairs, n_groups, stream_id,
-                       seed & 0xFFFFFFFFFFFFFFFF, stream, 1 if profile else 0, 0)
+                       seed & 0xFFFFFFFFFFFFFFFF, stream, 1 if profile else 0, int(pass_tiles))
     h = ctypes.c_void_p()
     _check(None, lib().mcinv_create(ctypes.byref(cfg), ctypes.byref(h)))
     return h

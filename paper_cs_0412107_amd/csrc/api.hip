@@ -35,6 +35,7 @@ namespace {
 thread_local std::string g_error;
 
 constexpr int64_t kSlotsSmallG = 64;     // time batches when there are < 16 groups
+constexpr int64_t kSmallLaunchRows = 4096;  // a colour launch below this many row-waves is "small"
 constexpr double kGuardThreshold = 1e30;
 
 }  // namespace
@@ -47,7 +48,8 @@ struct mcinv_ctx {
     size_t elem = 0;
     int comps = 1;
 
-    int64_t P = 0, ld = 0, G = 1, gs = 1, lg_shift = 6, A = 1, ntiles = 1, pairs_per_col = 256;
+    int64_t P = 0, ld = 0, G = 1, gs = 1, lg_shift = 6, A = 1, cpt = 1, ntiles = 1, pairs_per_col = 256;
+    int64_t pass_tiles = 1;   // pair tiles per pass (all colours of a pass before the next)
 
     // matrix
     bool loaded = false;
@@ -101,7 +103,7 @@ struct mcinv_ctx {
 
     std::string err;
 
-    int64_t diag_slot_stride() const { return n * A * comps; }
+    int64_t diag_slot_stride() const { return ntiles * n * cpt * comps; }
     int64_t block_slot_stride() const { return G * nI * nJ * comps; }
     int64_t entry_slot_stride() const { return G * ne * comps; }
 };
@@ -303,7 +305,7 @@ mcinv_status run_sweeps(mcinv_ctx* c, int64_t nsw, bool sample, V* z, V* w, int6
     a.stream = c->cfg.stream_id;
     a.noise = noise;
     a.lg_shift = (int32_t)c->lg_shift;
-    a.A = c->A;
+    a.n = c->n;
     a.flag = flag;
     a.thresh = (typename Real<V>::type)kGuardThreshold;
 
@@ -325,11 +327,31 @@ mcinv_status run_sweeps(mcinv_ctx* c, int64_t nsw, bool sample, V* z, V* w, int6
             e1 = take_event(c, next_ev);
             if (e0) HIP_TRY(c, hipEventRecord(e0, c->stream));
         }
-        for (int32_t col = 0; col < c->ncolors; ++col) {
+        // Passes over groups of pair tiles: within a pass every colour runs for
+        // the pass's tiles, so their state slices stay cache-resident across
+        // colours.  Trailing small colours (too few rows to fill a launch for
+        // one pass) run once over all tiles after the passes; per tile the
+        // colour order is unchanged.
+        const int64_t T = (ld + kPairsPerWave - 1) / kPairsPerWave;
+        const int64_t pt = use_counters ? std::min<int64_t>(std::max<int64_t>(c->pass_tiles, 1), T) : T;
+        int32_t cs = c->ncolors;
+        while (cs > 0 && (c->color_ptr[cs] - c->color_ptr[cs - 1]) * pt < kSmallLaunchRows) --cs;
+        if (pt >= T) cs = c->ncolors;
+        for (int64_t t0 = 0; t0 < T; t0 += pt) {
+            for (int32_t col = 0; col < cs; ++col) {
+                a.row_begin = c->color_ptr[col];
+                a.row_end = c->color_ptr[col + 1];
+                a.tile0 = t0;
+                a.tpart = want_trace ? c->d_tpart + c->tpart_off[col] * c->comps : nullptr;
+                HIP_TRY(c, launch_sweep<V>(a, std::min(pt, T - t0), sample, c->stream));
+            }
+        }
+        for (int32_t col = cs; col < c->ncolors; ++col) {
             a.row_begin = c->color_ptr[col];
             a.row_end = c->color_ptr[col + 1];
+            a.tile0 = 0;
             a.tpart = want_trace ? c->d_tpart + c->tpart_off[col] * c->comps : nullptr;
-            HIP_TRY(c, launch_sweep<V>(a, sample, c->stream));
+            HIP_TRY(c, launch_sweep<V>(a, T, sample, c->stream));
         }
         if (prof && e1) {
             HIP_TRY(c, hipEventRecord(e1, c->stream));
@@ -451,6 +473,7 @@ mcinv_status finalize_diag(mcinv_ctx* c, bool want_max)
     f.gs = c->gs;
     f.M = c->n;
     f.A = c->A;
+    f.cpt = c->cpt;
     f.pairs_per_col = c->pairs_per_col;
     f.comps = c->comps;
     f.out_index = c->d_perm;
@@ -542,8 +565,9 @@ mcinv_status mcinv_create(const mcinv_config* cfg, mcinv_ctx** out)
     while ((int64_t)1 << sh < lanes) ++sh;
     c->lg_shift = sh;
     c->pairs_per_col = lanes * kPairsPerLane;
-    c->A = (c->ld + c->pairs_per_col - 1) / c->pairs_per_col;
     c->ntiles = (c->ld + kPairsPerWave - 1) / kPairsPerWave;
+    c->cpt = kWave / lanes;
+    c->A = c->ntiles * c->cpt;
     c->nslots = G >= 16 ? 1 : kSlotsSmallG;
     c->slot_len.assign(c->nslots, 0.0);
 
@@ -736,6 +760,10 @@ mcinv_status mcinv_load_csr(mcinv_ctx* c, int64_t n, int64_t nnz, const int64_t*
         c->tpart_off[k + 1] = c->tpart_off[k] + (rows + 3) / 4 * c->ntiles;
     }
     c->npart = c->tpart_off[ncolors];
+    // One pass over all tiles unless asked otherwise: on the pedigree and lattice
+    // workloads, passes of one tile (a ~200 MB slice that could stay in the
+    // Infinity Cache) measured slower than one launch per colour over all tiles.
+    c->pass_tiles = c->cfg.pass_tiles > 0 ? c->cfg.pass_tiles : c->ntiles;
 
     mcinv_status s;
     switch (c->cfg.sweep_dtype) {

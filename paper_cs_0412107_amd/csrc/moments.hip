@@ -252,11 +252,12 @@ __global__ __launch_bounds__(64) void k_finalize_diag(const FinalizeArgs f)
         const int64_t b = c / f.G, g = c % f.G;
         const double wt = f.slot_len[b] * (double)f.gs;
         if (wt <= 0.0) continue;
-        const double* row = f.acc + b * f.slot_stride + q * f.A * f.comps;
+        const double* slot = f.acc + b * f.slot_stride;
         double sr = 0.0, si = 0.0;
         for (int64_t k = g * cols_per_group; k < (g + 1) * cols_per_group && k < f.A; ++k) {
-            sr += row[k * f.comps];
-            if (f.comps == 2) si += row[k * 2 + 1];
+            const double* v = slot + (((k / f.cpt) * f.M + q) * f.cpt + k % f.cpt) * f.comps;
+            sr += v[0];
+            if (f.comps == 2) si += v[1];
         }
         wsum += wt;
         er += sr;
@@ -278,11 +279,12 @@ __global__ __launch_bounds__(64) void k_finalize_diag(const FinalizeArgs f)
         const int64_t b = c / f.G, g = c % f.G;
         const double wt = f.slot_len[b] * (double)f.gs;
         if (wt <= 0.0) continue;
-        const double* row = f.acc + b * f.slot_stride + q * f.A * f.comps;
+        const double* slot = f.acc + b * f.slot_stride;
         double sr = 0.0, si = 0.0;
         for (int64_t k = g * cols_per_group; k < (g + 1) * cols_per_group && k < f.A; ++k) {
-            sr += row[k * f.comps];
-            if (f.comps == 2) si += row[k * 2 + 1];
+            const double* v = slot + (((k / f.cpt) * f.M + q) * f.cpt + k % f.cpt) * f.comps;
+            sr += v[0];
+            if (f.comps == 2) si += v[1];
         }
         const double dr = sr - wt * er;
         vr += dr * dr;

@@ -20,20 +20,22 @@ struct SweepArgs {
     int64_t ld;              // padded pairs per state row (multiple of 4)
     int64_t P;               // real pairs (pairs >= P are padding)
     int64_t row_begin, row_end;
+    int64_t tile0;           // first pair tile of this launch (blockIdx.y offset)
+    int64_t n;               // rows (positions) of the matrix
     uint32_t key0, key1;     // Philox key = seed
     uint32_t sweep;          // Philox counter word 1
     uint32_t stream;         // Philox counter word 3
     int32_t noise;           // NoiseKind
     int32_t lg_shift;        // log2(lanes summed into one diagonal column)
-    int64_t A;               // diagonal columns per row
-    double* diag;            // slot accumulator [n][A] (x2 for complex) or null
+    double* diag;            // slot accumulator [tiles][n][64 >> lg_shift] (x2 complex) or null
     double* tpart;           // per-workgroup trace partials of this launch, or null
     int32_t* flag;           // divergence flag (bit 0)
     typename Real<V>::type thresh;
 };
 
+// Launch over pair tiles [a.tile0, a.tile0 + ntiles).
 template <typename V>
-hipError_t launch_sweep(const SweepArgs<V>& a, bool sample, hipStream_t stream);
+hipError_t launch_sweep(const SweepArgs<V>& a, int64_t ntiles, bool sample, hipStream_t stream);
 
 hipError_t launch_noise_values(bool fp64, uint64_t seed, uint32_t stream_id, int32_t kind, int64_t count,
                                const int64_t* row, const int64_t* sweep, const int64_t* pair, double* out,
@@ -73,14 +75,15 @@ hipError_t launch_reduce_sum(const double* x, int64_t count, int comps, double* 
 // Cluster finalisation.  Clusters are (slot b, group g); slot b holds
 // slot_len[b] samples, each group gs pairs.
 struct FinalizeArgs {
-    const double* acc;       // diag: [nslots][n][A]; flat: [nslots][G][M]  (x comps)
+    const double* acc;       // diag: [nslots][tiles][n][cpt]; flat: [nslots][G][M]  (x comps)
     int64_t nslots;
     int64_t slot_stride;     // doubles per slot
     const double* slot_len;  // samples per slot
     int64_t G;
     int64_t gs;
     int64_t M;               // values (positions or flat entries)
-    int64_t A;               // diag only: columns per row
+    int64_t A;               // diag only: columns (tiles x cpt)
+    int64_t cpt;             // diag only: columns per pair tile
     int64_t pairs_per_col;   // diag only
     int comps;               // 1 real, 2 complex
     const int64_t* out_index;  // diag only: position -> original row

@@ -12,9 +12,25 @@
 // are wave-uniform and arrive through scalar loads; each neighbour costs one
 // coalesced 1-4 KiB segment of z and of w.  One Philox block per lane gives
 // the lane's four noise values.  A 256-thread workgroup holds four rows of
-// one 256-pair tile; grid = (row blocks of the colour) x (pair tiles).
+// one 256-pair tile; grid = (row blocks of the colour) x (pair tiles of this
+// launch).  The host may split a sweep into passes over groups of tiles so a
+// tile's state stays cache-resident across the colours of the pass.
 #include "device_common.h"
 #include "sweep.h"
+
+// Tuning knobs (compile time).
+#ifndef MCINV_XCD_REMAP
+#define MCINV_XCD_REMAP 0        // contiguous (tile, row block) ranges per XCD
+#endif
+#ifndef MCINV_GATHER_U4
+#define MCINV_GATHER_U4 4        // neighbours per gather chunk, 4-byte state
+#endif
+#ifndef MCINV_GATHER_U8
+#define MCINV_GATHER_U8 2        // 8-byte state (fp64, complex64)
+#endif
+#ifndef MCINV_GATHER_U16
+#define MCINV_GATHER_U16 1       // 16-byte state (complex128)
+#endif
 
 namespace mcinv {
 
@@ -58,8 +74,20 @@ __global__ __launch_bounds__(256) void k_sweep(const SweepArgs<V> a)
 
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t q = a.row_begin + (int64_t)blockIdx.x * 4 + wid;
-    const int64_t p0 = (int64_t)blockIdx.y * kPairsPerWave + lane * kPairsPerLane;
+#if MCINV_XCD_REMAP
+    // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs, so give
+    // XCD x one contiguous range of (tile, row block) indices of this launch.
+    const uint32_t total = gridDim.x * gridDim.y;
+    const uint32_t lin = blockIdx.x + gridDim.x * blockIdx.y;
+    const uint32_t xcd = lin % 8u, idx = lin / 8u, per = total / 8u, extra = total % 8u;
+    const uint32_t remap = xcd * per + (xcd < extra ? xcd : extra) + idx;
+    const uint32_t bx = remap % gridDim.x, by = remap / gridDim.x;
+#else
+    const uint32_t bx = blockIdx.x, by = blockIdx.y;
+#endif
+    const int64_t tile = a.tile0 + by;
+    const int64_t q = a.row_begin + (int64_t)bx * 4 + wid;
+    const int64_t p0 = tile * kPairsPerWave + lane * kPairsPerLane;
     const bool row_ok = q < a.row_end;
     const bool active = p0 < a.ld;
     double tre = 0.0, tim = 0.0;
@@ -73,7 +101,7 @@ __global__ __launch_bounds__(256) void k_sweep(const SweepArgs<V> a)
         // Gather in chunks of U neighbours: all 2U state loads of a chunk are
         // issued before the first multiply (memory-level parallelism per wave).
         // A chunk's unused slots reload entry 0 with zero coefficients.
-        constexpr int U = sizeof(V) >= 16 ? 1 : (sizeof(V) >= 8 ? 2 : 4);
+        constexpr int U = sizeof(V) >= 16 ? MCINV_GATHER_U16 : (sizeof(V) >= 8 ? MCINV_GATHER_U8 : MCINV_GATHER_U4);
         if (active) {
             const Entry<V>* e = a.ent + rr.begin;
             const int cnt = rr.count;
@@ -133,13 +161,14 @@ __global__ __launch_bounds__(256) void k_sweep(const SweepArgs<V> a)
                 if constexpr (CPLX) tim += __shfl_xor(tim, off);
             }
             if (a.diag != nullptr && active && (lane & (lg - 1)) == 0) {
-                const int64_t col = p0 >> (2 + a.lg_shift);
+                const int cpt = kWave >> a.lg_shift;
+                const int64_t at = (tile * a.n + q) * cpt + (lane >> a.lg_shift);
                 if constexpr (CPLX) {
-                    double* d = a.diag + 2 * (q * a.A + col);
+                    double* d = a.diag + 2 * at;
                     d[0] += tre;
                     d[1] += tim;
                 } else {
-                    a.diag[q * a.A + col] += tre;
+                    a.diag[at] += tre;
                 }
             }
             for (int off = lg; off < kWave; off <<= 1) {
@@ -157,7 +186,7 @@ __global__ __launch_bounds__(256) void k_sweep(const SweepArgs<V> a)
             }
             __syncthreads();
             if (threadIdx.x == 0) {
-                const int64_t slot = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+                const int64_t slot = tile * gridDim.x + bx;
                 const double r = ((lds_tr[0][0] + lds_tr[1][0]) + lds_tr[2][0]) + lds_tr[3][0];
                 if constexpr (CPLX) {
                     const double i = ((lds_tr[0][1] + lds_tr[1][1]) + lds_tr[2][1]) + lds_tr[3][1];
@@ -172,11 +201,11 @@ __global__ __launch_bounds__(256) void k_sweep(const SweepArgs<V> a)
 }
 
 template <typename V>
-hipError_t launch_sweep(const SweepArgs<V>& a, bool sample, hipStream_t stream)
+hipError_t launch_sweep(const SweepArgs<V>& a, int64_t ntiles, bool sample, hipStream_t stream)
 {
     const int64_t rows = a.row_end - a.row_begin;
-    if (rows <= 0) return hipSuccess;
-    const dim3 grid((unsigned)((rows + 3) / 4), (unsigned)((a.ld + kPairsPerWave - 1) / kPairsPerWave));
+    if (rows <= 0 || ntiles <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((rows + 3) / 4), (unsigned)ntiles);
     if (sample)
         k_sweep<V, true><<<grid, dim3(256), 0, stream>>>(a);
     else
@@ -184,10 +213,10 @@ hipError_t launch_sweep(const SweepArgs<V>& a, bool sample, hipStream_t stream)
     return hipGetLastError();
 }
 
-template hipError_t launch_sweep<float>(const SweepArgs<float>&, bool, hipStream_t);
-template hipError_t launch_sweep<double>(const SweepArgs<double>&, bool, hipStream_t);
-template hipError_t launch_sweep<Cx<float>>(const SweepArgs<Cx<float>>&, bool, hipStream_t);
-template hipError_t launch_sweep<Cx<double>>(const SweepArgs<Cx<double>>&, bool, hipStream_t);
+template hipError_t launch_sweep<float>(const SweepArgs<float>&, int64_t, bool, hipStream_t);
+template hipError_t launch_sweep<double>(const SweepArgs<double>&, int64_t, bool, hipStream_t);
+template hipError_t launch_sweep<Cx<float>>(const SweepArgs<Cx<float>>&, int64_t, bool, hipStream_t);
+template hipError_t launch_sweep<Cx<double>>(const SweepArgs<Cx<double>>&, int64_t, bool, hipStream_t);
 
 // --------------------------------------------------------------------------
 // Noise values for given (row, sweep, pair) triples, as the sweep draws them.
