@@ -201,6 +201,86 @@ mcinv_status mcinv_noise_values(int32_t device, uint64_t seed, uint32_t stream_i
  * had no context, when ctx is NULL). */
 const char* mcinv_last_error(const mcinv_ctx* ctx);
 
+/* ------------------------------------------------------------------------ */
+/* Batched form: many real matrices of uneven order, each with its own n_pairs
+ * chain pairs (fp32 sweeps, eqs 4-5), all swept by ONE persistent kernel per
+ * call (replayed from a captured HIP graph).  Matrix m is prepared exactly as
+ * a single-matrix context would prepare it and draws its noise with
+ * stream_id = m, so its chains are bit-identical to a single-matrix context
+ * with the same seed and stream_id = m.  Moments: the diagonal (fp64 sums,
+ * groups as in a single context) and one dense block per matrix whose
+ * products run on the matrix cores as bf16x3 (hi*hi + hi*lo + lo*hi, fp32
+ * accumulation over the pairs, fp64 sums); block standard errors come from 16
+ * time batches of length ceil(expected_samples / 16).                        */
+typedef struct mcinv_batch mcinv_batch;
+
+typedef struct {
+    int32_t  device;
+    int32_t  noise;          /* MCINV_NOISE_*                                    */
+    int64_t  n_pairs;        /* P per matrix: 16, 32, 64, 128 or 256             */
+    int32_t  n_groups;       /* G: P/G a power of two >= 4                       */
+    int32_t  rows_per_item;  /* rows per work item (0: 64; see autotune)         */
+    int32_t  grab;           /* work items taken per queue access (0: 4)         */
+    int32_t  reserved;
+    uint64_t seed;           /* Philox key (shared by all matrices)             */
+    void*    stream;         /* hipStream_t or NULL for a library stream         */
+} mcinv_batch_config;
+
+typedef struct {
+    int64_t n_matrices, n_rows, nnz, n_pairs;
+    int32_t n_groups, max_colors, rows_per_item, grab, grid, reserved;
+    int64_t items_per_sweep, sweeps_done, samples_done;
+    double  last_call_ms;    /* device time of the last burn_in / sample call   */
+} mcinv_batch_info;
+
+/* Create an empty batch of n_matrices matrices.  EINVAL on a bad layout. */
+mcinv_status mcinv_batch_create(const mcinv_batch_config* cfg, int64_t n_matrices, mcinv_batch** out);
+void mcinv_batch_destroy(mcinv_batch* b);
+
+/* Load matrix m (real, float64 values; CSR rules as mcinv_load_csr).  All
+ * matrices must be loaded before the first other call; the batch is then
+ * fixed.  ESINGULAR / EINVAL as mcinv_load_csr. */
+mcinv_status mcinv_batch_load_csr(mcinv_batch* b, int64_t m, int64_t n, int64_t nnz, const int64_t* row_ptr,
+                                  const int32_t* col_idx, const double* values);
+
+/* flags: MCINV_REQ_DIAG and/or MCINV_REQ_BLOCK.  block_dim (1..128): each
+ * matrix's block is its last block_dim rows x columns unless set with
+ * mcinv_batch_set_block.  expected_samples sets the block time-batch length.
+ * Clears the moments and the sample count. */
+mcinv_status mcinv_batch_set_requested(mcinv_batch* b, uint32_t flags, int32_t block_dim, int64_t expected_samples);
+
+/* Block rows and columns of matrix m (block_dim original indices each). */
+mcinv_status mcinv_batch_set_block(mcinv_batch* b, int64_t m, const int64_t* rows, const int64_t* cols);
+
+/* Burn-in / sampling sweeps of every matrix (one persistent launch per call,
+ * split only beyond 2^30 work items).  EDIVERGED as mcinv_burn_in; EDEVICE if
+ * a dependency wait inside the launch exceeded its bound. */
+mcinv_status mcinv_batch_burn_in(mcinv_batch* b, int64_t sweeps);
+mcinv_status mcinv_batch_sample(mcinv_batch* b, int64_t sweeps);
+
+/* Sample in chunks until max over all matrices and rows of SE/|est| of the
+ * diagonal is <= rel_se (or max_sweeps). */
+mcinv_status mcinv_batch_sample_until(mcinv_batch* b, double rel_se, int64_t max_sweeps, int64_t check_every,
+                                      int64_t* sweeps_done, double* achieved);
+
+/* Estimates of matrix m: MCINV_REQ_DIAG (n values, original order) or
+ * MCINV_REQ_BLOCK (block_dim^2, row-major); est and stderr_ as
+ * mcinv_read_estimates (real). */
+mcinv_status mcinv_batch_read_estimates(mcinv_batch* b, int64_t m, uint32_t quantity, double* est,
+                                        double* stderr_, int64_t capacity);
+
+/* Chain state of matrix m, [n][P] fp32, original row order. */
+mcinv_status mcinv_batch_read_state(mcinv_batch* b, int64_t m, int32_t which, float* host, int64_t bytes);
+
+/* Time every (rows per item, items per grab) candidate on sweeps_per_trial
+ * burn-in sweeps (plus one warm-up each; the chains advance as in burn-in)
+ * and keep the fastest. */
+mcinv_status mcinv_batch_autotune(mcinv_batch* b, int32_t sweeps_per_trial, int32_t* rows_per_item, int32_t* grab,
+                                  double* ms_per_sweep);
+
+mcinv_status mcinv_batch_get_info(mcinv_batch* b, mcinv_batch_info* out);
+const char* mcinv_batch_last_error(const mcinv_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

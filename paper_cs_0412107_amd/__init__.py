@@ -14,7 +14,12 @@ from ._binding import (DTYPES, MCINV_MOMENTS_BF16X3, MCINV_MOMENTS_FP64, MCINV_N
                        mcinv_reset_profile, mcinv_sample, mcinv_sample_until, mcinv_set_requested,
                        mcinv_write_state)
 
-__all__ = ["Sampler", "McinvError", "lib"]
+from ._binding import (mcinv_batch_autotune, mcinv_batch_burn_in, mcinv_batch_create, mcinv_batch_destroy,
+                       mcinv_batch_get_info, mcinv_batch_load_csr, mcinv_batch_read_estimates,
+                       mcinv_batch_read_state, mcinv_batch_sample, mcinv_batch_sample_until,
+                       mcinv_batch_set_block, mcinv_batch_set_requested)
+
+__all__ = ["Sampler", "BatchSampler", "McinvError", "lib"]
 
 
 def torch_stream():
@@ -117,3 +122,70 @@ class Sampler:
 
     def reset_profile(self):
         mcinv_reset_profile(self.ctx)
+
+
+class BatchSampler:
+    """The batched form: many real matrices, ``pairs`` chain pairs each, fp32
+    sweeps in one persistent launch per call."""
+
+    def __init__(self, matrices, pairs=64, groups=16, seed=0, noise=MCINV_NOISE_NORMAL, device=0,
+                 rows_per_item=0, grab=0, use_torch_stream=False):
+        stream = torch_stream() if use_torch_stream else None
+        self.b = mcinv_batch_create(len(matrices), device=device, noise=noise, n_pairs=pairs, n_groups=groups,
+                                    rows_per_item=rows_per_item, grab=grab, seed=seed, stream=stream)
+        self.n = [m.n for m in matrices]
+        self.P = pairs
+        self.bdim = 0
+        try:
+            for j, m in enumerate(matrices):
+                mcinv_batch_load_csr(self.b, j, m.n, m.nnz, m.row_ptr, m.col, m.val)
+        except Exception:
+            self.close()
+            raise
+
+    def close(self):
+        if getattr(self, "b", None) is not None:
+            mcinv_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def request(self, diag=True, block_dim=0, expected_samples=1):
+        flags = (MCINV_REQ_DIAG if diag else 0) | (MCINV_REQ_BLOCK if block_dim > 0 else 0)
+        self.bdim = block_dim
+        mcinv_batch_set_requested(self.b, flags, block_dim, expected_samples)
+
+    def set_block(self, m, rows, cols):
+        mcinv_batch_set_block(self.b, m, rows, cols)
+
+    def burn_in(self, sweeps):
+        mcinv_batch_burn_in(self.b, sweeps)
+
+    def sample(self, sweeps):
+        mcinv_batch_sample(self.b, sweeps)
+
+    def sample_until(self, rel_se, max_sweeps, check_every=10):
+        return mcinv_batch_sample_until(self.b, rel_se, max_sweeps, check_every)
+
+    def diag(self, m):
+        return mcinv_batch_read_estimates(self.b, m, MCINV_REQ_DIAG, self.n[m])
+
+    def block(self, m):
+        est, se = mcinv_batch_read_estimates(self.b, m, MCINV_REQ_BLOCK, self.bdim * self.bdim)
+        return est.reshape(self.bdim, self.bdim), se.reshape(self.bdim, self.bdim)
+
+    def state(self, m, which):
+        return mcinv_batch_read_state(self.b, m, which, self.n[m], self.P)
+
+    def autotune(self, sweeps_per_trial=2):
+        return mcinv_batch_autotune(self.b, sweeps_per_trial)
+
+    def info(self):
+        return mcinv_batch_get_info(self.b)

@@ -71,6 +71,34 @@ class mcinv_info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class mcinv_batch_config(ctypes.Structure):
+    _fields_ = [
+        ("device", ctypes.c_int32),
+        ("noise", ctypes.c_int32),
+        ("n_pairs", ctypes.c_int64),
+        ("n_groups", ctypes.c_int32),
+        ("rows_per_item", ctypes.c_int32),
+        ("grab", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class mcinv_batch_info(ctypes.Structure):
+    _fields_ = [
+        ("n_matrices", ctypes.c_int64), ("n_rows", ctypes.c_int64), ("nnz", ctypes.c_int64),
+        ("n_pairs", ctypes.c_int64),
+        ("n_groups", ctypes.c_int32), ("max_colors", ctypes.c_int32), ("rows_per_item", ctypes.c_int32),
+        ("grab", ctypes.c_int32), ("grid", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("items_per_sweep", ctypes.c_int64), ("sweeps_done", ctypes.c_int64), ("samples_done", ctypes.c_int64),
+        ("last_call_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 _lib = None
 
 # name -> (restype, argtypes)
@@ -97,6 +125,19 @@ SIGNATURES = {
     "mcinv_reset_profile": (_I32, [_P]),
     "mcinv_noise_values": (_I32, [_I32, _U64, _U32, _I32, _I32, _I64, _P, _P, _P, _P]),
     "mcinv_last_error": (ctypes.c_char_p, [_P]),
+    "mcinv_batch_create": (_I32, [ctypes.POINTER(mcinv_batch_config), _I64, ctypes.POINTER(_P)]),
+    "mcinv_batch_destroy": (None, [_P]),
+    "mcinv_batch_load_csr": (_I32, [_P, _I64, _I64, _I64, _P, _P, _P]),
+    "mcinv_batch_set_requested": (_I32, [_P, _U32, _I32, _I64]),
+    "mcinv_batch_set_block": (_I32, [_P, _I64, _P, _P]),
+    "mcinv_batch_burn_in": (_I32, [_P, _I64]),
+    "mcinv_batch_sample": (_I32, [_P, _I64]),
+    "mcinv_batch_sample_until": (_I32, [_P, _D, _I64, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_D)]),
+    "mcinv_batch_read_estimates": (_I32, [_P, _I64, _U32, _P, _P, _I64]),
+    "mcinv_batch_read_state": (_I32, [_P, _I64, _I32, _P, _I64]),
+    "mcinv_batch_autotune": (_I32, [_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_D)]),
+    "mcinv_batch_get_info": (_I32, [_P, ctypes.POINTER(mcinv_batch_info)]),
+    "mcinv_batch_last_error": (ctypes.c_char_p, [_P]),
 }
 
 
@@ -236,3 +277,90 @@ def mcinv_noise_values(device, seed, stream_id, noise, dtype, row, sweep, pair):
     _check(None, lib().mcinv_noise_values(device, seed & 0xFFFFFFFFFFFFFFFF, stream_id, noise, dtype, r.size,
                                           _ptr(r), _ptr(k), _ptr(p), _ptr(out)))
     return out
+
+
+# ---------------------------------------------------------------- batched --
+def _bcheck(b, status):
+    if status != MCINV_OK:
+        msg = lib().mcinv_batch_last_error(b)
+        raise McinvError(status, msg.decode() if msg else "")
+    return status
+
+
+def mcinv_batch_last_error(b=None):
+    m = lib().mcinv_batch_last_error(b)
+    return m.decode() if m else ""
+
+
+def mcinv_batch_create(n_matrices, device=0, noise=MCINV_NOISE_NORMAL, n_pairs=64, n_groups=16, rows_per_item=0,
+                       grab=0, seed=0, stream=None):
+    cfg = mcinv_batch_config(device, noise, n_pairs, n_groups, rows_per_item, grab, 0, seed & 0xFFFFFFFFFFFFFFFF,
+                             stream)
+    h = ctypes.c_void_p()
+    _bcheck(None, lib().mcinv_batch_create(ctypes.byref(cfg), int(n_matrices), ctypes.byref(h)))
+    return h
+
+
+def mcinv_batch_destroy(b):
+    lib().mcinv_batch_destroy(b)
+
+
+def mcinv_batch_load_csr(b, m, n, nnz, row_ptr, col_idx, values):
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    v = np.ascontiguousarray(values, dtype=np.float64)
+    _bcheck(b, lib().mcinv_batch_load_csr(b, int(m), int(n), int(nnz), _ptr(rp), _ptr(ci), _ptr(v)))
+
+
+def mcinv_batch_set_requested(b, flags, block_dim=0, expected_samples=1):
+    _bcheck(b, lib().mcinv_batch_set_requested(b, flags, int(block_dim), int(expected_samples)))
+
+
+def mcinv_batch_set_block(b, m, rows, cols):
+    r = np.ascontiguousarray(rows, dtype=np.int64)
+    c = np.ascontiguousarray(cols, dtype=np.int64)
+    _bcheck(b, lib().mcinv_batch_set_block(b, int(m), _ptr(r), _ptr(c)))
+
+
+def mcinv_batch_burn_in(b, sweeps):
+    _bcheck(b, lib().mcinv_batch_burn_in(b, int(sweeps)))
+
+
+def mcinv_batch_sample(b, sweeps):
+    _bcheck(b, lib().mcinv_batch_sample(b, int(sweeps)))
+
+
+def mcinv_batch_sample_until(b, rel_se, max_sweeps, check_every):
+    done = ctypes.c_int64(0)
+    ach = ctypes.c_double(0)
+    _bcheck(b, lib().mcinv_batch_sample_until(b, float(rel_se), int(max_sweeps), int(check_every),
+                                              ctypes.byref(done), ctypes.byref(ach)))
+    return done.value, ach.value
+
+
+def mcinv_batch_read_estimates(b, m, quantity, count):
+    est = np.empty(count, dtype=np.float64)
+    se = np.empty(count, dtype=np.float64)
+    _bcheck(b, lib().mcinv_batch_read_estimates(b, int(m), quantity, _ptr(est), _ptr(se), int(count)))
+    return est, se
+
+
+def mcinv_batch_read_state(b, m, which, n, P):
+    out = np.empty((n, P), dtype=np.float32)
+    _bcheck(b, lib().mcinv_batch_read_state(b, int(m), which, _ptr(out), out.nbytes))
+    return out
+
+
+def mcinv_batch_autotune(b, sweeps_per_trial=2):
+    r = ctypes.c_int32(0)
+    g = ctypes.c_int32(0)
+    ms = ctypes.c_double(0)
+    _bcheck(b, lib().mcinv_batch_autotune(b, int(sweeps_per_trial), ctypes.byref(r), ctypes.byref(g),
+                                          ctypes.byref(ms)))
+    return r.value, g.value, ms.value
+
+
+def mcinv_batch_get_info(b):
+    info = mcinv_batch_info()
+    _bcheck(b, lib().mcinv_batch_get_info(b, ctypes.byref(info)))
+    return info.as_dict()

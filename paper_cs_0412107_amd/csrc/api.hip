@@ -25,10 +25,10 @@
 
 #include "../../include/mcinv.h"
 #include "device_common.h"
+#include "prep.h"
 #include "sweep.h"
 
 using namespace mcinv;
-using cd = std::complex<double>;
 
 namespace {
 
@@ -195,25 +195,6 @@ mcinv_status upload(mcinv_ctx* c, T** p, const std::vector<T>& h)
     if (!h.empty()) HIP_TRY(c, hipMemcpyAsync(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
     return MCINV_OK;
 }
-
-// ---------------------------------------------------- precision dispatch --
-template <typename V> V cast_val(cd x);
-template <> float cast_val<float>(cd x) { return (float)x.real(); }
-template <> double cast_val<double>(cd x) { return x.real(); }
-template <> Cx<float> cast_val<Cx<float>>(cd x) { return Cx<float>{(float)x.real(), (float)x.imag()}; }
-template <> Cx<double> cast_val<Cx<double>>(cd x) { return Cx<double>{x.real(), x.imag()}; }
-
-struct MergedEntry {
-    int64_t col;   // position of neighbour
-    cd u, v;
-};
-
-// Host layout of the merged pattern in position order.
-struct Prepared {
-    std::vector<RowRec> rows;
-    std::vector<MergedEntry> ent;
-    std::vector<cd> a, b;
-};
 
 template <typename V>
 mcinv_status upload_matrix(mcinv_ctx* c, const Prepared& h)
@@ -620,139 +601,28 @@ mcinv_status mcinv_load_csr(mcinv_ctx* c, int64_t n, int64_t nnz, const int64_t*
 {
     if (!c) return fail(nullptr, MCINV_EINVAL, "null context");
     MC_TRY(set_device(c));
-    if (n < 1 || n > INT32_MAX || nnz < n || !row_ptr || !col_idx || !values)
-        return fail(c, MCINV_EINVAL, "bad sizes or null arrays");
     if (value_dtype != MCINV_R64 && value_dtype != MCINV_C128)
         return fail(c, MCINV_EINVAL, "values must be float64 (MCINV_R64) or complex128 (MCINV_C128)");
     if (value_dtype == MCINV_C128 && !c->cplx)
         return fail(c, MCINV_EINVAL, "a complex matrix needs a complex sweep dtype");
-    if (row_ptr[0] != 0 || row_ptr[n] != nnz) return fail(c, MCINV_EINVAL, "row_ptr[0] must be 0 and row_ptr[n] nnz");
-    for (int64_t i = 0; i < n; ++i) {
-        if (row_ptr[i + 1] < row_ptr[i]) return fail(c, MCINV_EINVAL, "row_ptr is decreasing");
-        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
-            if (col_idx[e] < 0 || col_idx[e] >= n) return fail(c, MCINV_EINVAL, "column index out of range");
-            if (e > row_ptr[i] && col_idx[e] <= col_idx[e - 1])
-                return fail(c, MCINV_EINVAL, "columns must be strictly increasing within a row");
-        }
-    }
-    const double* vd = (const double*)values;
-    auto val = [&](int64_t e) { return value_dtype == MCINV_C128 ? cd(vd[2 * e], vd[2 * e + 1]) : cd(vd[e], 0.0); };
-
-    // Diagonal and per-row constants (fp64).
-    std::vector<cd> diag(n);
-    for (int64_t i = 0; i < n; ++i) {
-        bool found = false;
-        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
-            if (col_idx[e] == i) {
-                diag[i] = val(e);
-                found = true;
-            }
-        if (!found || diag[i] == cd(0.0, 0.0))
-            return fail(c, MCINV_ESINGULAR, "row " + std::to_string(i) + " has no nonzero diagonal entry");
-    }
-
-    // Transpose: column i lists (row j, c_ji), rows ascending.
-    std::vector<int64_t> tptr(n + 1, 0);
-    for (int64_t e = 0; e < nnz; ++e) tptr[col_idx[e] + 1]++;
-    for (int64_t i = 0; i < n; ++i) tptr[i + 1] += tptr[i];
-    std::vector<int64_t> trow(nnz), tsrc(nnz);
-    {
-        std::vector<int64_t> fill(tptr.begin(), tptr.end() - 1);
-        for (int64_t i = 0; i < n; ++i)
-            for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
-                const int64_t slot = fill[col_idx[e]]++;
-                trow[slot] = i;
-                tsrc[slot] = e;
-            }
-    }
-
-    // Merged off-diagonal pattern per original row: union of row i and column i.
-    std::vector<int64_t> mptr(n + 1, 0);
-    std::vector<int64_t> mcol;
-    std::vector<cd> mu, mv;
-    mcol.reserve(2 * nnz);
-    mu.reserve(2 * nnz);
-    mv.reserve(2 * nnz);
-    for (int64_t i = 0; i < n; ++i) {
-        const cd inv = 1.0 / diag[i];
-        int64_t e = row_ptr[i], t = tptr[i];
-        const int64_t e_end = row_ptr[i + 1], t_end = tptr[i + 1];
-        while (e < e_end || t < t_end) {
-            const int64_t je = e < e_end ? col_idx[e] : INT64_MAX;
-            const int64_t jt = t < t_end ? trow[t] : INT64_MAX;
-            const int64_t j = std::min(je, jt);
-            cd u(0.0, 0.0), v(0.0, 0.0);
-            if (je == j) u = inv * val(e++);
-            if (jt == j) v = std::conj(inv) * std::conj(val(tsrc[t++]));
-            if (j == i) continue;
-            mcol.push_back(j);
-            mu.push_back(u);
-            mv.push_back(v);
-        }
-        mptr[i + 1] = (int64_t)mcol.size();
-    }
-
-    // Greedy first-fit colouring in natural order over the merged pattern.
-    std::vector<int32_t> color(n, 0);
-    std::vector<int64_t> mark(n + 1, -1);
-    int32_t ncolors = 0;
-    for (int64_t i = 0; i < n; ++i) {
-        for (int64_t e = mptr[i]; e < mptr[i + 1]; ++e)
-            if (mcol[e] < i) mark[color[mcol[e]]] = i;
-        int32_t k = 0;
-        while (mark[k] == i) ++k;
-        color[i] = k;
-        ncolors = std::max(ncolors, k + 1);
-    }
-    std::vector<int64_t> color_ptr(ncolors + 1, 0);
-    for (int64_t i = 0; i < n; ++i) color_ptr[color[i] + 1]++;
-    for (int32_t k = 0; k < ncolors; ++k) color_ptr[k + 1] += color_ptr[k];
-    std::vector<int64_t> perm(n), pos(n);
-    {
-        std::vector<int64_t> fill(color_ptr.begin(), color_ptr.end() - 1);
-        for (int64_t i = 0; i < n; ++i) {
-            const int64_t q = fill[color[i]]++;
-            perm[q] = i;
-            pos[i] = q;
-        }
-    }
-
-    // Position-space layout.
     Prepared h;
-    h.rows.resize(n);
-    h.a.resize(n);
-    h.b.resize(n);
-    h.ent.reserve(mcol.size());
+    bool singular = false;
+    const std::string why = prepare_matrix(n, nnz, row_ptr, col_idx, (const double*)values,
+                                           value_dtype == MCINV_C128, h, &singular);
+    if (!why.empty()) return fail(c, singular ? MCINV_ESINGULAR : MCINV_EINVAL, why);
     const bool real_values = value_dtype == MCINV_R64;
-    for (int64_t q = 0; q < n; ++q) {
-        const int64_t i = perm[q];
-        h.rows[q].begin = (int64_t)h.ent.size();
-        h.rows[q].count = (int32_t)(mptr[i + 1] - mptr[i]);
-        h.rows[q].orig = (uint32_t)i;
-        const size_t first = h.ent.size();
-        for (int64_t e = mptr[i]; e < mptr[i + 1]; ++e) h.ent.push_back(MergedEntry{pos[mcol[e]], mu[e], mv[e]});
-        std::sort(h.ent.begin() + first, h.ent.end(),
-                  [](const MergedEntry& x, const MergedEntry& y) { return x.col < y.col; });
-        const cd d = diag[i];
-        if (real_values) {
-            const double s = 1.0 / std::sqrt(std::fabs(d.real()));
-            h.a[q] = cd(s, 0.0);
-            h.b[q] = cd(d.real() > 0 ? s : -s, 0.0);
-        } else {
-            h.a[q] = 1.0 / std::sqrt(d);
-            h.b[q] = std::conj(h.a[q]);
-        }
-    }
+    const int32_t ncolors = h.ncolors;
+    const std::vector<int64_t>& color_ptr = h.color_ptr;
 
     free_matrix(c);
     c->n = n;
     c->nnz = nnz;
     c->n_off = (int64_t)h.ent.size();
     c->ncolors = ncolors;
-    c->perm = perm;
-    c->pos = pos;
-    c->color = color;
-    c->color_ptr = color_ptr;
+    c->perm = h.perm;
+    c->pos = h.pos;
+    c->color = h.color;
+    c->color_ptr = h.color_ptr;
     c->real_values = real_values;
     c->tpart_off.assign(ncolors + 1, 0);
     for (int32_t k = 0; k < ncolors; ++k) {
@@ -773,7 +643,7 @@ mcinv_status mcinv_load_csr(mcinv_ctx* c, int64_t n, int64_t nnz, const int64_t*
     default: s = upload_matrix<Cx<double>>(c, h); break;
     }
     if (s != MCINV_OK) return s;
-    MC_TRY(upload(c, &c->d_perm, perm));
+    MC_TRY(upload(c, &c->d_perm, h.perm));
     const size_t state_bytes = (size_t)n * c->ld * c->elem;
     HIP_TRY(c, hipMalloc(&c->d_z, state_bytes));
     HIP_TRY(c, hipMalloc(&c->d_w, state_bytes));

@@ -305,18 +305,22 @@ __global__ __launch_bounds__(64) void k_finalize_diag(const FinalizeArgs f)
     }
 }
 
-// Flat accumulators [nslots][G][M]: one thread per value.
+// Flat accumulators: value m of group g in slot b at
+// acc[b * slot_stride + (g * gstride + m * mstride) * comps]; one thread per value.
 __global__ __launch_bounds__(64) void k_finalize_flat(const FinalizeArgs f)
 {
-    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= f.M) return;
+    const int64_t m0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m0 >= f.M) return;
+    const int64_t gstride = f.gstride > 0 ? f.gstride : f.M;
+    const int64_t mstride = f.mstride > 0 ? f.mstride : 1;
     const int64_t ncl = f.nslots * f.G;
+    const int64_t m = f.out_index ? f.out_index[m0] : m0;  // output index
     double wsum = 0.0, er = 0.0, ei = 0.0;
     int64_t nc = 0;
     for (int64_t c = 0; c < ncl; ++c) {
         const double wt = f.slot_len[c / f.G] * (double)f.gs;
         if (wt <= 0.0) continue;
-        const double* v = f.acc + (c / f.G) * f.slot_stride + ((c % f.G) * f.M + m) * f.comps;
+        const double* v = f.acc + (c / f.G) * f.slot_stride + ((c % f.G) * gstride + m0 * mstride) * f.comps;
         wsum += wt;
         er += v[0];
         if (f.comps == 2) ei += v[1];
@@ -334,7 +338,7 @@ __global__ __launch_bounds__(64) void k_finalize_flat(const FinalizeArgs f)
     for (int64_t c = 0; c < ncl; ++c) {
         const double wt = f.slot_len[c / f.G] * (double)f.gs;
         if (wt <= 0.0) continue;
-        const double* v = f.acc + (c / f.G) * f.slot_stride + ((c % f.G) * f.M + m) * f.comps;
+        const double* v = f.acc + (c / f.G) * f.slot_stride + ((c % f.G) * gstride + m0 * mstride) * f.comps;
         const double dr = v[0] - wt * er;
         vr += dr * dr;
         if (f.comps == 2) {

@@ -86,7 +86,9 @@ struct FinalizeArgs {
     int64_t cpt;             // diag only: columns per pair tile
     int64_t pairs_per_col;   // diag only
     int comps;               // 1 real, 2 complex
-    const int64_t* out_index;  // diag only: position -> original row
+    const int64_t* out_index;  // position -> output index (diag; optional for flat)
+    int64_t gstride;         // flat only: doubles/comps between groups (0: M)
+    int64_t mstride;         // flat only: between consecutive values (0: 1)
     double* est;             // [M][comps] (at out_index)
     double* se;              // [M]
     unsigned long long* max_rel;  // diag only, may be null: max se/|est| as bits

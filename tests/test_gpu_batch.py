@@ -1,0 +1,152 @@
+"""Batched form on the GPU: many matrices of uneven order in one persistent
+launch must reproduce, bit for bit, the chains of each matrix swept alone by
+the single-matrix path (same seed, stream_id = matrix index), and therefore
+the oracle."""
+
+import numpy as np
+import pytest
+
+import gen
+import oracle
+from gpu_util import oracle_matrix, print_case, rel_err
+
+pytestmark = pytest.mark.gpu
+
+mc = pytest.importorskip("paper_cs_0412107_amd")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+SIZES = [200, 1500, 333, 2900, 64, 800, 1201, 450, 3000, 97, 640, 2048]
+
+
+@pytest.fixture(scope="module")
+def mats():
+    return [gen.round_values(gen.pedigree(int(n), seed=300 + j), np.float32) for j, n in enumerate(SIZES)]
+
+
+def test_batched_states_equal_single_path(mats):
+    print_case(test="batch_states", matrices=len(mats))
+    P, G, seed = 64, 16, 0x412107 + 3
+    with mc.BatchSampler(mats, pairs=P, groups=G, seed=seed, rows_per_item=32, grab=2) as b:
+        b.burn_in(4)
+        for m in (0, 3, 4, 9, 11):
+            with mc.Sampler(mats[m], pairs=P, groups=G, dtype="f32", seed=seed, stream_id=m) as s:
+                s.burn_in(4)
+                for which in (0, 1):
+                    assert np.array_equal(b.state(m, which), s.state(which)), (m, which)
+
+
+def test_batched_matches_oracle(mats):
+    P, G, seed = 64, 16, 11
+    m = 5
+    ora = oracle.Run(mats[m], seed=seed, pairs=P, groups=G, stream=m)
+    with mc.BatchSampler(mats, pairs=P, groups=G, seed=seed) as b:
+        b.burn_in(3)
+        ora.burn_in(3)
+        assert rel_err(b.state(m, 0), ora.z) <= 1e-5
+        assert rel_err(b.state(m, 1), ora.w) <= 1e-5
+
+
+@pytest.mark.parametrize("P,G", [(64, 16), (32, 2), (128, 8)])
+def test_batched_moments_equal_single_path(mats, P, G):
+    print_case(test="batch_moments", P=P, G=G)
+    seed, S, bd = 99, 12, 48
+    with mc.BatchSampler(mats[:6], pairs=P, groups=G, seed=seed, rows_per_item=16, grab=1) as b:
+        b.burn_in(5)
+        b.request(diag=True, block_dim=bd, expected_samples=S)
+        b.sample(S)
+        for m in (1, 3):
+            with mc.Sampler(mats[m], pairs=P, groups=G, dtype="f32", seed=seed, stream_id=m) as s:
+                s.burn_in(5)
+                s.request(diag=True, trace=False)
+                s.sample(S)
+                d, se = s.diag()
+            bd_, bse = b.diag(m)
+            np.testing.assert_allclose(bd_, d, rtol=1e-12, atol=0)
+            if G >= 16:
+                np.testing.assert_allclose(bse, se, rtol=1e-9)
+            # block: the single path with one group and bf16x3 products is the same MFMA sequence
+            n = mats[m].n
+            rows = np.arange(n - bd, n)
+            with mc.Sampler(mats[m], pairs=P, groups=1, dtype="f32", seed=seed, stream_id=m,
+                            moments="bf16x3") as s1:
+                s1.burn_in(5)
+                s1.request(diag=False, trace=False, block_rows=rows, block_cols=rows)
+                s1.sample(S)
+                sb, _ = s1.block()
+            bb, bbse = b.block(m)
+            np.testing.assert_allclose(bb, sb, rtol=1e-12, atol=1e-15)
+            assert np.all(np.isfinite(bbse))
+    # and the block against the fp64 oracle
+    m = 3
+    ora = oracle.Run(mats[m], seed=seed, pairs=P, groups=1, stream=m)
+    ora.burn_in(5)
+    n = mats[m].n
+    rows = np.arange(n - bd, n)
+    ora.request(S, diag=False, block_rows=rows, block_cols=rows, trace=False)
+    ora.sample(S)
+    ob, _ = ora.block()
+    assert rel_err(bb, ob.real) <= 1e-4
+
+
+def test_graph_replays_continue_the_chain(mats):
+    """Three replays of a 3-sweep launch equal one 9-sweep launch."""
+    P, G, seed = 64, 16, 5
+    sub = mats[:5]
+    with mc.BatchSampler(sub, pairs=P, groups=G, seed=seed) as a, \
+            mc.BatchSampler(sub, pairs=P, groups=G, seed=seed) as b:
+        a.burn_in(2)
+        b.burn_in(2)
+        a.request(diag=True, block_dim=32, expected_samples=9)
+        b.request(diag=True, block_dim=32, expected_samples=9)
+        for _ in range(3):
+            a.sample(3)
+        b.sample(9)
+        for m in range(len(sub)):
+            assert np.array_equal(a.state(m, 0), b.state(m, 0))
+            da, _ = a.diag(m)
+            db, _ = b.diag(m)
+            assert np.array_equal(da, db)
+        assert a.info()["samples_done"] == 9
+
+
+def test_autotune_and_sample_until(mats):
+    P, G, seed = 64, 16, 21
+    with mc.BatchSampler(mats, pairs=P, groups=G, seed=seed) as b:
+        r, g, ms = b.autotune(1)
+        assert r in (16, 32, 64, 128, 256) and g in (1, 4, 16) and ms > 0
+        info = b.info()
+        burned = info["sweeps_done"]
+        b.burn_in(30)
+        b.request(diag=True)
+        done, ach = b.sample_until(0.05, 400, 10)
+        assert ach <= 0.05 and done <= 400
+        # the schedule does not change the chain: same state as the single path
+        with mc.Sampler(mats[2], pairs=P, groups=G, dtype="f32", seed=seed, stream_id=2) as s:
+            s.burn_in(burned + 30 + done)
+            assert np.array_equal(b.state(2, 0), s.state(0))
+
+
+def test_batch_errors(mats):
+    with pytest.raises(mc.McinvError) as ei:
+        mc.mcinv_batch_create(2, n_pairs=48)
+    assert ei.value.code == mc.MCINV_EINVAL
+    b = mc.mcinv_batch_create(2, n_pairs=64, n_groups=16)
+    try:
+        m = mats[0]
+        mc.mcinv_batch_load_csr(b, 0, m.n, m.nnz, m.row_ptr, m.col, m.val)
+        with pytest.raises(mc.McinvError) as ei:
+            mc.mcinv_batch_burn_in(b, 1)
+        assert ei.value.code == mc.MCINV_ESTATE
+    finally:
+        mc.mcinv_batch_destroy(b)
+    with mc.BatchSampler(mats[:3], pairs=64, groups=16) as bs:
+        with pytest.raises(mc.McinvError) as ei:
+            bs.request(diag=True, block_dim=129)
+        assert ei.value.code == mc.MCINV_EINVAL
