@@ -29,6 +29,11 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+def log(msg):
+    """Progress on stderr (stdout carries only the JSON line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def algorithmic_bytes_per_sweep(n, nnz, P, s_state, s_val):
     """State streamed once per sweep (z and w, read and written) plus the
     matrix: CSR of C and of C^dagger and three per-row constants."""
@@ -64,6 +69,80 @@ def profiled_traffic(workload):
     return float(vals["traffic_bytes_per_launch"])
 
 
+def time_to_1pct(pkg, torch, m, P, G, seed, dtype, moments, burn_in, rel=0.01, check=10, max_sweeps=20000):
+    """Wall time from a fresh context to max_i SE_i/|est_i| <= rel on the whole
+    diagonal: fixed burn-in, then sampling checked every `check` sweeps."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = pkg.Sampler(m, pairs=P, groups=G, dtype=dtype, seed=seed, moments=moments, use_torch_stream=True)
+    s.burn_in(burn_in)
+    s.request(diag=True, trace=False)
+    done, ach = s.sample_until(rel, max_sweeps, check)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    s.close()
+    return {"seconds": t, "burn_in": burn_in, "sample_sweeps": done, "max_rel_se": ach,
+            "form": f"{dtype} sweeps, {moments} blocks"}
+
+
+def batched_forms(pkg, torch, gen, rel=0.01, check=10):
+    """Batched workload: 512 pedigree matrices, n log-uniform in [1e3, 5e4],
+    64 chain pairs each.  Time to 1% on every diagonal entry of every matrix:
+    one batched context (persistent launches) versus the plain path run
+    matrix by matrix; plus the batched sampling throughput."""
+    w = gen.WORKLOADS["batched"]
+    mats = [gen.round_values(x, np.float32) for x in gen.batched_pedigrees(w["m"], w["lo"], w["hi"], w["seed"])]
+    P, G, seed, burn = w["pairs"], w["groups"], w["noise_seed"], w["burn_in"]
+    nnz = sum(x.nnz for x in mats)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = pkg.BatchSampler(mats, pairs=P, groups=G, seed=seed, use_torch_stream=True)
+    sched, r, g, tune_ms = b.autotune(1)
+    b.burn_in(burn)
+    b.request(diag=True, block_dim=w["block"], expected_samples=200)
+    done, ach = b.sample_until(rel, 20000, check)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    # batched sampling throughput (block moments on the matrix cores included)
+    K = 20
+    b.sample(K)
+    ms_call = b.info()["last_call_ms"]
+    info = b.info()
+    b.close()
+    alg = sum(algorithmic_bytes_per_sweep(x.n, x.nnz, P, 4, 4) for x in mats)
+    log(f"batched form: {t_batch:.2f} s to 1% ({done} sample sweeps); plain form, matrix by matrix ...")
+    # plain form, matrix by matrix (same seeds: stream id = matrix index)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    worst = 0.0
+    sweeps_plain = []
+    for j, x in enumerate(mats):
+        s = pkg.Sampler(x, pairs=P, groups=G, dtype="f32", seed=seed, stream_id=j, moments="bf16x3",
+                        use_torch_stream=True)
+        s.burn_in(burn)
+        s.request(diag=True, trace=False)
+        dj, aj = s.sample_until(rel, 20000, check)
+        worst = max(worst, aj)
+        if j % 64 == 63:
+            log(f"plain form: {j + 1} matrices, {time.perf_counter() - t1:.1f} s")
+        sweeps_plain.append(dj)
+        s.close()
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t1
+    return {"workload": f"{len(mats)} pedigree matrices, n log-uniform in [{w['lo']}, {w['hi']}] "
+                        f"(sum n = {sum(x.n for x in mats)}, nnz = {nnz}), {P} pairs each, fp32",
+            "batched_seconds": t_batch, "batched_sample_sweeps": done, "batched_max_rel_se": ach,
+            "autotune": {"schedule": ["phased graph", "persistent"][sched], "rows_per_item": r, "grab": g,
+                         "ms_per_sweep": tune_ms},
+            "plain_seconds": t_plain, "plain_sample_sweeps_max": max(sweeps_plain), "plain_max_rel_se": worst,
+            "speedup_vs_plain": t_plain / t_batch,
+            "throughput": {"nonzero_updates_per_s": 2.0 * nnz * P * K / (ms_call / 1e3),
+                           "ms_per_sweep": ms_call / K, "items_per_sweep": info["items_per_sweep"],
+                           "algorithmic_GBps": alg * K / (ms_call / 1e3) / 1e9,
+                           "note": "one graph launch of 20 sampling sweeps with 128x128 bf16x3 block moments, "
+                                   "autotuned schedule"}}
+
+
 def cpu_baseline(m, seed, P, G, budget_s):
     """The oracle (single-threaded C, fp64) on a bounded sample of the same
     workload: a few chain pairs, as many sweeps as fit the time budget."""
@@ -90,6 +169,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-1%% phase")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-form comparison")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (scale for HBM counters)")
     args = ap.parse_args()
@@ -119,7 +199,8 @@ def main():
     blk = np.arange(n - w["block"], n) if "block" in w else None
     torch.cuda.set_device(0)
 
-    s = pkg.Sampler(m, pairs=P, groups=G, dtype=dtype, seed=seed, use_torch_stream=True, profile=True)
+    s = pkg.Sampler(m, pairs=P, groups=G, dtype=dtype, seed=seed, use_torch_stream=True, profile=True,
+                    moments="bf16x3" if dtype == "f32" else "fp64")
     info0 = s.info()
     s.burn_in(w["burn_in"])
     s.request(diag=True, trace=True, block_rows=blk, block_cols=blk)
@@ -180,18 +261,21 @@ def main():
                         "p99": float(np.quantile(rel, 0.99)), "samples": args.warmup + K},
     }
 
+    log(f"throughput: {ups:.3e} nonzero-updates/s, {ms / K:.3f} ms per step")
     if not args.no_ttt:
-        s2 = pkg.Sampler(m, pairs=P, groups=G, dtype=dtype, seed=seed + 1, use_torch_stream=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        s2.burn_in(w["burn_in"])
-        s2.request(diag=True, trace=False)
-        done, ach = s2.sample_until(0.01, 5000, 10)
-        torch.cuda.synchronize()
-        tt = time.perf_counter() - t0
-        s2.close()
-        result["time_to_1pct"] = {"seconds": tt, "burn_in": w["burn_in"], "sample_sweeps": done,
-                                  "max_rel_se": ach, "form": f"plain {dtype}, fixed burn-in"}
+        forms = {}
+        if args.workload == "pedigree":
+            forms["plain_fp64"] = time_to_1pct(pkg, torch, gen.pedigree(n, seed=w["seed"]), P, G, seed + 1,
+                                               "f64", "fp64", w["burn_in"])
+        forms["precision"] = time_to_1pct(pkg, torch, m, P, G, seed + 1, dtype,
+                                          "bf16x3" if dtype == "f32" else "fp64", w["burn_in"])
+        if "plain_fp64" in forms:
+            forms["precision"]["speedup_vs_plain"] = forms["plain_fp64"]["seconds"] / forms["precision"]["seconds"]
+        log(f"time to 1%: {forms['precision']['seconds']:.2f} s")
+        if args.workload == "pedigree" and not args.no_batched:
+            forms["batched"] = batched_forms(pkg, torch, gen)
+        result["forms"] = forms
+        result["time_to_1pct"] = forms["precision"]
 
     if args.copy_calibration:
         nbytes = 1 << 30
@@ -211,6 +295,7 @@ def main():
         del src, dst
 
     if not args.no_cpu:
+        log("cpu baseline (oracle) ...")
         result["cpu_baseline"] = cpu_baseline(m, seed, P, G, args.cpu_budget)
     print(json.dumps(result), flush=True)
 

@@ -203,8 +203,9 @@ const char* mcinv_last_error(const mcinv_ctx* ctx);
 
 /* ------------------------------------------------------------------------ */
 /* Batched form: many real matrices of uneven order, each with its own n_pairs
- * chain pairs (fp32 sweeps, eqs 4-5), all swept by ONE persistent kernel per
- * call (replayed from a captured HIP graph).  Matrix m is prepared exactly as
+ * chain pairs (fp32 sweeps, eqs 4-5), all swept together by one graph launch
+ * per call (a persistent kernel, or one kernel per colour phase; see the
+ * schedules below).  Matrix m is prepared exactly as
  * a single-matrix context would prepare it and draws its noise with
  * stream_id = m, so its chains are bit-identical to a single-matrix context
  * with the same seed and stream_id = m.  Moments: the diagonal (fp64 sums,
@@ -214,21 +215,30 @@ const char* mcinv_last_error(const mcinv_ctx* ctx);
  * time batches of length ceil(expected_samples / 16).                        */
 typedef struct mcinv_batch mcinv_batch;
 
+/* Batched schedules.  PERSISTENT: one launch runs all sweeps of a call; work
+ * items (sweep, colour, matrix, row chunk) are taken in order from a device
+ * queue and wait on per-matrix completion counters (agent-scope release /
+ * acquire).  PHASED: per sweep one launch per colour across all matrices and
+ * one for the block moments, the whole call captured as one HIP graph and
+ * replayed with a single graph launch; kernel boundaries order the phases. */
+#define MCINV_SCHEDULE_PHASED     0
+#define MCINV_SCHEDULE_PERSISTENT 1
+
 typedef struct {
     int32_t  device;
     int32_t  noise;          /* MCINV_NOISE_*                                    */
     int64_t  n_pairs;        /* P per matrix: 16, 32, 64, 128 or 256             */
     int32_t  n_groups;       /* G: P/G a power of two >= 4                       */
     int32_t  rows_per_item;  /* rows per work item (0: 64; see autotune)         */
-    int32_t  grab;           /* work items taken per queue access (0: 4)         */
-    int32_t  reserved;
+    int32_t  grab;           /* persistent schedule: items per queue access (0: 4) */
+    int32_t  schedule;       /* MCINV_SCHEDULE_PHASED or MCINV_SCHEDULE_PERSISTENT */
     uint64_t seed;           /* Philox key (shared by all matrices)             */
     void*    stream;         /* hipStream_t or NULL for a library stream         */
 } mcinv_batch_config;
 
 typedef struct {
     int64_t n_matrices, n_rows, nnz, n_pairs;
-    int32_t n_groups, max_colors, rows_per_item, grab, grid, reserved;
+    int32_t n_groups, max_colors, rows_per_item, grab, grid, schedule;
     int64_t items_per_sweep, sweeps_done, samples_done;
     double  last_call_ms;    /* device time of the last burn_in / sample call   */
 } mcinv_batch_info;
@@ -272,11 +282,12 @@ mcinv_status mcinv_batch_read_estimates(mcinv_batch* b, int64_t m, uint32_t quan
 /* Chain state of matrix m, [n][P] fp32, original row order. */
 mcinv_status mcinv_batch_read_state(mcinv_batch* b, int64_t m, int32_t which, float* host, int64_t bytes);
 
-/* Time every (rows per item, items per grab) candidate on sweeps_per_trial
- * burn-in sweeps (plus one warm-up each; the chains advance as in burn-in)
- * and keep the fastest. */
-mcinv_status mcinv_batch_autotune(mcinv_batch* b, int32_t sweeps_per_trial, int32_t* rows_per_item, int32_t* grab,
-                                  double* ms_per_sweep);
+/* Time every (schedule, rows per item, items per grab) candidate on
+ * sweeps_per_trial burn-in sweeps (plus one warm-up each; the chains advance
+ * as in burn-in, and the schedule never changes the chains) and keep the
+ * fastest.  Any output pointer may be NULL. */
+mcinv_status mcinv_batch_autotune(mcinv_batch* b, int32_t sweeps_per_trial, int32_t* schedule,
+                                  int32_t* rows_per_item, int32_t* grab, double* ms_per_sweep);
 
 mcinv_status mcinv_batch_get_info(mcinv_batch* b, mcinv_batch_info* out);
 const char* mcinv_batch_last_error(const mcinv_batch* b);

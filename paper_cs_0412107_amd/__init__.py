@@ -129,10 +129,11 @@ class BatchSampler:
     sweeps in one persistent launch per call."""
 
     def __init__(self, matrices, pairs=64, groups=16, seed=0, noise=MCINV_NOISE_NORMAL, device=0,
-                 rows_per_item=0, grab=0, use_torch_stream=False):
+                 rows_per_item=0, grab=0, use_torch_stream=False, schedule=0):
         stream = torch_stream() if use_torch_stream else None
         self.b = mcinv_batch_create(len(matrices), device=device, noise=noise, n_pairs=pairs, n_groups=groups,
-                                    rows_per_item=rows_per_item, grab=grab, seed=seed, stream=stream)
+                                    rows_per_item=rows_per_item, grab=grab, seed=seed, stream=stream,
+                                    schedule=schedule)
         self.n = [m.n for m in matrices]
         self.P = pairs
         self.bdim = 0

@@ -79,7 +79,7 @@ class mcinv_batch_config(ctypes.Structure):
         ("n_groups", ctypes.c_int32),
         ("rows_per_item", ctypes.c_int32),
         ("grab", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("schedule", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
         ("stream", ctypes.c_void_p),
     ]
@@ -90,13 +90,13 @@ class mcinv_batch_info(ctypes.Structure):
         ("n_matrices", ctypes.c_int64), ("n_rows", ctypes.c_int64), ("nnz", ctypes.c_int64),
         ("n_pairs", ctypes.c_int64),
         ("n_groups", ctypes.c_int32), ("max_colors", ctypes.c_int32), ("rows_per_item", ctypes.c_int32),
-        ("grab", ctypes.c_int32), ("grid", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("grab", ctypes.c_int32), ("grid", ctypes.c_int32), ("schedule", ctypes.c_int32),
         ("items_per_sweep", ctypes.c_int64), ("sweeps_done", ctypes.c_int64), ("samples_done", ctypes.c_int64),
         ("last_call_ms", ctypes.c_double),
     ]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 _lib = None
@@ -135,7 +135,8 @@ SIGNATURES = {
     "mcinv_batch_sample_until": (_I32, [_P, _D, _I64, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_D)]),
     "mcinv_batch_read_estimates": (_I32, [_P, _I64, _U32, _P, _P, _I64]),
     "mcinv_batch_read_state": (_I32, [_P, _I64, _I32, _P, _I64]),
-    "mcinv_batch_autotune": (_I32, [_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_D)]),
+    "mcinv_batch_autotune": (_I32, [_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32),
+                                    ctypes.POINTER(_D)]),
     "mcinv_batch_get_info": (_I32, [_P, ctypes.POINTER(mcinv_batch_info)]),
     "mcinv_batch_last_error": (ctypes.c_char_p, [_P]),
 }
@@ -292,10 +293,13 @@ def mcinv_batch_last_error(b=None):
     return m.decode() if m else ""
 
 
+MCINV_SCHEDULE_PHASED, MCINV_SCHEDULE_PERSISTENT = 0, 1
+
+
 def mcinv_batch_create(n_matrices, device=0, noise=MCINV_NOISE_NORMAL, n_pairs=64, n_groups=16, rows_per_item=0,
-                       grab=0, seed=0, stream=None):
-    cfg = mcinv_batch_config(device, noise, n_pairs, n_groups, rows_per_item, grab, 0, seed & 0xFFFFFFFFFFFFFFFF,
-                             stream)
+                       grab=0, seed=0, stream=None, schedule=MCINV_SCHEDULE_PHASED):
+    cfg = mcinv_batch_config(device, noise, n_pairs, n_groups, rows_per_item, grab, schedule,
+                             seed & 0xFFFFFFFFFFFFFFFF, stream)
     h = ctypes.c_void_p()
     _bcheck(None, lib().mcinv_batch_create(ctypes.byref(cfg), int(n_matrices), ctypes.byref(h)))
     return h
@@ -352,12 +356,13 @@ def mcinv_batch_read_state(b, m, which, n, P):
 
 
 def mcinv_batch_autotune(b, sweeps_per_trial=2):
+    sc = ctypes.c_int32(0)
     r = ctypes.c_int32(0)
     g = ctypes.c_int32(0)
     ms = ctypes.c_double(0)
-    _bcheck(b, lib().mcinv_batch_autotune(b, int(sweeps_per_trial), ctypes.byref(r), ctypes.byref(g),
-                                          ctypes.byref(ms)))
-    return r.value, g.value, ms.value
+    _bcheck(b, lib().mcinv_batch_autotune(b, int(sweeps_per_trial), ctypes.byref(sc), ctypes.byref(r),
+                                          ctypes.byref(g), ctypes.byref(ms)))
+    return sc.value, r.value, g.value, ms.value
 
 
 def mcinv_batch_get_info(b):

@@ -26,6 +26,7 @@
 #include "../../include/mcinv.h"
 #include "device_common.h"
 #include "prep.h"
+#include "moments.h"
 #include "sweep.h"
 
 using namespace mcinv;

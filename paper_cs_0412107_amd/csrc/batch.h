@@ -75,6 +75,10 @@ struct BatchArgs {
 };
 
 hipError_t launch_batch(const BatchArgs& a, int grid, hipStream_t stream);
+// Phased schedule: the items of one phase, one workgroup each.
+hipError_t launch_batch_phase(const BatchArgs& a, const BItem* items, int64_t nitems, bool block_phase,
+                              hipStream_t stream);
+hipError_t launch_batch_tick(BatchClock* clock, bool sample, hipStream_t stream);
 int batch_kernel_occupancy();  // workgroups per CU the batch kernel can keep resident
 
 }  // namespace mcinv

@@ -14,6 +14,9 @@
 // handed out earlier, so the oldest unfinished item can always run; a wait
 // that exceeds its bound sets an error flag and every workgroup exits.
 //
+// A second, phased schedule runs the same item code with one launch per
+// phase instead (see k_batch_rows); the host times both and keeps the faster.
+//
 // Lane layout: a row's P pairs are spread over P/4 lanes (4 pairs each, one
 // Philox block per lane); a wave holds 256/P rows.  The gather, noise and
 // update arithmetic is the single-matrix kernel's, in the same order, so a
@@ -105,41 +108,24 @@ __device__ inline void batch_block(const BatchArgs& a, const BItem& it, int64_t 
     const int i16 = lane & 15, kg = lane >> 4;
     const int64_t slot = min(sample / a.batch_len, (int64_t)a.nslots_block - 1);
     const int bd = a.bdim;
-    const int nt = (bd + 31) / 32;
+    const int nt = (bd + 15) / 16;
     const int64_t* I = a.bI + a.mats[it.m].blk;
     const int64_t* J = a.bJ + a.mats[it.m].blk;
     double* acc_out = a.block + (slot * a.nmats + it.m) * (int64_t)bd * bd;
     for (int tt = wid; tt < nt * nt; tt += 4) {
-        const int r0 = 32 * (tt / nt), t0 = 32 * (tt % nt);
-        const float* zrow[2];
-        const float* wrow[2];
-        bool zok[2], wok[2];
+        const int r0 = 16 * (tt / nt), t0 = 16 * (tt % nt);
+        const int r = r0 + i16, c = t0 + i16;
+        const bool zok = r < bd, wok = c < bd;
+        const float* zrow = a.z + (zok ? I[r] : 0) * (int64_t)a.P;
+        const float* wrow = a.w + (wok ? J[c] : 0) * (int64_t)a.P;
+        f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+        bf16x3_tile16(zrow, zok, wrow, wok, 0, a.P, kg, acc);
+        if (!wok) continue;
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            const int r = r0 + 16 * t + i16, c = t0 + 16 * t + i16;
-            zok[t] = r < bd;
-            wok[t] = c < bd;
-            zrow[t] = a.z + (zok[t] ? I[r] : 0) * (int64_t)a.P;
-            wrow[t] = a.w + (wok[t] ? J[c] : 0) * (int64_t)a.P;
+        for (int v = 0; v < 4; ++v) {
+            const int ro = r0 + 4 * kg + v;
+            if (ro < bd) acc_out[(int64_t)ro * bd + c] += (double)acc[v];
         }
-        f32x4 acc[2][2];
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-        bf16x3_tile(zrow, zok, wrow, wok, 0, a.P, kg, acc);
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                const int c = t0 + 16 * j + i16;
-                if (c >= bd) continue;
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int r = r0 + 16 * i + 4 * kg + v;
-                    if (r < bd) acc_out[(int64_t)r * bd + c] += (double)acc[i][j][v];
-                }
-            }
     }
 }
 
@@ -211,6 +197,46 @@ __global__ __launch_bounds__(256) void k_batch(const BatchArgs a)
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
         }
     }
+}
+
+// Phased schedule: one launch per phase (a colour of every matrix, or the
+// block moments of every matrix); kernel boundaries order the phases, so no
+// fences are needed.  A one-thread kernel advances the clock after a sweep.
+__global__ __launch_bounds__(256) void k_batch_rows(const BatchArgs a, const BItem* items)
+{
+    const BItem it = items[blockIdx.x];
+    batch_rows(a, it, a.clock->sweep, a.sample ? a.clock->sample : -1);
+}
+
+__global__ __launch_bounds__(256) void k_batch_blocks(const BatchArgs a, const BItem* items)
+{
+    const BItem it = items[blockIdx.x];
+    batch_block(a, it, a.clock->sample);
+}
+
+__global__ void k_batch_tick(BatchClock* clock, int32_t sample)
+{
+    if (threadIdx.x == 0) {
+        clock->sweep += 1;
+        if (sample) clock->sample += 1;
+    }
+}
+
+hipError_t launch_batch_phase(const BatchArgs& a, const BItem* items, int64_t nitems, bool block_phase,
+                              hipStream_t stream)
+{
+    if (nitems <= 0) return hipSuccess;
+    if (block_phase)
+        k_batch_blocks<<<dim3((unsigned)nitems), dim3(256), 0, stream>>>(a, items);
+    else
+        k_batch_rows<<<dim3((unsigned)nitems), dim3(256), 0, stream>>>(a, items);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_tick(BatchClock* clock, bool sample, hipStream_t stream)
+{
+    k_batch_tick<<<dim3(1), dim3(64), 0, stream>>>(clock, sample ? 1 : 0);
+    return hipGetLastError();
 }
 
 hipError_t launch_batch(const BatchArgs& a, int grid, hipStream_t stream)

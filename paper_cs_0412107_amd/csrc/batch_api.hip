@@ -23,6 +23,7 @@
 #include "batch.h"
 #include "device_common.h"
 #include "prep.h"
+#include "moments.h"
 #include "sweep.h"
 
 using namespace mcinv;
@@ -66,6 +67,11 @@ struct mcinv_batch {
     BItem* d_items_sample = nullptr;
     BMat* d_mats_sample = nullptr;
     int64_t ips_burn = 0, ips_sample = 0;
+    int32_t schedule = MCINV_SCHEDULE_PHASED;
+    // phase boundaries of the item lists (burn, sample) and whether a phase is
+    // the block-moment phase
+    std::vector<int64_t> phase_off[2];
+    std::vector<bool> phase_block[2];
     std::map<std::pair<int64_t, int>, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
 
     // moments
@@ -155,7 +161,11 @@ mcinv_status build_items(mcinv_batch* b)
         const bool with_block = pass == 1 && b->bdim > 0 && (b->flags & MCINV_REQ_BLOCK);
         std::vector<BItem> items;
         std::vector<int32_t> per_m(b->M, 0);
-        for (int32_t c = 0; c < b->max_colors; ++c)
+        b->phase_off[pass].clear();
+        b->phase_block[pass].clear();
+        for (int32_t c = 0; c < b->max_colors; ++c) {
+            b->phase_off[pass].push_back((int64_t)items.size());
+            b->phase_block[pass].push_back(false);
             for (int64_t m = 0; m < b->M; ++m) {
                 const Prepared& h = b->prep[m];
                 if (c >= h.ncolors) continue;
@@ -172,6 +182,11 @@ mcinv_status build_items(mcinv_batch* b)
                     per_m[m]++;
                 }
             }
+        }
+        if (with_block) {
+            b->phase_off[pass].push_back((int64_t)items.size());
+            b->phase_block[pass].push_back(true);
+        }
         if (with_block)
             for (int64_t m = 0; m < b->M; ++m) {
                 BItem it{};
@@ -181,6 +196,7 @@ mcinv_status build_items(mcinv_batch* b)
                 items.push_back(it);
                 per_m[m]++;
             }
+        b->phase_off[pass].push_back((int64_t)items.size());
         std::vector<BMat> mats(b->M);
         for (int64_t m = 0; m < b->M; ++m) {
             mats[m].row0 = b->row0[m];
@@ -261,7 +277,7 @@ mcinv_status commit(mcinv_batch* b)
     return MCINV_OK;
 }
 
-hipError_t run_launch(mcinv_batch* b, int64_t nsweeps, bool sample)
+BatchArgs make_args(mcinv_batch* b, int64_t nsweeps, bool sample)
 {
     BatchArgs a{};
     a.rows = b->d_rows;
@@ -296,7 +312,27 @@ hipError_t run_launch(mcinv_batch* b, int64_t nsweeps, bool sample)
     a.block = sample && (b->flags & MCINV_REQ_BLOCK) ? b->d_block : nullptr;
     a.flag = b->d_flag;
     a.thresh = 1e30f;
-    return launch_batch(a, b->grid, b->stream);
+    return a;
+}
+
+// One call's sweeps on the stream: a single persistent launch, or per sweep
+// one launch per phase followed by the clock tick.
+hipError_t run_launch(mcinv_batch* b, int64_t nsweeps, bool sample)
+{
+    const BatchArgs a = make_args(b, nsweeps, sample);
+    if (b->schedule == MCINV_SCHEDULE_PERSISTENT) return launch_batch(a, b->grid, b->stream);
+    const int pass = sample ? 1 : 0;
+    const std::vector<int64_t>& off = b->phase_off[pass];
+    for (int64_t k = 0; k < nsweeps; ++k) {
+        for (size_t p = 0; p + 1 < off.size(); ++p) {
+            const hipError_t e = launch_batch_phase(a, a.items + off[p], off[p + 1] - off[p],
+                                                    b->phase_block[pass][p], b->stream);
+            if (e != hipSuccess) return e;
+        }
+        const hipError_t e = launch_batch_tick(b->d_clock, sample, b->stream);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // Runs nsweeps sweeps as graph replays of one persistent launch each.
@@ -405,6 +441,8 @@ mcinv_status mcinv_batch_create(const mcinv_batch_config* cfg, int64_t n_matrice
     if (n_matrices < 1 || n_matrices > (1 << 20)) return bfail(nullptr, MCINV_EINVAL, "bad matrix count");
     if (cfg->noise < 0 || cfg->noise > 2) return bfail(nullptr, MCINV_EINVAL, "unknown noise kind");
     if (cfg->rows_per_item < 0 || cfg->grab < 0) return bfail(nullptr, MCINV_EINVAL, "bad schedule");
+    if (cfg->schedule != MCINV_SCHEDULE_PHASED && cfg->schedule != MCINV_SCHEDULE_PERSISTENT)
+        return bfail(nullptr, MCINV_EINVAL, "unknown schedule");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev)
         return bfail(nullptr, MCINV_EDEVICE, "no such HIP device");
@@ -418,6 +456,7 @@ mcinv_status mcinv_batch_create(const mcinv_batch_config* cfg, int64_t n_matrice
     b->prep.resize(n_matrices);
     b->loaded.assign(n_matrices, false);
     b->nslots_diag = G >= 16 ? 1 : kDiagSlotsSmallG;
+    b->schedule = cfg->schedule;
     if (cfg->rows_per_item > 0) b->rows_per_item = cfg->rows_per_item;
     if (cfg->grab > 0) b->grab = cfg->grab;
     auto bail = [&](const char* msg) {
@@ -686,20 +725,23 @@ mcinv_status mcinv_batch_read_state(mcinv_batch* b, int64_t m, int32_t which, fl
     return MCINV_OK;
 }
 
-mcinv_status mcinv_batch_autotune(mcinv_batch* b, int32_t sweeps_per_trial, int32_t* rows_per_item, int32_t* grab,
-                                  double* ms_per_sweep)
+mcinv_status mcinv_batch_autotune(mcinv_batch* b, int32_t sweeps_per_trial, int32_t* schedule,
+                                  int32_t* rows_per_item, int32_t* grab, double* ms_per_sweep)
 {
     BTRY(check_batch(b));
     if (sweeps_per_trial < 1) return bfail(b, MCINV_EINVAL, "sweeps_per_trial must be >= 1");
-    const int32_t rows_c[] = {16, 32, 64, 128, 256};
-    const int32_t grab_c[] = {1, 4, 16};
+    const int32_t rows_c[] = {16, 32, 64, 128, 256, 512, 1024};
+    const int32_t grab_c[] = {1, 4};
     double best = INFINITY;
-    int32_t best_r = b->rows_per_item, best_g = b->grab;
+    int32_t best_r = b->rows_per_item, best_g = b->grab, best_s = b->schedule;
     hipEvent_t e0, e1;
     BHIP(b, hipEventCreate(&e0));
     BHIP(b, hipEventCreate(&e1));
+    for (int32_t sched : {MCINV_SCHEDULE_PHASED, MCINV_SCHEDULE_PERSISTENT})
     for (int32_t r : rows_c)
         for (int32_t g : grab_c) {
+            if (sched == MCINV_SCHEDULE_PHASED && g != grab_c[0]) continue;  // grab is persistent-only
+            b->schedule = sched;
             b->rows_per_item = r;
             b->grab = g;
             BTRY(build_items(b));
@@ -715,13 +757,16 @@ mcinv_status mcinv_batch_autotune(mcinv_batch* b, int32_t sweeps_per_trial, int3
                 best = per;
                 best_r = r;
                 best_g = g;
+                best_s = sched;
             }
         }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     b->rows_per_item = best_r;
     b->grab = best_g;
+    b->schedule = best_s;
     BTRY(build_items(b));
+    if (schedule) *schedule = best_s;
     if (rows_per_item) *rows_per_item = best_r;
     if (grab) *grab = best_g;
     if (ms_per_sweep) *ms_per_sweep = best;
@@ -741,6 +786,7 @@ mcinv_status mcinv_batch_get_info(mcinv_batch* b, mcinv_batch_info* out)
     out->rows_per_item = b->rows_per_item;
     out->grab = b->grab;
     out->grid = b->grid;
+    out->schedule = b->schedule;
     out->items_per_sweep = b->ips_sample > 0 ? b->ips_sample : b->ips_burn;
     out->sweeps_done = b->sweeps;
     out->samples_done = b->samples;

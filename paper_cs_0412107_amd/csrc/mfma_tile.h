@@ -82,4 +82,24 @@ __device__ inline void bf16x3_tile(const float* const zrow[2], const bool zok[2]
     }
 }
 
+// acc += Z W^T over pairs [pbeg, pend) for one 16 x 16 tile: this lane holds
+// row zrow (tile row l mod 16) and column row wrow.  Same MFMA sequence per
+// output tile as bf16x3_tile, in a quarter of the registers.
+__device__ inline void bf16x3_tile16(const float* zrow, bool zok, const float* wrow, bool wok, int64_t pbeg,
+                                     int64_t pend, int kg, f32x4& acc)
+{
+    for (int64_t kb = pbeg; kb < pend; kb += 32) {
+        const int64_t p = kb + 8 * kg;
+        bf16x8 zh, zl, wh, wl;
+        float v[8];
+        load8(zrow, p, pend, zok, v);
+        split8(v, zh, zl);
+        load8(wrow, p, pend, wok, v);
+        split8(v, wh, wl);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zh, wh, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zh, wl, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(zl, wh, acc, 0, 0, 0);
+    }
+}
+
 }  // namespace mcinv

@@ -9,6 +9,7 @@
 //  - k_finalize_*: cluster ratio estimator -> estimate and standard error.
 //  - k_geyer: Geyer's initial positive sequence on the trace series.
 #include "device_common.h"
+#include "moments.h"
 #include "sweep.h"
 
 namespace mcinv {
@@ -330,6 +331,7 @@ __global__ __launch_bounds__(64) void k_finalize_flat(const FinalizeArgs f)
         f.est[m * f.comps] = __builtin_nan("");
         if (f.comps == 2) f.est[m * 2 + 1] = __builtin_nan("");
         f.se[m] = __builtin_nan("");
+        if (f.max_rel) atomicMax(f.max_rel, (unsigned long long)__double_as_longlong(__builtin_inf()));
         return;
     }
     er /= wsum;
@@ -351,6 +353,11 @@ __global__ __launch_bounds__(64) void k_finalize_flat(const FinalizeArgs f)
     f.est[m * f.comps] = er;
     if (f.comps == 2) f.est[m * 2 + 1] = ei;
     f.se[m] = se;
+    if (f.max_rel != nullptr) {
+        double rel = se / sqrt(er * er + ei * ei);
+        if (!(rel >= 0.0) || !(rel < __builtin_inf())) rel = __builtin_inf();
+        atomicMax(f.max_rel, (unsigned long long)__double_as_longlong(rel));
+    }
 }
 
 hipError_t launch_finalize_diag(const FinalizeArgs& f, hipStream_t stream)

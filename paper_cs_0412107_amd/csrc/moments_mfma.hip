@@ -11,6 +11,7 @@
 // workgroup holds four groups of the same tile.
 #include "device_common.h"
 #include "mfma_tile.h"
+#include "moments.h"
 #include "sweep.h"
 
 namespace mcinv {

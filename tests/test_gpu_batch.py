@@ -30,10 +30,11 @@ def mats():
     return [gen.round_values(gen.pedigree(int(n), seed=300 + j), np.float32) for j, n in enumerate(SIZES)]
 
 
-def test_batched_states_equal_single_path(mats):
-    print_case(test="batch_states", matrices=len(mats))
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_batched_states_equal_single_path(mats, schedule):
+    print_case(test="batch_states", matrices=len(mats), schedule=schedule)
     P, G, seed = 64, 16, 0x412107 + 3
-    with mc.BatchSampler(mats, pairs=P, groups=G, seed=seed, rows_per_item=32, grab=2) as b:
+    with mc.BatchSampler(mats, pairs=P, groups=G, seed=seed, rows_per_item=32, grab=2, schedule=schedule) as b:
         b.burn_in(4)
         for m in (0, 3, 4, 9, 11):
             with mc.Sampler(mats[m], pairs=P, groups=G, dtype="f32", seed=seed, stream_id=m) as s:
@@ -53,11 +54,12 @@ def test_batched_matches_oracle(mats):
         assert rel_err(b.state(m, 1), ora.w) <= 1e-5
 
 
-@pytest.mark.parametrize("P,G", [(64, 16), (32, 2), (128, 8)])
-def test_batched_moments_equal_single_path(mats, P, G):
-    print_case(test="batch_moments", P=P, G=G)
+@pytest.mark.parametrize("P,G,schedule", [(64, 16, 0), (64, 16, 1), (32, 2, 0), (128, 8, 1)])
+def test_batched_moments_equal_single_path(mats, P, G, schedule):
+    print_case(test="batch_moments", P=P, G=G, schedule=schedule)
     seed, S, bd = 99, 12, 48
-    with mc.BatchSampler(mats[:6], pairs=P, groups=G, seed=seed, rows_per_item=16, grab=1) as b:
+    with mc.BatchSampler(mats[:6], pairs=P, groups=G, seed=seed, rows_per_item=16, grab=1,
+                         schedule=schedule) as b:
         b.burn_in(5)
         b.request(diag=True, block_dim=bd, expected_samples=S)
         b.sample(S)
@@ -95,12 +97,13 @@ def test_batched_moments_equal_single_path(mats, P, G):
     assert rel_err(bb, ob.real) <= 1e-4
 
 
-def test_graph_replays_continue_the_chain(mats):
-    """Three replays of a 3-sweep launch equal one 9-sweep launch."""
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_graph_replays_continue_the_chain(mats, schedule):
+    """Three replays of a 3-sweep call equal one 9-sweep call."""
     P, G, seed = 64, 16, 5
     sub = mats[:5]
-    with mc.BatchSampler(sub, pairs=P, groups=G, seed=seed) as a, \
-            mc.BatchSampler(sub, pairs=P, groups=G, seed=seed) as b:
+    with mc.BatchSampler(sub, pairs=P, groups=G, seed=seed, schedule=schedule) as a, \
+            mc.BatchSampler(sub, pairs=P, groups=G, seed=seed, schedule=schedule) as b:
         a.burn_in(2)
         b.burn_in(2)
         a.request(diag=True, block_dim=32, expected_samples=9)
@@ -119,8 +122,8 @@ def test_graph_replays_continue_the_chain(mats):
 def test_autotune_and_sample_until(mats):
     P, G, seed = 64, 16, 21
     with mc.BatchSampler(mats, pairs=P, groups=G, seed=seed) as b:
-        r, g, ms = b.autotune(1)
-        assert r in (16, 32, 64, 128, 256) and g in (1, 4, 16) and ms > 0
+        sched, r, g, ms = b.autotune(1)
+        assert sched in (0, 1) and r in (16, 32, 64, 128, 256, 512, 1024) and g in (1, 4) and ms > 0
         info = b.info()
         burned = info["sweeps_done"]
         b.burn_in(30)
