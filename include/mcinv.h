@@ -183,6 +183,11 @@ mcinv_status mcinv_get_permutation(mcinv_ctx* ctx, int64_t* perm, int32_t* color
  * sp(T) and sp(S) (Sec. 2.3).  Does not touch the chain state.  iters >= 2. */
 mcinv_status mcinv_check_convergence(mcinv_ctx* ctx, int64_t iters, double* rho_T, double* rho_S);
 
+/* Restrict the stop check of mcinv_sample_until (max SE/|est| of the
+ * diagonal) to the given original rows; count 0 restores every row.  The
+ * estimates of all rows are still computed.  Cleared by mcinv_load_csr. */
+mcinv_status mcinv_set_stop_rows(mcinv_ctx* ctx, const int64_t* rows, int64_t count);
+
 /* Sizes, counters and (when profiling) kernel times. */
 mcinv_status mcinv_get_info(mcinv_ctx* ctx, mcinv_info* out);
 
@@ -291,6 +296,114 @@ mcinv_status mcinv_batch_autotune(mcinv_batch* b, int32_t sweeps_per_trial, int3
 
 mcinv_status mcinv_batch_get_info(mcinv_batch* b, mcinv_batch_info* out);
 const char* mcinv_batch_last_error(const mcinv_batch* b);
+
+/* ------------------------------------------------------------------------ */
+/* Learned surrogate of the diagonal.  Writing C = D (I + M), M = D^-1 R with
+ * R the off-diagonal part, the series C^-1 = sum_k (-M)^k D^-1 (it converges
+ * under the dominance that Sec. 2.3 needs for the sampler) gives
+ *     y_i = c_ii (C^-1)_ii = 1 + (M^2)_ii - (M^3)_ii + ...
+ * The surrogate predicts y_i from local terms of that series and statistics of
+ * row i's neighbourhood; the sampler's estimates (eq 1/C) are its labels, and
+ * a gate sends the rows whose validated error is too large back to the
+ * sampler.                                                                   */
+
+#define MCINV_N_FEATURES 32
+
+/* Features of every row of a real matrix (CSR rules as mcinv_load_csr,
+ * float64 values), out[n][32] float32 in the caller's row order, computed in
+ * fp64 on the device.  Feature k of row i (m_ij = c_ij / c_ii; "neighbours"
+ * are the j != i with c_ij or c_ji stored; r_j = row abs sum / |c_jj|):
+ *   0 log|c_ii|                       1 sum_j |c_ij| / |c_ii| (= r_i)
+ *   2 sum_j |c_ji| / |c_ii|           3, 4 row / column off-diagonal count / 8
+ *   5 (M^2)_ii                        6 (M^3)_ii
+ *   7 sum_j |m_ij| |m_ji|             8 sum_j m_ij^2
+ *   9 sum_j c_ij / c_ii              10 sum_j c_ji / c_ii
+ *  11-14 mean, max, min, std of the neighbours' r_j
+ *  15-17 mean, max, min of log|c_jj| - log|c_ii|;  18 std of log|c_jj|
+ *  19, 20 mean, max of the neighbours' (M^2)_jj
+ *  21, 22 mean, max of the neighbours' feature 2;  23 mean of their (M^3)_jj
+ *  24 neighbour count / 8     25 1 + (M^2)_ii     26 1 + (M^2)_ii - (M^3)_ii
+ *  27 r_i^2    28 ((M^2)_ii)^2    29 (M^2)_ii r_i    30 sum_j r_j^2 / 8    31 1
+ * Statistics over an empty neighbourhood are 0.  ESINGULAR / EINVAL as
+ * mcinv_load_csr; the message is mcinv_last_error(NULL). */
+mcinv_status mcinv_features(int32_t device, int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
+                            const double* values, float* out);
+
+/* The network: 32 -> 128 -> 128 -> 1, GELU (erf form) after the two hidden
+ * layers.  Parameters, float32, in this order (20865 values):
+ *   W1[32][128] (input-major), b1[128], W2[128][128] (input-major), b2[128],
+ *   w3[128], b3.
+ * Features are normalised as (x - mean) * inv_std before the first layer.
+ * Products run on the matrix cores with bf16 operands (round to nearest even:
+ * the normalised features, W1, W2, the first hidden activations and the
+ * second layer's deltas) and fp32 accumulation; everything else is fp32.
+ * Training minimises sum_r w_r (out_r - y_r)^2 / R over batches of R rows
+ * with Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on fp32
+ * master weights.  Zero-initialised parameters until set. */
+#define MCINV_MLP_PARAMS 20865
+typedef struct mcinv_mlp mcinv_mlp;
+
+mcinv_status mcinv_mlp_create(int32_t device, mcinv_mlp** out);
+void mcinv_mlp_destroy(mcinv_mlp* m);
+/* Set (and reset Adam's moments and step count) / read the parameters. */
+mcinv_status mcinv_mlp_set_params(mcinv_mlp* m, const float* params);
+mcinv_status mcinv_mlp_get_params(mcinv_mlp* m, float* params);
+/* mean[32], inv_std[32]: the feature normalisation (default 0 and 1). */
+mcinv_status mcinv_mlp_set_normalization(mcinv_mlp* m, const float* mean, const float* inv_std);
+/* Training rows: X[N][32] raw features, labels y[N], row weights w[N]
+ * (copied to the device; replaces earlier data). */
+mcinv_status mcinv_mlp_set_data(mcinv_mlp* m, const float* X, const float* y, const float* w, int64_t N);
+/* Set the normalisation to the training data's column means and inverse
+ * standard deviations (population, fp64; 1 for a constant column) and return
+ * them (either pointer may be NULL). */
+mcinv_status mcinv_mlp_fit_normalization(mcinv_mlp* m, float* mean, float* inv_std);
+/* Row weights of the loss from the labels' standard errors:
+ * w_i = 1 / (se_i^2 + eps), scaled to mean 1.  Host code. */
+mcinv_status mcinv_mlp_label_weights(int64_t N, const double* y_se, double eps, float* w);
+/* Gradient of the loss over the given training rows (nrows a positive
+ * multiple of 64, indices in [0, N)) at the current parameters, grads[20865]
+ * in parameter order, and the loss.  Does not change the parameters. */
+mcinv_status mcinv_mlp_gradients(mcinv_mlp* m, const int64_t* rows, int32_t nrows, float* grads, float* loss);
+/* steps Adam steps with learning rate lr.  Step t (counted from the last
+ * set_params, starting at 1) trains on the rows floor(x N / 2^64), x = (o0 << 32)
+ * | o1 of the Philox4x32-10 block with key (seed lo, seed hi) and counter (r,
+ * t, 0x5EED, 0xA11CE), r = 0..batch_rows-1.  batch_rows: a multiple of 64 up
+ * to 2^20.  loss_history (may be NULL): steps values, the loss before each step. */
+mcinv_status mcinv_mlp_train(mcinv_mlp* m, int64_t steps, int32_t batch_rows, float lr, uint64_t seed,
+                             float* loss_history);
+/* Predictions out[N] for raw features X[N][32] (host arrays). */
+mcinv_status mcinv_mlp_predict(mcinv_mlp* m, const float* X, int64_t N, float* out);
+const char* mcinv_mlp_last_error(const mcinv_mlp* m);
+
+/* The gate: which rows take the network's prediction and which go back to
+ * the sampler.  Validation rows (features X[N][32], predictions, sampler
+ * labels y and their standard errors) are binned on two features, each by its
+ * quantile edges: the sorted values at floor(k N / bins), k = 1..bins-1, and a
+ * value's bin is the number of edges <= it.  A bin's validated relative error
+ * is sqrt(max(sum r^2 - sum s^2, 0) / count), r = (pred - y)/y, s = se/y (the
+ * observed spread less what the label noise explains); the bin needs the
+ * sampler when it holds fewer than min_rows rows or that error exceeds tol.
+ * Host code, float64. */
+typedef struct {
+    int32_t feature_a, feature_b;  /* binning features, 0..31                    */
+    int32_t bins;                  /* bins per feature, 1..256                    */
+    int32_t min_rows;              /* fewer validation rows in a bin: sampler     */
+    double  tol;                   /* largest accepted relative error (e.g. 0.01) */
+} mcinv_gate_config;
+typedef struct mcinv_gate mcinv_gate;
+
+/* EINVAL: bad configuration, a non-finite binning feature, a zero or
+ * non-finite label. */
+mcinv_status mcinv_gate_fit(const mcinv_gate_config* cfg, int64_t N, const float* X, const double* pred,
+                            const double* y, const double* y_se, mcinv_gate** out);
+/* fallback[i] = 1 when row i's bin needs the sampler (or a binning feature is NaN). */
+mcinv_status mcinv_gate_apply(const mcinv_gate* g, int64_t N, const float* X, uint8_t* fallback);
+/* edges_a, edges_b [bins-1]; bin_err, bin_count, bin_fallback [bins * bins],
+ * bin (a, b) at a * bins + b (err is +inf for an empty bin).  Any may be NULL. */
+mcinv_status mcinv_gate_read(const mcinv_gate* g, double* edges_a, double* edges_b, double* bin_err,
+                             int64_t* bin_count, uint8_t* bin_fallback);
+void mcinv_gate_destroy(mcinv_gate* g);
+const char* mcinv_gate_last_error(void);
 
 #ifdef __cplusplus
 }

@@ -114,6 +114,11 @@ class Sampler:
     def permutation(self):
         return mcinv_get_permutation(self.ctx, self.n)
 
+    def set_stop_rows(self, rows=None):
+        """Restrict ``sample_until``'s stop check to these original rows (None: all)."""
+        from ._binding import mcinv_set_stop_rows
+        mcinv_set_stop_rows(self.ctx, rows)
+
     def check_convergence(self, iters=200):
         return mcinv_check_convergence(self.ctx, iters)
 

@@ -99,6 +99,11 @@ class mcinv_batch_info(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class mcinv_gate_config(ctypes.Structure):
+    _fields_ = [("feature_a", ctypes.c_int32), ("feature_b", ctypes.c_int32), ("bins", ctypes.c_int32),
+                ("min_rows", ctypes.c_int32), ("tol", ctypes.c_double)]
+
+
 _lib = None
 
 # name -> (restype, argtypes)
@@ -120,6 +125,7 @@ SIGNATURES = {
     "mcinv_read_state": (_I32, [_P, _I32, _P, _I64]),
     "mcinv_write_state": (_I32, [_P, _I32, _P, _I64]),
     "mcinv_get_permutation": (_I32, [_P, _P, _P]),
+    "mcinv_set_stop_rows": (_I32, [_P, _P, _I64]),
     "mcinv_check_convergence": (_I32, [_P, _I64, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "mcinv_get_info": (_I32, [_P, ctypes.POINTER(mcinv_info)]),
     "mcinv_reset_profile": (_I32, [_P]),
@@ -139,6 +145,24 @@ SIGNATURES = {
                                     ctypes.POINTER(_D)]),
     "mcinv_batch_get_info": (_I32, [_P, ctypes.POINTER(mcinv_batch_info)]),
     "mcinv_batch_last_error": (ctypes.c_char_p, [_P]),
+    "mcinv_features": (_I32, [_I32, _I64, _I64, _P, _P, _P, _P]),
+    "mcinv_mlp_create": (_I32, [_I32, ctypes.POINTER(_P)]),
+    "mcinv_mlp_destroy": (None, [_P]),
+    "mcinv_mlp_set_params": (_I32, [_P, _P]),
+    "mcinv_mlp_get_params": (_I32, [_P, _P]),
+    "mcinv_mlp_set_normalization": (_I32, [_P, _P, _P]),
+    "mcinv_mlp_set_data": (_I32, [_P, _P, _P, _P, _I64]),
+    "mcinv_mlp_fit_normalization": (_I32, [_P, _P, _P]),
+    "mcinv_mlp_label_weights": (_I32, [_I64, _P, _D, _P]),
+    "mcinv_mlp_gradients": (_I32, [_P, _P, _I32, _P, ctypes.POINTER(ctypes.c_float)]),
+    "mcinv_mlp_train": (_I32, [_P, _I64, _I32, ctypes.c_float, _U64, _P]),
+    "mcinv_mlp_predict": (_I32, [_P, _P, _I64, _P]),
+    "mcinv_mlp_last_error": (ctypes.c_char_p, [_P]),
+    "mcinv_gate_fit": (_I32, [ctypes.POINTER(mcinv_gate_config), _I64, _P, _P, _P, _P, ctypes.POINTER(_P)]),
+    "mcinv_gate_apply": (_I32, [_P, _I64, _P, _P]),
+    "mcinv_gate_read": (_I32, [_P, _P, _P, _P, _P, _P]),
+    "mcinv_gate_destroy": (None, [_P]),
+    "mcinv_gate_last_error": (ctypes.c_char_p, []),
 }
 
 
@@ -244,6 +268,11 @@ def mcinv_read_state(ctx, which, n, P, sweep_dtype):
 def mcinv_write_state(ctx, which, state, sweep_dtype):
     a = np.ascontiguousarray(state, dtype=NP_STATE[sweep_dtype])
     _check(ctx, lib().mcinv_write_state(ctx, which, _ptr(a), a.nbytes))
+
+
+def mcinv_set_stop_rows(ctx, rows=None):
+    r = None if rows is None else np.ascontiguousarray(rows, dtype=np.int64)
+    _check(ctx, lib().mcinv_set_stop_rows(ctx, _ptr(r), 0 if r is None else int(r.size)))
 
 
 def mcinv_get_permutation(ctx, n):
@@ -369,3 +398,159 @@ def mcinv_batch_get_info(b):
     info = mcinv_batch_info()
     _bcheck(b, lib().mcinv_batch_get_info(b, ctypes.byref(info)))
     return info.as_dict()
+
+
+# -------------------------------------------------------------- surrogate --
+MCINV_N_FEATURES = 32
+MCINV_MLP_PARAMS = 20865
+
+
+def mcinv_features(device, n, nnz, row_ptr, col_idx, values):
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    v = np.ascontiguousarray(values, dtype=np.float64)
+    out = np.empty((int(n), MCINV_N_FEATURES), dtype=np.float32)
+    _check(None, lib().mcinv_features(int(device), int(n), int(nnz), _ptr(rp), _ptr(ci), _ptr(v), _ptr(out)))
+    return out
+
+
+def _mcheck(m, status):
+    if status != MCINV_OK:
+        msg = lib().mcinv_mlp_last_error(m)
+        raise McinvError(status, msg.decode() if msg else "")
+    return status
+
+
+def mcinv_mlp_last_error(m=None):
+    s = lib().mcinv_mlp_last_error(m)
+    return s.decode() if s else ""
+
+
+def mcinv_mlp_create(device=0):
+    h = ctypes.c_void_p()
+    _mcheck(None, lib().mcinv_mlp_create(int(device), ctypes.byref(h)))
+    return h
+
+
+def mcinv_mlp_destroy(m):
+    lib().mcinv_mlp_destroy(m)
+
+
+def _f32(a, size=None):
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if size is not None and a.size != size:
+        raise ValueError(f"expected {size} values, got {a.size}")
+    return a
+
+
+def mcinv_mlp_set_params(m, params):
+    p = _f32(params, MCINV_MLP_PARAMS)
+    _mcheck(m, lib().mcinv_mlp_set_params(m, _ptr(p)))
+
+
+def mcinv_mlp_get_params(m):
+    out = np.empty(MCINV_MLP_PARAMS, dtype=np.float32)
+    _mcheck(m, lib().mcinv_mlp_get_params(m, _ptr(out)))
+    return out
+
+
+def mcinv_mlp_set_normalization(m, mean, inv_std):
+    a = _f32(mean, MCINV_N_FEATURES)
+    b = _f32(inv_std, MCINV_N_FEATURES)
+    _mcheck(m, lib().mcinv_mlp_set_normalization(m, _ptr(a), _ptr(b)))
+
+
+def mcinv_mlp_set_data(m, X, y, w):
+    X = _f32(X)
+    y = _f32(y)
+    w = _f32(w)
+    N = y.size
+    if X.size != N * MCINV_N_FEATURES or w.size != N:
+        raise ValueError("X must be [N][32], y and w [N]")
+    _mcheck(m, lib().mcinv_mlp_set_data(m, _ptr(X), _ptr(y), _ptr(w), int(N)))
+
+
+def mcinv_mlp_fit_normalization(m):
+    mean = np.empty(MCINV_N_FEATURES, dtype=np.float32)
+    inv = np.empty(MCINV_N_FEATURES, dtype=np.float32)
+    _mcheck(m, lib().mcinv_mlp_fit_normalization(m, _ptr(mean), _ptr(inv)))
+    return mean, inv
+
+
+def mcinv_mlp_label_weights(y_se, eps=1e-6):
+    se = np.ascontiguousarray(y_se, dtype=np.float64)
+    w = np.empty(se.size, dtype=np.float32)
+    _mcheck(None, lib().mcinv_mlp_label_weights(int(se.size), _ptr(se), float(eps), _ptr(w)))
+    return w
+
+
+def mcinv_mlp_gradients(m, rows):
+    r = np.ascontiguousarray(rows, dtype=np.int64)
+    g = np.empty(MCINV_MLP_PARAMS, dtype=np.float32)
+    loss = ctypes.c_float(0)
+    _mcheck(m, lib().mcinv_mlp_gradients(m, _ptr(r), int(r.size), _ptr(g), ctypes.byref(loss)))
+    return g, loss.value
+
+
+def mcinv_mlp_train(m, steps, batch_rows, lr, seed):
+    hist = np.empty(max(int(steps), 1), dtype=np.float32)
+    _mcheck(m, lib().mcinv_mlp_train(m, int(steps), int(batch_rows), float(lr), seed & 0xFFFFFFFFFFFFFFFF,
+                                      _ptr(hist)))
+    return hist[:int(steps)]
+
+
+def mcinv_mlp_predict(m, X):
+    X = _f32(X)
+    N = X.size // MCINV_N_FEATURES
+    out = np.empty(N, dtype=np.float32)
+    _mcheck(m, lib().mcinv_mlp_predict(m, _ptr(X), int(N), _ptr(out)))
+    return out
+
+
+def _gcheck(status):
+    if status != MCINV_OK:
+        msg = lib().mcinv_gate_last_error()
+        raise McinvError(status, msg.decode() if msg else "")
+    return status
+
+
+def mcinv_gate_fit(X, pred, y, y_se, feature_a, feature_b, bins, min_rows, tol):
+    X = _f32(X)
+    N = X.size // MCINV_N_FEATURES
+    pr = np.ascontiguousarray(pred, dtype=np.float64)
+    yy = np.ascontiguousarray(y, dtype=np.float64)
+    se = np.ascontiguousarray(y_se, dtype=np.float64)
+    if pr.size != N or yy.size != N or se.size != N:
+        raise ValueError("pred, y and y_se need one value per row of X")
+    cfg = mcinv_gate_config(int(feature_a), int(feature_b), int(bins), int(min_rows), float(tol))
+    h = ctypes.c_void_p()
+    _gcheck(lib().mcinv_gate_fit(ctypes.byref(cfg), int(N), _ptr(X), _ptr(pr), _ptr(yy), _ptr(se),
+                                 ctypes.byref(h)))
+    return h
+
+
+def mcinv_gate_apply(g, X):
+    X = _f32(X)
+    N = X.size // MCINV_N_FEATURES
+    out = np.empty(N, dtype=np.uint8)
+    _gcheck(lib().mcinv_gate_apply(g, int(N), _ptr(X), _ptr(out)))
+    return out
+
+
+def mcinv_gate_read(g, bins):
+    ea = np.empty(max(bins - 1, 0), dtype=np.float64)
+    eb = np.empty(max(bins - 1, 0), dtype=np.float64)
+    err = np.empty(bins * bins, dtype=np.float64)
+    cnt = np.empty(bins * bins, dtype=np.int64)
+    fb = np.empty(bins * bins, dtype=np.uint8)
+    _gcheck(lib().mcinv_gate_read(g, _ptr(ea), _ptr(eb), _ptr(err), _ptr(cnt), _ptr(fb)))
+    return {"edges_a": ea, "edges_b": eb, "err": err, "count": cnt, "fallback": fb.astype(bool)}
+
+
+def mcinv_gate_destroy(g):
+    lib().mcinv_gate_destroy(g)
+
+
+def mcinv_gate_last_error():
+    m = lib().mcinv_gate_last_error()
+    return m.decode() if m else ""

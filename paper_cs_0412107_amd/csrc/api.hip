@@ -41,6 +41,10 @@ constexpr double kGuardThreshold = 1e30;
 
 }  // namespace
 
+namespace mcinv {
+void set_context_free_error(const std::string& msg) { g_error = msg; }
+}  // namespace mcinv
+
 struct mcinv_ctx {
     mcinv_config cfg{};
     hipStream_t stream = nullptr;
@@ -96,6 +100,7 @@ struct mcinv_ctx {
     int64_t est_cap = 0;
     unsigned long long* d_maxrel = nullptr;
     double* d_geyer = nullptr;
+    uint8_t* d_stop = nullptr;   // rows the stop check covers (null: every row)
 
     // profiling
     std::vector<hipEvent_t> events;
@@ -168,6 +173,7 @@ void free_matrix(mcinv_ctx* c)
     dfree(c->d_z);
     dfree(c->d_w);
     dfree(c->d_perm);
+    dfree(c->d_stop);
     dfree(c->d_est);
     dfree(c->d_se);
     c->est_cap = 0;
@@ -462,6 +468,7 @@ mcinv_status finalize_diag(mcinv_ctx* c, bool want_max)
     f.est = c->d_est;
     f.se = c->d_se;
     f.max_rel = want_max ? c->d_maxrel : nullptr;
+    f.stop_mask = c->d_stop;
     HIP_TRY(c, launch_finalize_diag(f, c->stream));
     return MCINV_OK;
 }
@@ -838,6 +845,24 @@ mcinv_status mcinv_write_state(mcinv_ctx* c, int32_t which, const void* host, in
         std::memcpy(tmp.data() + (size_t)c->pos[i] * c->ld * c->elem, in + (size_t)i * row_bytes, row_bytes);
     HIP_TRY(c, hipMemcpyAsync(which ? c->d_w : c->d_z, tmp.data(), tmp.size(), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return MCINV_OK;
+}
+
+mcinv_status mcinv_set_stop_rows(mcinv_ctx* c, const int64_t* rows, int64_t count)
+{
+    MC_TRY(check_ready(c));
+    if (count < 0 || (count > 0 && !rows)) return fail(c, MCINV_EINVAL, "bad stop-row list");
+    std::vector<uint8_t> mask;
+    if (count > 0) {
+        mask.assign(c->n, 0);
+        for (int64_t k = 0; k < count; ++k) {
+            if (rows[k] < 0 || rows[k] >= c->n) return fail(c, MCINV_EINVAL, "stop row out of range");
+            mask[rows[k]] = 1;
+        }
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    dfree(c->d_stop);
+    if (count > 0) MC_TRY(upload(c, &c->d_stop, mask));
     return MCINV_OK;
 }
 

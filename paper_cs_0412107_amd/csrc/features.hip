@@ -1,0 +1,248 @@
+// Local features of each row for the learned surrogate of diag(C^-1).
+//
+// With C = D (I + M), M = D^-1 R (R the off-diagonal part), the Neumann series
+// gives c_ii (C^-1)_ii = 1 + (M^2)_ii - (M^3)_ii + ...; the features are local
+// terms of that series and neighbourhood statistics (list in include/mcinv.h,
+// mcinv_features).  Pass 1 computes the per-row terms; pass 2 the statistics
+// over each row's merged neighbours (row i or column i of C) from pass 1's
+// output.  fp64 arithmetic, one thread per row, fp32 output.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "../../include/mcinv.h"
+#include "prep.h"
+
+namespace mcinv {
+
+constexpr int kNF = 32;
+
+struct FEnt {
+    int32_t col;   // position of the neighbour
+    int32_t pad;
+    double cij;    // c_ij (row entry), 0 if not stored
+    double cji;    // c_ji (column entry), 0 if not stored
+};
+
+// c_ki for neighbour k of row i: binary search of k in i's sorted merged list.
+__device__ inline double lookup_cji(const FEnt* e, int32_t cnt, int32_t k)
+{
+    int lo = 0, hi = cnt - 1;
+    while (lo <= hi) {
+        const int mid = (lo + hi) >> 1;
+        const int32_t c = e[mid].col;
+        if (c == k) return e[mid].cji;
+        if (c < k)
+            lo = mid + 1;
+        else
+            hi = mid - 1;
+    }
+    return 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_features_pass1(int64_t n, const int64_t* beg, const int32_t* cnt,
+                                                        const FEnt* ent, const double* d, double* F)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const FEnt* e = ent + beg[i];
+    const int32_t c = cnt[i];
+    const double di = d[i], adi = fabs(di);
+    double rs = 0, cs = 0, nr = 0, nc = 0, m2 = 0, m3 = 0, a2 = 0, sq = 0, srow = 0, scol = 0;
+    for (int32_t t = 0; t < c; ++t) {
+        const int32_t j = e[t].col;
+        const double cij = e[t].cij, cji = e[t].cji, dj = d[j];
+        rs += fabs(cij);
+        cs += fabs(cji);
+        nr += cij != 0.0 ? 1.0 : 0.0;
+        nc += cji != 0.0 ? 1.0 : 0.0;
+        const double mij = cij / di, mji = cji / dj;
+        m2 += mij * mji;
+        a2 += fabs(mij) * fabs(mji);
+        sq += mij * mij;
+        srow += cij;
+        scol += cji;
+        if (cij != 0.0) {
+            // sum_k m_jk m_ki over the stored entries of row j
+            const FEnt* ej = ent + beg[j];
+            const int32_t cj = cnt[j];
+            double inner = 0.0;
+            for (int32_t u = 0; u < cj; ++u) {
+                const int32_t k = ej[u].col;
+                if (k == (int32_t)i || ej[u].cij == 0.0) continue;
+                const double cki = lookup_cji(e, c, k);
+                inner += (ej[u].cij / dj) * (cki / d[k]);
+            }
+            m3 += mij * inner;
+        }
+    }
+    double* f = F + i * kNF;
+    f[0] = log(adi);
+    f[1] = rs / adi;
+    f[2] = cs / adi;
+    f[3] = nr / 8.0;
+    f[4] = nc / 8.0;
+    f[5] = m2;
+    f[6] = m3;
+    f[7] = a2;
+    f[8] = sq;
+    f[9] = srow / di;
+    f[10] = scol / di;
+    f[24] = c / 8.0;
+    f[25] = 1.0 + m2;
+    f[26] = 1.0 + m2 - m3;
+    f[27] = f[1] * f[1];
+    f[28] = m2 * m2;
+    f[29] = m2 * f[1];
+    f[31] = 1.0;
+}
+
+__device__ inline void stats(double v, double& s1, double& s2, double& mx, double& mn)
+{
+    s1 += v;
+    s2 += v * v;
+    mx = fmax(mx, v);
+    mn = fmin(mn, v);
+}
+
+__global__ __launch_bounds__(256) void k_features_pass2(int64_t n, const int64_t* beg, const int32_t* cnt,
+                                                        const FEnt* ent, double* F, const int64_t* out_row,
+                                                        float* out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const FEnt* e = ent + beg[i];
+    const int32_t c = cnt[i];
+    double* f = F + i * kNF;
+    double r1 = 0, r2 = 0, rmx = -INFINITY, rmn = INFINITY;   // neighbours' row ratio
+    double l1 = 0, l2 = 0, lmx = -INFINITY, lmn = INFINITY;   // neighbours' log|c_jj|
+    double q1 = 0, q2 = 0, qmx = -INFINITY, qmn = INFINITY;   // neighbours' (M^2)_jj
+    double c1 = 0, c2 = 0, cmx = -INFINITY, cmn = INFINITY;   // neighbours' column ratio
+    double t1 = 0;                                            // neighbours' (M^3)_jj
+    for (int32_t t = 0; t < c; ++t) {
+        const double* g = F + (int64_t)e[t].col * kNF;
+        stats(g[1], r1, r2, rmx, rmn);
+        stats(g[0], l1, l2, lmx, lmn);
+        stats(g[5], q1, q2, qmx, qmn);
+        stats(g[2], c1, c2, cmx, cmn);
+        t1 += g[6];
+    }
+    double o[kNF];
+    for (int k = 0; k < kNF; ++k) o[k] = f[k];
+    if (c > 0) {
+        const double rm = r1 / c, lm = l1 / c;
+        // population standard deviations from the squared deviations (a second
+        // pass: no cancellation when the neighbours' values are all equal)
+        double rv = 0.0, lv = 0.0;
+        for (int32_t t = 0; t < c; ++t) {
+            const double* g = F + (int64_t)e[t].col * kNF;
+            rv += (g[1] - rm) * (g[1] - rm);
+            lv += (g[0] - lm) * (g[0] - lm);
+        }
+        o[11] = rm;
+        o[12] = rmx;
+        o[13] = rmn;
+        o[14] = sqrt(rv / c);
+        o[15] = lm - f[0];
+        o[16] = lmx - f[0];
+        o[17] = lmn - f[0];
+        o[18] = sqrt(lv / c);
+        o[19] = q1 / c;
+        o[20] = qmx;
+        o[21] = c1 / c;
+        o[22] = cmx;
+        o[23] = t1 / c;
+    } else {
+        for (int k = 11; k <= 23; ++k) o[k] = 0.0;
+    }
+    o[30] = r2 / 8.0;
+    float* dst = out + out_row[i] * kNF;
+    for (int k = 0; k < kNF; ++k) dst[k] = (float)o[k];
+}
+
+}  // namespace mcinv
+
+using namespace mcinv;
+
+extern "C" mcinv_status mcinv_features(int32_t device, int64_t n, int64_t nnz, const int64_t* row_ptr,
+                                       const int32_t* col_idx, const double* values, float* out)
+{
+    if (!out) {
+        set_context_free_error("mcinv_features: null output");
+        return MCINV_EINVAL;
+    }
+    Prepared h;
+    bool singular = false;
+    const std::string why = prepare_matrix(n, nnz, row_ptr, col_idx, values, false, h, &singular);
+    if (!why.empty()) {
+        set_context_free_error("mcinv_features: " + why);
+        return singular ? MCINV_ESINGULAR : MCINV_EINVAL;
+    }
+    std::vector<int64_t> beg(n);
+    std::vector<int32_t> cnt(n);
+    std::vector<FEnt> ent(h.ent.size());
+    std::vector<double> d(n);
+    for (int64_t q = 0; q < n; ++q) {
+        beg[q] = h.rows[q].begin;
+        cnt[q] = h.rows[q].count;
+        d[q] = h.diag[q].real();
+        for (int64_t t = h.rows[q].begin; t < h.rows[q].begin + h.rows[q].count; ++t) {
+            // the merged entry stores u = c_ij / c_ii and v = c_ji / c_ii (real C)
+            ent[t].col = (int32_t)h.ent[t].col;
+            ent[t].pad = 0;
+            ent[t].cij = h.ent[t].u.real() * d[q];
+            ent[t].cji = h.ent[t].v.real() * d[q];
+        }
+    }
+    if (hipSetDevice(device) != hipSuccess) {
+        set_context_free_error("mcinv_features: no such device");
+        return MCINV_EDEVICE;
+    }
+    int64_t *d_beg = nullptr, *d_row = nullptr;
+    int32_t* d_cnt = nullptr;
+    FEnt* d_ent = nullptr;
+    double *d_d = nullptr, *d_F = nullptr;
+    float* d_out = nullptr;
+    hipError_t e = hipSuccess;
+    auto alloc = [&](void** p, size_t bytes) {
+        if (e == hipSuccess) e = hipMalloc(p, bytes > 0 ? bytes : 1);
+    };
+    alloc((void**)&d_beg, sizeof(int64_t) * n);
+    alloc((void**)&d_row, sizeof(int64_t) * n);
+    alloc((void**)&d_cnt, sizeof(int32_t) * n);
+    alloc((void**)&d_ent, sizeof(FEnt) * ent.size());
+    alloc((void**)&d_d, sizeof(double) * n);
+    alloc((void**)&d_F, sizeof(double) * n * kNF);
+    alloc((void**)&d_out, sizeof(float) * n * kNF);
+    if (e == hipSuccess) e = hipMemcpy(d_beg, beg.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_row, h.perm.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_cnt, cnt.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess && !ent.empty())
+        e = hipMemcpy(d_ent, ent.data(), sizeof(FEnt) * ent.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_d, d.data(), sizeof(double) * n, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(d_F, 0, sizeof(double) * n * kNF);
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    if (e == hipSuccess) {
+        k_features_pass1<<<blocks, 256>>>(n, d_beg, d_cnt, d_ent, d_d, d_F);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        k_features_pass2<<<blocks, 256>>>(n, d_beg, d_cnt, d_ent, d_F, d_row, d_out);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipMemcpy(out, d_out, sizeof(float) * n * kNF, hipMemcpyDeviceToHost);
+    (void)hipFree(d_beg);
+    (void)hipFree(d_row);
+    (void)hipFree(d_cnt);
+    (void)hipFree(d_ent);
+    (void)hipFree(d_d);
+    (void)hipFree(d_F);
+    (void)hipFree(d_out);
+    if (e != hipSuccess) {
+        set_context_free_error(std::string("mcinv_features: ") + hipGetErrorString(e));
+        return e == hipErrorOutOfMemory ? MCINV_ENOMEM : MCINV_EDEVICE;
+    }
+    return MCINV_OK;
+}

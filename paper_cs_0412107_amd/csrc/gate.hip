@@ -1,0 +1,137 @@
+// The surrogate's gate: which rows may take the network's prediction of
+// c_ii (C^-1)_ii and which go back to the sampler (eq 1/C).
+//
+// Fit: rows of validation matrices with sampler labels y (and their standard
+// errors) are binned on two features, each by its quantile edges (the sorted
+// values at floor(k N / bins), k = 1..bins-1; bin = number of edges <= x).  A
+// bin's validated relative error is sqrt(max(sum r^2 - sum s^2, 0) / count)
+// with r = (pred - y) / y and s = se / y: the observed spread less the part
+// the label noise explains.  A bin needs the sampler when it holds fewer than
+// min_rows rows or its error exceeds tol.  Host code, float64, rows summed in
+// order.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mcinv.h"
+
+struct mcinv_gate {
+    mcinv_gate_config cfg{};
+    std::vector<double> ea, eb, err;
+    std::vector<int64_t> count;
+    std::vector<uint8_t> fallback;
+};
+
+namespace {
+
+void set_err(const std::string& m);
+
+std::vector<double> quantile_edges(const float* X, int64_t N, int32_t f, int32_t bins)
+{
+    std::vector<double> v(N);
+    for (int64_t i = 0; i < N; ++i) v[i] = (double)X[i * MCINV_N_FEATURES + f];
+    std::sort(v.begin(), v.end());
+    std::vector<double> e(bins - 1);
+    for (int32_t k = 1; k < bins; ++k) e[k - 1] = v[(size_t)(((int64_t)k * N) / bins)];
+    return e;
+}
+
+int64_t bin_of(const std::vector<double>& edges, double x)
+{
+    return std::upper_bound(edges.begin(), edges.end(), x) - edges.begin();
+}
+
+thread_local std::string g_gerr;
+void set_err(const std::string& m) { g_gerr = m; }
+
+}  // namespace
+
+extern "C" {
+
+mcinv_status mcinv_gate_fit(const mcinv_gate_config* cfg, int64_t N, const float* X, const double* pred,
+                            const double* y, const double* y_se, mcinv_gate** out)
+{
+    if (!cfg || !X || !pred || !y || !y_se || !out || N < 1) {
+        set_err("mcinv_gate_fit: null argument or no rows");
+        return MCINV_EINVAL;
+    }
+    *out = nullptr;
+    if (cfg->feature_a < 0 || cfg->feature_a >= MCINV_N_FEATURES || cfg->feature_b < 0 ||
+        cfg->feature_b >= MCINV_N_FEATURES || cfg->bins < 1 || cfg->bins > 256 || cfg->min_rows < 0 ||
+        !(cfg->tol >= 0.0)) {
+        set_err("mcinv_gate_fit: bad configuration");
+        return MCINV_EINVAL;
+    }
+    for (int64_t i = 0; i < N; ++i)
+        if (!std::isfinite(X[i * MCINV_N_FEATURES + cfg->feature_a]) ||
+            !std::isfinite(X[i * MCINV_N_FEATURES + cfg->feature_b]) || !(y[i] != 0.0) || !std::isfinite(y[i])) {
+            set_err("mcinv_gate_fit: non-finite binning feature or zero / non-finite label at row " +
+                    std::to_string(i));
+            return MCINV_EINVAL;
+        }
+    mcinv_gate* g = new mcinv_gate();
+    g->cfg = *cfg;
+    const int32_t B = cfg->bins;
+    g->ea = quantile_edges(X, N, cfg->feature_a, B);
+    g->eb = quantile_edges(X, N, cfg->feature_b, B);
+    std::vector<double> r2((size_t)B * B, 0.0), s2((size_t)B * B, 0.0);
+    g->count.assign((size_t)B * B, 0);
+    for (int64_t i = 0; i < N; ++i) {
+        const int64_t b = bin_of(g->ea, X[i * MCINV_N_FEATURES + cfg->feature_a]) * B +
+                          bin_of(g->eb, X[i * MCINV_N_FEATURES + cfg->feature_b]);
+        const double r = (pred[i] - y[i]) / y[i], s = y_se[i] / y[i];
+        g->count[b] += 1;
+        r2[b] += r * r;
+        s2[b] += s * s;
+    }
+    g->err.assign((size_t)B * B, INFINITY);
+    g->fallback.assign((size_t)B * B, 1);
+    for (size_t b = 0; b < g->err.size(); ++b) {
+        if (g->count[b] > 0) g->err[b] = std::sqrt(std::max(r2[b] - s2[b], 0.0) / (double)g->count[b]);
+        g->fallback[b] = (g->count[b] < cfg->min_rows || !(g->err[b] <= cfg->tol)) ? 1 : 0;
+    }
+    *out = g;
+    return MCINV_OK;
+}
+
+mcinv_status mcinv_gate_apply(const mcinv_gate* g, int64_t N, const float* X, uint8_t* fallback)
+{
+    if (!g || (N > 0 && (!X || !fallback)) || N < 0) {
+        set_err("mcinv_gate_apply: bad arguments");
+        return MCINV_EINVAL;
+    }
+    const int32_t B = g->cfg.bins;
+    for (int64_t i = 0; i < N; ++i) {
+        const double xa = X[i * MCINV_N_FEATURES + g->cfg.feature_a];
+        const double xb = X[i * MCINV_N_FEATURES + g->cfg.feature_b];
+        if (std::isnan(xa) || std::isnan(xb)) {
+            fallback[i] = 1;
+            continue;
+        }
+        fallback[i] = g->fallback[(size_t)(bin_of(g->ea, xa) * B + bin_of(g->eb, xb))];
+    }
+    return MCINV_OK;
+}
+
+mcinv_status mcinv_gate_read(const mcinv_gate* g, double* edges_a, double* edges_b, double* bin_err,
+                             int64_t* bin_count, uint8_t* bin_fallback)
+{
+    if (!g) {
+        set_err("mcinv_gate_read: null gate");
+        return MCINV_EINVAL;
+    }
+    if (edges_a) std::memcpy(edges_a, g->ea.data(), sizeof(double) * g->ea.size());
+    if (edges_b) std::memcpy(edges_b, g->eb.data(), sizeof(double) * g->eb.size());
+    if (bin_err) std::memcpy(bin_err, g->err.data(), sizeof(double) * g->err.size());
+    if (bin_count) std::memcpy(bin_count, g->count.data(), sizeof(int64_t) * g->count.size());
+    if (bin_fallback) std::memcpy(bin_fallback, g->fallback.data(), g->fallback.size());
+    return MCINV_OK;
+}
+
+void mcinv_gate_destroy(mcinv_gate* g) { delete g; }
+
+const char* mcinv_gate_last_error(void) { return g_gerr.c_str(); }
+
+}  // extern "C"

@@ -59,6 +59,7 @@ struct FinalizeArgs {
     double* est;             // [M][comps] (at out_index)
     double* se;              // [M]
     unsigned long long* max_rel;  // diag only, may be null: max se/|est| as bits
+    const uint8_t* stop_mask;     // diag only, may be null: rows (output index) that max_rel covers
 };
 hipError_t launch_finalize_diag(const FinalizeArgs& f, hipStream_t stream);
 hipError_t launch_finalize_flat(const FinalizeArgs& f, hipStream_t stream);

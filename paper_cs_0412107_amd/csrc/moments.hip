@@ -266,11 +266,12 @@ __global__ __launch_bounds__(64) void k_finalize_diag(const FinalizeArgs f)
         ++nc;
     }
     const int64_t out = f.out_index[q];
+    const bool stop_row = f.max_rel != nullptr && (f.stop_mask == nullptr || f.stop_mask[out] != 0);
     if (wsum <= 0.0) {
         f.est[out * f.comps] = __builtin_nan("");
         if (f.comps == 2) f.est[out * 2 + 1] = __builtin_nan("");
         f.se[out] = __builtin_nan("");
-        if (f.max_rel) atomicMax(f.max_rel, (unsigned long long)__double_as_longlong(__builtin_inf()));
+        if (stop_row) atomicMax(f.max_rel, (unsigned long long)__double_as_longlong(__builtin_inf()));
         return;
     }
     er /= wsum;
@@ -299,7 +300,7 @@ __global__ __launch_bounds__(64) void k_finalize_diag(const FinalizeArgs f)
     f.est[out * f.comps] = er;
     if (f.comps == 2) f.est[out * 2 + 1] = ei;
     f.se[out] = se;
-    if (f.max_rel != nullptr) {
+    if (stop_row) {
         double rel = se / sqrt(er * er + ei * ei);
         if (!(rel >= 0.0) || !(rel < __builtin_inf())) rel = __builtin_inf();
         atomicMax(f.max_rel, (unsigned long long)__double_as_longlong(rel));

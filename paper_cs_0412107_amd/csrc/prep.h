@@ -37,6 +37,7 @@ struct Prepared {
     std::vector<RowRec> rows;       // per position; begin relative to this matrix
     std::vector<MergedEntry> ent;   // per position, columns ascending
     std::vector<cd> a, b;           // per position
+    std::vector<cd> diag;           // c_ii per position
 };
 
 // Returns an empty string on success, else the reason; *singular is set when
@@ -142,6 +143,7 @@ inline std::string prepare_matrix(int64_t n, int64_t nnz, const int64_t* row_ptr
     h.rows.assign(n, RowRec{});
     h.a.assign(n, cd());
     h.b.assign(n, cd());
+    h.diag.assign(n, cd());
     h.ent.clear();
     h.ent.reserve(mcol.size());
     for (int64_t q = 0; q < n; ++q) {
@@ -154,6 +156,7 @@ inline std::string prepare_matrix(int64_t n, int64_t nnz, const int64_t* row_ptr
         std::sort(h.ent.begin() + first, h.ent.end(),
                   [](const MergedEntry& x, const MergedEntry& y) { return x.col < y.col; });
         const cd d = diag[i];
+        h.diag[q] = d;
         if (!complex_values) {
             const double s = 1.0 / std::sqrt(std::fabs(d.real()));
             h.a[q] = cd(s, 0.0);
@@ -169,6 +172,9 @@ inline std::string prepare_matrix(int64_t n, int64_t nnz, const int64_t* row_ptr
     h.color_ptr = std::move(color_ptr);
     return "";
 }
+
+// Message returned by mcinv_last_error(NULL) (entry points without a context).
+void set_context_free_error(const std::string& msg);
 
 template <typename V> V cast_val(cd x);
 template <> inline float cast_val<float>(cd x) { return (float)x.real(); }

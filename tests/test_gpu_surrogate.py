@@ -1,0 +1,205 @@
+"""Learned surrogate on the GPU against the oracle: the feature kernels
+(fp64, element by element), the network's forward pass, its gradients and a
+few Adam steps (bf16 operands at the documented rounding points on both
+sides), the normalisation fit, and an end-to-end check that training lowers
+the held-out error below the Neumann baselines and that the gate's sampler
+fallback meets the tolerance on the rows it covers."""
+
+import numpy as np
+import pytest
+
+import gen
+from gpu_util import print_case
+from oracle import surrogate as S
+
+pytestmark = pytest.mark.gpu
+
+mc = pytest.importorskip("paper_cs_0412107_amd")
+from paper_cs_0412107_amd import surrogate as sur  # noqa: E402
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _odd_matrix():
+    """Small matrix with an isolated row, one-sided entries and negative diagonals."""
+    rng = np.random.default_rng(3)
+    n = 90
+    A = rng.uniform(-1, 1, (n, n)) * (rng.random((n, n)) < 0.06)
+    np.fill_diagonal(A, 0)
+    A[7, :] = 0
+    A[:, 7] = 0
+    d = 1.4 * np.maximum(np.abs(A).sum(axis=1), np.abs(A).sum(axis=0)) + 0.3
+    d *= np.where(rng.random(n) < 0.3, -1.0, 1.0)
+    A[np.diag_indices(n)] = d
+    return gen.from_dense(A)
+
+
+@pytest.mark.parametrize("case", ["pedigree", "random", "odd"])
+def test_features_match_oracle(case):
+    print_case(test="features", case=case)
+    m = {"pedigree": lambda: gen.pedigree(3001, seed=41, lam=0.3, founders=0.1),
+         "random": lambda: gen.random_dominant(1000, 4, seed=42, factor=1.3),
+         "odd": _odd_matrix}[case]()
+    got = sur.features(m)
+    ref = S.features(m)
+    assert got.shape == (m.n, 32) and got.dtype == np.float32
+    # fp64 on both sides, rounded once to float32
+    np.testing.assert_allclose(got, ref.astype(np.float32), rtol=2e-7, atol=1e-9)
+
+
+def test_features_errors():
+    m = gen.diag_matrix(np.array([1.0, 0.0, 2.0]))
+    with pytest.raises(mc.McinvError) as ei:
+        sur.features(m)
+    assert ei.value.code == mc.MCINV_ESINGULAR
+
+
+def _net_case(seed, N):
+    rng = np.random.default_rng(seed)
+    p = S.init_params(seed)
+    p["b1"] = rng.uniform(-0.5, 0.5, 128)
+    p["b2"] = rng.uniform(-0.5, 0.5, 128)
+    X = (rng.standard_normal((N, 32)) * rng.uniform(0.1, 3, 32) + rng.uniform(-2, 2, 32)).astype(np.float32)
+    X[:, 31] = 1.0
+    mean, inv = S.fit_normalization(X)
+    y = (1 + 0.2 * rng.standard_normal(N)).astype(np.float32)
+    w = S.label_weights(rng.uniform(0.001, 0.01, N)).astype(np.float32)
+    return p, X, y, w, mean, inv
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+@pytest.mark.parametrize("N", [1000, 64, 5])
+def test_forward_matches_oracle(N):
+    print_case(test="mlp_forward", N=N)
+    p, X, y, w, mean, inv = _net_case(11, N)
+    with sur.Network(params=S.flatten(p)) as net:
+        net.set_normalization(mean, inv)
+        out = net.predict(X)
+    ref, _ = S.mlp_forward(S.unflatten(S.flatten(p).astype(np.float32)), S.normalize(X, mean, inv))
+    err = np.abs(out - ref)
+    # fp32 accumulation (~1e-6) plus rare one-ulp bf16 flips of a hidden activation
+    assert np.max(err) <= 5e-4 and np.quantile(err, 0.99) <= 2e-5, (np.max(err), np.quantile(err, 0.99))
+
+
+def test_fit_normalization_and_weights_match_oracle():
+    p, X, y, w, mean, inv = _net_case(12, 3000)
+    with sur.Network(params=S.flatten(p)) as net:
+        gm, gi = net.set_data(X, y, w, normalize=True)
+    np.testing.assert_allclose(gm, mean, rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(gi, inv, rtol=1e-6)
+    se = np.random.default_rng(1).uniform(0.0, 0.02, 500)
+    np.testing.assert_allclose(mc.mcinv_mlp_label_weights(se, 1e-6), S.label_weights(se, 1e-6), rtol=1e-6)
+
+
+@pytest.mark.parametrize("R", [256, 64])
+def test_gradients_match_oracle(R):
+    print_case(test="mlp_gradients", R=R)
+    p, X, y, w, mean, inv = _net_case(13, 1000)
+    rows = np.random.default_rng(5).integers(0, 1000, R)
+    p32 = S.unflatten(S.flatten(p).astype(np.float32))
+    with sur.Network(params=S.flatten(p)) as net:
+        net.set_data(X, y, w, normalize=False)
+        net.set_normalization(mean, inv)
+        g, loss = net.gradients(rows)
+    Xn = S.normalize(X[rows], mean, inv)
+    ref = S.mlp_grads(p32, Xn, y[rows].astype(np.float64), w[rows].astype(np.float64), bf16_ops=True,
+                      denom=float(R))
+    rloss = S.mlp_loss(p32, Xn, y[rows].astype(np.float64), w[rows].astype(np.float64), denom=float(R))
+    gd = S.unflatten(g)
+    for k in S.ORDER:
+        assert _rel(gd[k], ref[k]) <= 2e-3, (k, _rel(gd[k], ref[k]))
+    assert abs(loss - rloss) <= 1e-4 * rloss
+
+
+def test_adam_steps_match_oracle():
+    """Three Adam steps on Philox-drawn batches.  The first Adam step moves each
+    weight by about lr * sign(g), so weights whose gradient is near zero may move
+    either way: those are checked against Adam's step bound only."""
+    print_case(test="mlp_train")
+    p, X, y, w, mean, inv = _net_case(14, 777)
+    steps, R, lr, seed = 3, 128, 1e-3, 0xC0FFEE
+    p0 = S.flatten(p).astype(np.float32)
+    with sur.Network(params=p0) as net:
+        net.set_data(X, y, w, normalize=False)
+        net.set_normalization(mean, inv)
+        hist = net.train(steps, R, lr, seed)
+        got = net.params().astype(np.float64)
+    ref = S.unflatten(p0)
+    st = {}
+    losses = []
+    for t in range(1, steps + 1):
+        rows = S.batch_rows(seed, t, 777, R)
+        Xn = S.normalize(X[rows], mean, inv)
+        yy, ww = y[rows].astype(np.float64), w[rows].astype(np.float64)
+        losses.append(S.mlp_loss(ref, Xn, yy, ww, denom=float(R)))
+        g = S.mlp_grads(ref, Xn, yy, ww, bf16_ops=True, denom=float(R))
+        ref = S.adam_step(ref, g, st, lr)
+    np.testing.assert_allclose(hist, losses, rtol=2e-4)
+    d_got = got - p0
+    d_ref = S.flatten(ref) - p0
+    diff = np.abs(d_got - d_ref)
+    assert np.max(np.abs(d_got)) <= steps * lr * 1.01
+    assert np.mean(diff <= 0.05 * lr) >= 0.99, np.mean(diff <= 0.05 * lr)
+
+
+def test_train_errors():
+    with sur.Network() as net:
+        with pytest.raises(mc.McinvError) as ei:
+            net.train(1, 128)
+        assert ei.value.code == mc.MCINV_ESTATE
+        net.set_data(np.zeros((10, 32), np.float32), np.ones(10, np.float32), np.ones(10, np.float32))
+        with pytest.raises(mc.McinvError) as ei:
+            net.train(1, 100)
+        assert ei.value.code == mc.MCINV_EINVAL
+        with pytest.raises(mc.McinvError):
+            net.gradients(np.array([0, 1, 2, 10] * 16))
+
+
+def _exact_labels(m):
+    A = gen.to_dense(m).real
+    return np.diag(A) * np.diag(np.linalg.inv(A))
+
+
+def test_training_beats_neumann_baselines_and_gate_falls_back():
+    print_case(test="surrogate_end_to_end")
+    params = gen.surrogate_params(10, seed=2024)
+    mats = [gen.pedigree(1200, seed=q["seed"], founders=q["founders"], lam=q["lam"], factor=q["factor"])
+            for q in params]
+    F = [sur.features(m) for m in mats]
+    Y = [_exact_labels(m) for m in mats]
+    Xtr, ytr = np.concatenate(F[:7]), np.concatenate(Y[:7])
+    with sur.Network(seed=3) as net:
+        net.set_data(Xtr, ytr, np.ones(ytr.size, np.float32))
+        hist = net.train(600, 1024, 2e-3, 5)
+        assert hist[-20:].mean() < 0.2 * hist[:5].mean()
+        Xv, yv = np.concatenate(F[7:9]), np.concatenate(Y[7:9])
+        pv = net.predict(Xv).astype(np.float64)
+        err_net = np.sqrt(np.mean(((pv - yv) / yv) ** 2))
+        err_n2 = np.sqrt(np.mean(((Xv[:, 25] - yv) / yv) ** 2))
+        err_jac = np.sqrt(np.mean(((1.0 - yv) / yv) ** 2))
+        assert err_net < err_n2 < err_jac, (err_net, err_n2, err_jac)
+        # gate on validation (exact labels: zero label error), then the held-out matrix
+        gate = sur.Gate(Xv, pv, yv, np.zeros_like(yv), feature_a=1, feature_b=5, bins=4, min_rows=20,
+                        tol=0.005)
+        m = mats[9]
+        est, src, info = sur.estimate_diag(
+            m, net, gate, lambda mm: mc.Sampler(mm, pairs=256, groups=16, dtype="f32", seed=9),
+            rel_se=0.02, max_sweeps=4000, check_every=20, burn_in=100)
+        exact = Y[9] / np.diag(gen.to_dense(m).real)
+        rel = np.abs(est - exact) / np.abs(exact)
+        if src.any():
+            assert info["achieved"] <= 0.02
+            assert np.quantile(rel[src == 1], 0.99) <= 0.1   # sampler rows: within a few SE
+        acc = src == 0
+        assert np.all(gate.fallback(F[9]) == src.astype(bool))
+        if acc.any():
+            assert np.sqrt(np.mean(rel[acc] ** 2)) <= 0.02
+        gate.close()
