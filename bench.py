@@ -69,19 +69,28 @@ def profiled_traffic(workload):
     return float(vals["traffic_bytes_per_launch"])
 
 
+BURN_TOL = 5e-5   # coupling tolerance of the paper's numerical tests
+
+
 def time_to_1pct(pkg, torch, m, P, G, seed, dtype, moments, burn_in, rel=0.01, check=10, max_sweeps=20000):
     """Wall time from a fresh context to max_i SE_i/|est_i| <= rel on the whole
-    diagonal: fixed burn-in, then sampling checked every `check` sweeps."""
+    diagonal: burn-in (a fixed count, or "coupled": until the coupled paths
+    agree to BURN_TOL), then sampling checked every `check` sweeps."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s = pkg.Sampler(m, pairs=P, groups=G, dtype=dtype, seed=seed, moments=moments, use_torch_stream=True)
-    s.burn_in(burn_in)
+    if burn_in == "coupled":
+        nb, _, _ = s.burn_in_coupled(BURN_TOL, 10000)
+        burn_desc = f"coupled to {BURN_TOL:g}"
+    else:
+        s.burn_in(burn_in)
+        nb, burn_desc = burn_in, "fixed"
     s.request(diag=True, trace=False)
     done, ach = s.sample_until(rel, max_sweeps, check)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     s.close()
-    return {"seconds": t, "burn_in": burn_in, "sample_sweeps": done, "max_rel_se": ach,
+    return {"seconds": t, "burn_in": nb, "burn_in_rule": burn_desc, "sample_sweeps": done, "max_rel_se": ach,
             "form": f"{dtype} sweeps, {moments} blocks"}
 
 
@@ -143,6 +152,115 @@ def batched_forms(pkg, torch, gen, rel=0.01, check=10):
                                    "autotuned schedule"}}
 
 
+MLP_FLOP_PER_ROW_STEP = 2 * (32 * 128 + 128 * 128 + 128) + 2 * (2 * 128 + 2 * 128 * 128 + 32 * 128)
+
+
+def surrogate_form(pkg, torch, gen, n_train, n_val, rel_label=0.005, rel=0.01, steps=2000, batch=16384):
+    """Learned-surrogate workload: pedigree matrices with random generator
+    parameters (n = 2e4) labelled by the batched sampler to rel_label, 32
+    features per row, the network trained on the labelled rows, a gate fitted
+    on validation matrices, then a held-out matrix (n = 1e6): surrogate plus
+    sampler fallback versus the plain sampler to 1% on every row."""
+    from paper_cs_0412107_amd import surrogate as sur
+    w = gen.WORKLOADS["surrogate"]
+    qs = gen.surrogate_params(n_train + n_val + 1, seed=w["seed"])
+
+    def make(q, n):
+        return gen.round_values(gen.pedigree(n, seed=q["seed"], founders=q["founders"], lam=q["lam"],
+                                             factor=q["factor"]), np.float32)
+
+    t0 = time.perf_counter()
+    mats = [make(q, w["train_n"]) for q in qs[:n_train + n_val]]
+    log(f"surrogate: {len(mats)} matrices generated in {time.perf_counter() - t0:.1f} s; labelling ...")
+    bw = gen.WORKLOADS["batched"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b = pkg.BatchSampler(mats, pairs=bw["pairs"], groups=bw["groups"], seed=w["noise_seed"], use_torch_stream=True)
+    b.autotune(1)
+    b.burn_in(bw["burn_in"])
+    b.request(diag=True)
+    lab_sweeps, lab_ach = b.sample_until(rel_label, 40000, 50)
+    torch.cuda.synchronize()
+    t_label = time.perf_counter() - t0
+    Y, YSE = [], []
+    for j, x in enumerate(mats):
+        est, se = b.diag(j)
+        y, yse = sur.labels_from_estimates(x, est, se)
+        Y.append(y)
+        YSE.append(yse)
+    b.close()
+    log(f"surrogate: labels in {t_label:.1f} s ({lab_sweeps} sample sweeps, max rel SE {lab_ach:.4f}); features ...")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F = [sur.features(x) for x in mats]
+    t_feat = time.perf_counter() - t0
+    Xtr, ytr, setr = np.concatenate(F[:n_train]), np.concatenate(Y[:n_train]), np.concatenate(YSE[:n_train])
+    Xv, yv, sev = np.concatenate(F[n_train:]), np.concatenate(Y[n_train:]), np.concatenate(YSE[n_train:])
+    net = sur.Network(seed=w["seed"])
+    net.set_data(Xtr, ytr, pkg.mcinv_mlp_label_weights(setr))
+    net.train(20, batch, 1e-3, 1)  # warm-up (part of the training)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist = net.train(steps, batch, 1e-3, 2)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    pv = net.predict(Xv).astype(np.float64)
+    rv = (pv - yv) / yv
+    gate = sur.Gate(Xv, pv, yv, sev, feature_a=1, feature_b=5, bins=8, min_rows=200, tol=rel)
+    log(f"surrogate: trained {steps} steps x {batch} rows in {t_train:.2f} s; held-out matrix ...")
+
+    m = make(qs[-1], w["eval_n"])
+    P, G = 1024, 16
+    plain = time_to_1pct(pkg, torch, m, P, G, w["noise_seed"] + 1, "f32", "fp64", "coupled", rel=rel)
+    burn = plain["burn_in"]
+    with pkg.Sampler(m, pairs=P, groups=G, dtype="f32", seed=w["noise_seed"] + 1) as s:
+        s.burn_in(burn)
+        s.request(diag=True, trace=False)
+        s.sample(plain["sample_sweeps"])
+        d_plain, se_plain = s.diag()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    est, src, info = sur.estimate_diag(
+        m, net, gate, lambda mm: pkg.Sampler(mm, pairs=P, groups=G, dtype="f32", seed=w["noise_seed"] + 1,
+                                             use_torch_stream=True),
+        rel_se=rel, max_sweeps=20000, check_every=10, burn_in="coupled")
+    torch.cuda.synchronize()
+    t_sur = time.perf_counter() - t0
+    acc = src == 0
+    r = (est - d_plain) / d_plain
+    s_rel = se_plain / np.abs(d_plain)
+    net.close()
+    gate_tab = gate.table()
+    gate.close()
+    return {
+        "workload": f"{n_train} train + {n_val} validation pedigree matrices (n={w['train_n']}, random "
+                    f"dominance 1.2-2.0, lambda 0-0.5, founders 2-20%), held-out n={m.n}",
+        "labels": {"seconds": t_label, "sample_sweeps": lab_sweeps, "max_rel_se": lab_ach,
+                   "rows": int(sum(x.n for x in mats)), "form": "batched sampler, 64 pairs per matrix"},
+        "features": {"seconds": t_feat, "rows": int(sum(x.n for x in mats)),
+                     "rows_per_s": sum(x.n for x in mats) / t_feat, "note": "host preparation included"},
+        "training": {"seconds": t_train, "steps": steps, "batch_rows": batch,
+                     "rows_per_s": steps * batch / t_train,
+                     "TFLOPs": MLP_FLOP_PER_ROW_STEP * steps * batch / t_train / 1e12,
+                     "mfma_frac_bf16_peak": MLP_FLOP_PER_ROW_STEP * steps * batch / t_train / 2.5e15,
+                     "loss_first": float(hist[0]), "loss_last": float(hist[-1])},
+        "validation": {"rms_rel_err": float(np.sqrt(np.mean(rv ** 2))),
+                       "rms_rel_err_neumann2": float(np.sqrt(np.mean(((Xv[:, 25] - yv) / yv) ** 2))),
+                       "rms_rel_err_jacobi": float(np.sqrt(np.mean(((1.0 - yv) / yv) ** 2))),
+                       "gate_bins_fallback": int(gate_tab["fallback"].sum()),
+                       "gate_bins": int(gate_tab["fallback"].size)},
+        "held_out": {"n": int(m.n), "plain_seconds": plain["seconds"],
+                     "plain_sample_sweeps": plain["sample_sweeps"], "surrogate_seconds": t_sur,
+                     "speedup_vs_plain": plain["seconds"] / t_sur,
+                     "accepted_rows": int(acc.sum()), "fallback_rows": int((~acc).sum()),
+                     "fallback_sweeps": info["sweeps"],
+                     "accepted_rms_rel_diff_vs_plain": float(np.sqrt(np.mean(r[acc] ** 2))) if acc.any() else None,
+                     "accepted_model_err_est": float(np.sqrt(max(np.mean(r[acc] ** 2) - np.mean(s_rel[acc] ** 2),
+                                                                 0.0))) if acc.any() else None,
+                     "plain_pairs": P},
+    }
+
+
 def cpu_baseline(m, seed, P, G, budget_s):
     """The oracle (single-threaded C, fp64) on a bounded sample of the same
     workload: a few chain pairs, as many sweeps as fit the time budget."""
@@ -170,6 +288,10 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-1%% phase")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form comparison")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate form")
+    ap.add_argument("--surrogate-train", type=int, default=192,
+                    help="training matrices of the surrogate form (the full workload has 2000)")
+    ap.add_argument("--surrogate-val", type=int, default=32)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (scale for HBM counters)")
     args = ap.parse_args()
@@ -269,13 +391,20 @@ def main():
                                                "f64", "fp64", w["burn_in"])
         forms["precision"] = time_to_1pct(pkg, torch, m, P, G, seed + 1, dtype,
                                           "bf16x3" if dtype == "f32" else "fp64", w["burn_in"])
+        forms["precision_coupled"] = time_to_1pct(pkg, torch, m, P, G, seed + 1, dtype,
+                                                  "bf16x3" if dtype == "f32" else "fp64", "coupled")
         if "plain_fp64" in forms:
-            forms["precision"]["speedup_vs_plain"] = forms["plain_fp64"]["seconds"] / forms["precision"]["seconds"]
-        log(f"time to 1%: {forms['precision']['seconds']:.2f} s")
+            for k in ("precision", "precision_coupled"):
+                forms[k]["speedup_vs_plain"] = forms["plain_fp64"]["seconds"] / forms[k]["seconds"]
+        log(f"time to 1%: {forms['precision']['seconds']:.2f} s (burn-in {w['burn_in']}), "
+            f"{forms['precision_coupled']['seconds']:.3f} s (coupled burn-in, "
+            f"{forms['precision_coupled']['burn_in']} sweeps)")
         if args.workload == "pedigree" and not args.no_batched:
             forms["batched"] = batched_forms(pkg, torch, gen)
+        if args.workload == "pedigree" and not args.no_surrogate:
+            forms["surrogate"] = surrogate_form(pkg, torch, gen, args.surrogate_train, args.surrogate_val)
         result["forms"] = forms
-        result["time_to_1pct"] = forms["precision"]
+        result["time_to_1pct"] = forms["precision_coupled"]
 
     if args.copy_calibration:
         nbytes = 1 << 30

@@ -177,6 +177,20 @@ mcinv_status mcinv_write_state(mcinv_ctx* ctx, int32_t which, const void* host, 
  * color_of_row[i] = colour of original row i (int32[n]).  Either may be NULL. */
 mcinv_status mcinv_get_permutation(mcinv_ctx* ctx, int64_t* perm, int32_t* color_of_row);
 
+/* Burn-in by coupling (Sec. 2.3, Algorithm 1 steps 1-5): a second path per
+ * chain started at x*_i = i (1-based original index) and driven by the same
+ * noise is run until both coupled differences, max_i |z_i - z*_i| and
+ * max_i |w_i - w*_i|, are below tol (the paper uses 5e-5).  By eq 12 the
+ * difference of two such paths is the noiseless Gauss-Seidel iteration on
+ * C d = 0 (z) and C^dagger d = 0 (w), identical for every chain pair, so the
+ * library runs that one iteration (in the sweep precision), checks it after
+ * every sweep, and then advances the chains by the same number N of noisy
+ * sweeps: the chains end exactly as after mcinv_burn_in(ctx, N).  Stops at
+ * max_sweeps if the tolerance is not reached (*diff_z / *diff_w tell).
+ * EDIVERGED when the difference becomes non-finite.  Outputs may be NULL. */
+mcinv_status mcinv_burn_in_coupled(mcinv_ctx* ctx, double tol, int64_t max_sweeps, int64_t* sweeps_done,
+                                   double* diff_z, double* diff_w);
+
 /* Noiseless sweeps from x_i = i (Algorithm 1's second start) on C x = 0 and
  * C^dagger y = 0: the Gauss-Seidel iterations eq 12 shows the chain
  * difference obeys.  Returns the observed contraction rates, which tend to

@@ -129,6 +129,30 @@ class OracleError(RuntimeError):
     pass
 
 
+def coupled_burn_in(m, seed, tol, max_sweeps, order=None, stream=0, noise_kind=NOISE_NORMAL, pair_ids=(0,)):
+    """Algorithm 1, steps 1-5, literally: paths started at z = w = 0 and at
+    z* = w* = i (1-based index), driven by the same noise, swept together
+    until max_i |z_i - z*_i| < tol and max_i |w_i - w*_i| < tol.  Returns the
+    number of sweeps N and the differences after each sweep."""
+    if order is None:
+        _, order, _ = greedy_color(m)
+    a = Run(m, seed, pairs=len(pair_ids), pair_ids=pair_ids, order=order, stream=stream, noise_kind=noise_kind)
+    b = Run(m, seed, pairs=len(pair_ids), pair_ids=pair_ids, order=order, stream=stream, noise_kind=noise_kind)
+    start = np.arange(1, m.n + 1, dtype=np.float64)[:, None]
+    b.z[:] = start
+    b.w[:] = start
+    diffs = []
+    for k in range(1, max_sweeps + 1):
+        a.burn_in(1)
+        b.burn_in(1)
+        dz = float(np.max(np.abs(b.z - a.z)))
+        dw = float(np.max(np.abs(b.w - a.w)))
+        diffs.append((dz, dw))
+        if dz < tol and dw < tol:
+            return k, diffs
+    return max_sweeps, diffs
+
+
 class Run:
     """One oracle run: ``pairs`` chain pairs (global ids ``pair_ids``) of the
     correlated-chains sampler on matrix ``m``.

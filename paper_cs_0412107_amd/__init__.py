@@ -85,6 +85,11 @@ class Sampler:
     def burn_in(self, sweeps):
         mcinv_burn_in(self.ctx, sweeps)
 
+    def burn_in_coupled(self, tol=5e-5, max_sweeps=10000):
+        """Burn in until the coupled paths agree to tol; returns (sweeps, diff_z, diff_w)."""
+        from ._binding import mcinv_burn_in_coupled
+        return mcinv_burn_in_coupled(self.ctx, tol, max_sweeps)
+
     def sample(self, sweeps):
         mcinv_sample(self.ctx, sweeps)
 

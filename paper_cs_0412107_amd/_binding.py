@@ -119,6 +119,7 @@ SIGNATURES = {
     "mcinv_load_csr": (_I32, [_P, _I64, _I64, _P, _P, _P, _I32]),
     "mcinv_set_requested": (_I32, [_P, _U32, _P, _I64, _P, _I64, _P, _P, _I64]),
     "mcinv_burn_in": (_I32, [_P, _I64]),
+    "mcinv_burn_in_coupled": (_I32, [_P, _D, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "mcinv_sample": (_I32, [_P, _I64]),
     "mcinv_sample_until": (_I32, [_P, _D, _I64, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_D)]),
     "mcinv_read_estimates": (_I32, [_P, _U32, _P, _P, _I64]),
@@ -236,6 +237,15 @@ def mcinv_set_requested(ctx, flags, block_rows=None, block_cols=None, entry_i=No
 
 def mcinv_burn_in(ctx, sweeps):
     _check(ctx, lib().mcinv_burn_in(ctx, int(sweeps)))
+
+
+def mcinv_burn_in_coupled(ctx, tol=5e-5, max_sweeps=10000):
+    n = ctypes.c_int64(0)
+    dz = ctypes.c_double(0)
+    dw = ctypes.c_double(0)
+    _check(ctx, lib().mcinv_burn_in_coupled(ctx, float(tol), int(max_sweeps), ctypes.byref(n), ctypes.byref(dz),
+                                            ctypes.byref(dw)))
+    return n.value, dz.value, dw.value
 
 
 def mcinv_sample(ctx, sweeps):

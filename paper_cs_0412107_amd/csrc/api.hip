@@ -874,19 +874,19 @@ mcinv_status mcinv_get_permutation(mcinv_ctx* c, int64_t* perm, int32_t* color_o
     return MCINV_OK;
 }
 
-mcinv_status mcinv_check_convergence(mcinv_ctx* c, int64_t iters, double* rho_T, double* rho_S)
+// The difference of two coupled paths (same noise, starts 0 and x*_i = i,
+// 1-based original index: Algorithm 1, step 1) obeys eq 12: noiseless
+// Gauss-Seidel sweeps on C d = 0 (z) and C^dagger d = 0 (w), the same for
+// every chain pair.  Allocates the two [n][ld] difference chains holding x*.
+mcinv_status coupled_start(mcinv_ctx* c, int64_t ld, void** zc, void** wc, int32_t** fl)
 {
-    MC_TRY(check_ready(c));
-    if (iters < 2) return fail(c, MCINV_EINVAL, "iters must be >= 2");
-    const int64_t ld = 4;
     const size_t bytes = (size_t)c->n * ld * c->elem;
-    void *zc = nullptr, *wc = nullptr;
-    int32_t* fl = nullptr;
-    HIP_TRY(c, hipMalloc(&zc, bytes));
-    HIP_TRY(c, hipMalloc(&wc, bytes));
-    HIP_TRY(c, hipMalloc((void**)&fl, sizeof(int32_t)));
-    HIP_TRY(c, hipMemsetAsync(fl, 0, sizeof(int32_t), c->stream));
-    // x_i = i (1-based, Algorithm 1's second start) in every lane.
+    *zc = *wc = nullptr;
+    *fl = nullptr;
+    HIP_TRY(c, hipMalloc(zc, bytes));
+    HIP_TRY(c, hipMalloc(wc, bytes));
+    HIP_TRY(c, hipMalloc((void**)fl, sizeof(int32_t)));
+    HIP_TRY(c, hipMemsetAsync(*fl, 0, sizeof(int32_t), c->stream));
     std::vector<char> init(bytes, 0);
     for (int64_t q = 0; q < c->n; ++q)
         for (int64_t p = 0; p < ld; ++p) {
@@ -899,8 +899,105 @@ mcinv_status mcinv_check_convergence(mcinv_ctx* c, int64_t iters, double* rho_T,
                 std::memcpy(dst, &x, sizeof(double));
             }
         }
-    HIP_TRY(c, hipMemcpyAsync(zc, init.data(), bytes, hipMemcpyHostToDevice, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(wc, init.data(), bytes, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(*zc, init.data(), bytes, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(*wc, init.data(), bytes, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return MCINV_OK;
+}
+
+mcinv_status noiseless_sweeps(mcinv_ctx* c, int64_t k, void* zc, void* wc, int64_t ld, int32_t* fl)
+{
+    switch (c->cfg.sweep_dtype) {
+    case MCINV_R32: return run_sweeps<float>(c, k, false, (float*)zc, (float*)wc, ld, 1, MCINV_NOISE_NONE, fl, false);
+    case MCINV_R64: return run_sweeps<double>(c, k, false, (double*)zc, (double*)wc, ld, 1, MCINV_NOISE_NONE, fl, false);
+    case MCINV_C64:
+        return run_sweeps<Cx<float>>(c, k, false, (Cx<float>*)zc, (Cx<float>*)wc, ld, 1, MCINV_NOISE_NONE, fl, false);
+    default:
+        return run_sweeps<Cx<double>>(c, k, false, (Cx<double>*)zc, (Cx<double>*)wc, ld, 1, MCINV_NOISE_NONE, fl,
+                                      false);
+    }
+}
+
+mcinv_status max_abs(mcinv_ctx* c, const void* x, int64_t ld, unsigned long long* out)
+{
+    switch (c->cfg.sweep_dtype) {
+    case MCINV_R32: HIP_TRY(c, launch_max_abs<float>((const float*)x, c->n, ld, out, c->stream)); break;
+    case MCINV_R64: HIP_TRY(c, launch_max_abs<double>((const double*)x, c->n, ld, out, c->stream)); break;
+    case MCINV_C64: HIP_TRY(c, launch_max_abs<Cx<float>>((const Cx<float>*)x, c->n, ld, out, c->stream)); break;
+    default: HIP_TRY(c, launch_max_abs<Cx<double>>((const Cx<double>*)x, c->n, ld, out, c->stream)); break;
+    }
+    return MCINV_OK;
+}
+
+mcinv_status mcinv_burn_in_coupled(mcinv_ctx* c, double tol, int64_t max_sweeps, int64_t* sweeps_done,
+                                   double* diff_z, double* diff_w)
+{
+    MC_TRY(check_ready(c));
+    if (!(tol > 0.0) || max_sweeps < 0) return fail(c, MCINV_EINVAL, "tol must be > 0 and max_sweeps >= 0");
+    const int64_t ld = 4;
+    void *zc = nullptr, *wc = nullptr;
+    int32_t* fl = nullptr;
+    unsigned long long* dmax = nullptr;
+    mcinv_status s = coupled_start(c, ld, &zc, &wc, &fl);
+    if (s == MCINV_OK && hipMalloc((void**)&dmax, 2 * sizeof(unsigned long long)) != hipSuccess)
+        s = fail(c, MCINV_ENOMEM, "device allocation failed");
+    int64_t N = max_sweeps;
+    double dz = INFINITY, dw = INFINITY;
+    for (int64_t k = 1; k <= max_sweeps && s == MCINV_OK; ++k) {
+        if ((s = noiseless_sweeps(c, 1, zc, wc, ld, fl)) != MCINV_OK) break;
+        if (hipMemsetAsync(dmax, 0, 2 * sizeof(unsigned long long), c->stream) != hipSuccess) {
+            s = fail(c, MCINV_EDEVICE, "hipMemsetAsync failed");
+            break;
+        }
+        if ((s = max_abs(c, zc, ld, dmax)) != MCINV_OK || (s = max_abs(c, wc, ld, dmax + 1)) != MCINV_OK) break;
+        unsigned long long bits[2] = {0, 0};
+        if (hipMemcpyAsync(bits, dmax, sizeof(bits), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess) {
+            s = fail(c, MCINV_EDEVICE, "copying the coupling difference failed");
+            break;
+        }
+        std::memcpy(&dz, &bits[0], sizeof(double));
+        std::memcpy(&dw, &bits[1], sizeof(double));
+        if (!std::isfinite(dz) || !std::isfinite(dw)) {
+            s = fail(c, MCINV_EDIVERGED, "coupled paths diverge: the Gauss-Seidel iteration of eq 12 does not "
+                                         "contract (sp(T) or sp(S) >= 1)");
+            break;
+        }
+        if (dz < tol && dw < tol) {
+            N = k;
+            break;
+        }
+    }
+    (void)hipFree(zc);
+    (void)hipFree(wc);
+    (void)hipFree(fl);
+    (void)hipFree(dmax);
+    if (s != MCINV_OK) return s;
+    MC_TRY(dispatch_sweeps(c, N, false));
+    c->sweeps += N;
+    if (sweeps_done) *sweeps_done = N;
+    if (diff_z) *diff_z = dz;
+    if (diff_w) *diff_w = dw;
+    return check_flag(c);
+}
+
+mcinv_status mcinv_check_convergence(mcinv_ctx* c, int64_t iters, double* rho_T, double* rho_S)
+{
+    MC_TRY(check_ready(c));
+    if (iters < 2) return fail(c, MCINV_EINVAL, "iters must be >= 2");
+    const int64_t ld = 4;
+    const size_t bytes = (size_t)c->n * ld * c->elem;
+    void *zc = nullptr, *wc = nullptr;
+    int32_t* fl = nullptr;
+    {
+        const mcinv_status s0 = coupled_start(c, ld, &zc, &wc, &fl);
+        if (s0 != MCINV_OK) {
+            (void)hipFree(zc);
+            (void)hipFree(wc);
+            (void)hipFree(fl);
+            return s0;
+        }
+    }
     std::vector<char> host(bytes);
     auto norms = [&](double* nz, double* nw) -> mcinv_status {
         double m[2] = {0.0, 0.0};
@@ -929,17 +1026,7 @@ mcinv_status mcinv_check_convergence(mcinv_ctx* c, int64_t iters, double* rho_T,
     const int64_t half = iters / 2;
     double z1 = 0, w1 = 0, z2 = 0, w2 = 0;
     mcinv_status s = MCINV_OK;
-    auto sweep = [&](int64_t k) -> mcinv_status {
-        switch (c->cfg.sweep_dtype) {
-        case MCINV_R32: return run_sweeps<float>(c, k, false, (float*)zc, (float*)wc, ld, 1, MCINV_NOISE_NONE, fl, false);
-        case MCINV_R64: return run_sweeps<double>(c, k, false, (double*)zc, (double*)wc, ld, 1, MCINV_NOISE_NONE, fl, false);
-        case MCINV_C64:
-            return run_sweeps<Cx<float>>(c, k, false, (Cx<float>*)zc, (Cx<float>*)wc, ld, 1, MCINV_NOISE_NONE, fl, false);
-        default:
-            return run_sweeps<Cx<double>>(c, k, false, (Cx<double>*)zc, (Cx<double>*)wc, ld, 1, MCINV_NOISE_NONE, fl,
-                                          false);
-        }
-    };
+    auto sweep = [&](int64_t k) -> mcinv_status { return noiseless_sweeps(c, k, zc, wc, ld, fl); };
     if ((s = sweep(half)) == MCINV_OK && (s = norms(&z1, &w1)) == MCINV_OK && (s = sweep(iters - half)) == MCINV_OK)
         s = norms(&z2, &w2);
     (void)hipFree(zc);

@@ -12,8 +12,8 @@
 //                   activations and deltas go out transposed as bf16 for the
 //                   weight gradients, bias / w3 partial sums per workgroup.
 //   k_mlp_wgrad   : dW1 = X^T dz1, dW2 = h1^T dz2 over the step's rows
-//                   (32 x 32 tile per workgroup, K split over its 4 waves,
-//                   summed in a fixed order).
+//                   (32 x 32 tile per workgroup, the rows split over
+//                   workgroups and over its 4 waves, summed in a fixed order).
 //   k_mlp_update  : gradient assembly (partials summed in a fixed order),
 //                   Adam step, bf16 copies of the weights.
 // Rounding points (what the oracle reproduces): the normalised features,
@@ -21,6 +21,7 @@
 // biases and every elementwise step stay fp32.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -268,30 +269,34 @@ __global__ __launch_bounds__(256) void k_mlp_fwd_bwd(const MlpArgs a)
 }
 
 // dW (rows x 128) = L Rt^T over K training rows: L is [rows][K], Rt is
-// [128][K] (bf16, the transposed activations / deltas).  Wave `wid` takes the
-// 32-row slabs wid, wid + 4, ...; the four partial tiles are summed in order.
+// [128][K] (bf16, the transposed activations / deltas).  Workgroup (tile,
+// ks) covers the rows [ks Kc, (ks + 1) Kc) of the step; its wave `wid` takes
+// the 32-row slabs wid, wid + 4, ... of that range and the four partial tiles
+// are summed in order.  The ks partials go to wpart[ks][W1 | b1 gap | W2] and
+// are summed in order of ks by the update kernel.
 __global__ __launch_bounds__(256) void k_mlp_wgrad(const bf16_t* XT, const bf16_t* dz1T, const bf16_t* h1T,
-                                                   const bf16_t* dz2T, int32_t K, float* grads)
+                                                   const bf16_t* dz2T, int32_t K, int32_t Kc, float* wpart)
 {
     __shared__ float red[4][32][33];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int i16 = lane & 15, kg = lane >> 4;
     // tiles 0..3: dW1 (32 x 128), tiles 4..19: dW2 (128 x 128)
     const int tile = blockIdx.x;
+    const int ks = blockIdx.y;
     const bf16_t *L, *Rt;
-    int r0, c0, ncols_out, base;
+    int r0, c0, base;
     if (tile < 4) {
         L = XT; Rt = dz1T; r0 = 0; c0 = 32 * tile; base = oW1;
     } else {
         L = h1T; Rt = dz2T; r0 = 32 * ((tile - 4) / 4); c0 = 32 * ((tile - 4) % 4); base = oW2;
     }
-    ncols_out = kH;
     f32x4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int kb = 32 * wid; kb < K; kb += 128) {   // K: a multiple of 32
+    const int k_end = min(K, (ks + 1) * Kc);   // Kc and K: multiples of 32
+    for (int kb = ks * Kc + 32 * wid; kb < k_end; kb += 128) {
         bf16x8 av[2], bv[2];
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
@@ -310,10 +315,11 @@ __global__ __launch_bounds__(256) void k_mlp_wgrad(const bf16_t* XT, const bf16_
 #pragma unroll
             for (int v = 0; v < 4; ++v) red[wid][16 * i + 4 * kg + v][16 * j + i16] = acc[i][j][v];
     __syncthreads();
+    float* out = wpart + (int64_t)ks * ob2;
     for (int t = threadIdx.x; t < 32 * 32; t += 256) {
         const int r = t / 32, c = t % 32;
         const float s = ((red[0][r][c] + red[1][r][c]) + red[2][r][c]) + red[3][r][c];
-        grads[base + (r0 + r) * ncols_out + c0 + c] = s;
+        out[base + (r0 + r) * kH + c0 + c] = s;
     }
 }
 
@@ -321,7 +327,9 @@ struct UpdateArgs {
     float* P;                // master parameters
     float* m;                // Adam first moments
     float* v;                // Adam second moments
-    float* grads;            // W1, W2 gradients (wgrad); biases and w3 written here too
+    float* grads;            // the assembled gradient [kParams]
+    const float* wpart;      // weight-gradient partials [nks][ob2]
+    int32_t nks;
     const float* part;       // [blocks][kPart]
     int32_t blocks;
     int32_t apply;           // 0: only assemble the gradient
@@ -344,7 +352,9 @@ __global__ __launch_bounds__(256) void k_mlp_update(const UpdateArgs u)
     if (p >= kParams) return;
     float g;
     if ((p >= oW1 && p < ob1) || (p >= oW2 && p < ob2)) {
-        g = u.grads[p];
+        g = 0.f;
+        for (int k = 0; k < u.nks; ++k) g += u.wpart[(int64_t)k * ob2 + p];
+        u.grads[p] = g;
     } else {
         int k;
         if (p < oW2)
@@ -426,6 +436,7 @@ struct mcinv_mlp {
     int64_t N = 0;
     // step buffers
     int32_t Rcap = 0;
+    float* wpart = nullptr;  // [kMaxKs][ob2]
     int64_t* idx = nullptr;
     bf16_t* XT = nullptr;
     bf16_t* h1T = nullptr;
@@ -464,6 +475,14 @@ mcinv_status merr(mcinv_mlp* m, mcinv_status code, const std::string& msg)
                         std::string(#expr) + ": " + hipGetErrorString(e_));                     \
     } while (0)
 
+// Row splits of the weight-gradient GEMMs: about 512 rows each, at most 64.
+int32_t ks_of(int32_t R) { return std::max(1, std::min(64, R / 512)); }
+int32_t kc_of(int32_t R)
+{
+    const int32_t ks = ks_of(R);
+    return ((R + ks - 1) / ks + 31) / 32 * 32;
+}
+
 mcinv_status ensure_step(mcinv_mlp* m, int32_t R)
 {
     if (R <= m->Rcap) return MCINV_OK;
@@ -473,7 +492,9 @@ mcinv_status ensure_step(mcinv_mlp* m, int32_t R)
     mfree(m->dz2T);
     mfree(m->dz1T);
     mfree(m->part);
+    mfree(m->wpart);
     MHIP(m, hipMalloc((void**)&m->idx, sizeof(int64_t) * R));
+    MHIP(m, hipMalloc((void**)&m->wpart, sizeof(float) * ob2 * (size_t)ks_of(R)));
     MHIP(m, hipMalloc((void**)&m->XT, sizeof(bf16_t) * kF * (size_t)R));
     MHIP(m, hipMalloc((void**)&m->h1T, sizeof(bf16_t) * kH * (size_t)R));
     MHIP(m, hipMalloc((void**)&m->dz2T, sizeof(bf16_t) * kH * (size_t)R));
@@ -515,13 +536,16 @@ mcinv_status run_step(mcinv_mlp* m, int32_t R, bool apply, float lr, float* loss
     const int blocks = R / 64;
     k_mlp_fwd_bwd<<<dim3(blocks), dim3(256), 0, m->stream>>>(a);
     MHIP(m, hipGetLastError());
-    k_mlp_wgrad<<<dim3(20), dim3(256), 0, m->stream>>>(m->XT, m->dz1T, m->h1T, m->dz2T, R, m->grads);
+    const int32_t kc = kc_of(R), nks = (R + kc - 1) / kc;
+    k_mlp_wgrad<<<dim3(20, nks), dim3(256), 0, m->stream>>>(m->XT, m->dz1T, m->h1T, m->dz2T, R, kc, m->wpart);
     MHIP(m, hipGetLastError());
     UpdateArgs u{};
     u.P = m->P;
     u.m = m->m;
     u.v = m->v;
     u.grads = m->grads;
+    u.wpart = m->wpart;
+    u.nks = nks;
     u.part = m->part;
     u.blocks = blocks;
     u.apply = apply ? 1 : 0;
@@ -607,6 +631,7 @@ void mcinv_mlp_destroy(mcinv_mlp* m)
     mfree(m->dz2T);
     mfree(m->dz1T);
     mfree(m->part);
+    mfree(m->wpart);
     if (m->stream) (void)hipStreamDestroy(m->stream);
     delete m;
 }

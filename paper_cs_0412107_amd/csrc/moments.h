@@ -35,6 +35,11 @@ hipError_t launch_entries(const V* z, const V* w, int64_t ld, const int64_t* ei,
 // acc[m] = acc[2m] + acc[2m+1] for m < half, acc[m] = 0 for half <= m < 2 half.
 hipError_t launch_merge_slots(double* acc, int64_t slot_elems, int64_t half, hipStream_t stream);
 
+// Largest magnitude of x[q * ld], q < n, into *out (double bits, atomic max;
+// clear *out first).
+template <typename V>
+hipError_t launch_max_abs(const V* x, int64_t n, int64_t ld, unsigned long long* out, hipStream_t stream);
+
 // Deterministic sum of x[count][comps] into out[comps] (two stages, one launch).
 hipError_t launch_reduce_sum(const double* x, int64_t count, int comps, double* partial, uint32_t* counter,
                              double* out, hipStream_t stream);

@@ -167,6 +167,42 @@ __global__ __launch_bounds__(256) void k_merge_slots(double* acc, int64_t slot_e
     for (int64_t m = half; m < 2 * half; ++m) acc[m * slot_elems + e] = 0.0;
 }
 
+// max_q |x[q * ld]| over n rows (lane 0 of each row) as the bits of a
+// non-negative double (their integer order is the value order); non-finite
+// values count as +inf.
+__device__ inline double modulus(float x) { return fabs((double)x); }
+__device__ inline double modulus(double x) { return fabs(x); }
+template <typename R> __device__ inline double modulus(Cx<R> x)
+{
+    return sqrt((double)x.re * (double)x.re + (double)x.im * (double)x.im);
+}
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_max_abs(const V* x, int64_t n, int64_t ld, unsigned long long* out)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double v = 0.0;
+    if (q < n) {
+        v = modulus(x[q * ld]);
+        if (!(v < __builtin_inf())) v = __builtin_inf();
+    }
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(v));
+}
+
+template <typename V>
+hipError_t launch_max_abs(const V* x, int64_t n, int64_t ld, unsigned long long* out, hipStream_t stream)
+{
+    if (n <= 0) return hipSuccess;
+    k_max_abs<V><<<dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream>>>(x, n, ld, out);
+    return hipGetLastError();
+}
+template hipError_t launch_max_abs<float>(const float*, int64_t, int64_t, unsigned long long*, hipStream_t);
+template hipError_t launch_max_abs<double>(const double*, int64_t, int64_t, unsigned long long*, hipStream_t);
+template hipError_t launch_max_abs<Cx<float>>(const Cx<float>*, int64_t, int64_t, unsigned long long*, hipStream_t);
+template hipError_t launch_max_abs<Cx<double>>(const Cx<double>*, int64_t, int64_t, unsigned long long*,
+                                               hipStream_t);
+
 hipError_t launch_merge_slots(double* acc, int64_t slot_elems, int64_t half, hipStream_t stream)
 {
     if (slot_elems <= 0 || half <= 0) return hipSuccess;

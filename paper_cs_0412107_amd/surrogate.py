@@ -126,7 +126,9 @@ def estimate_diag(matrix, net, gate, sampler_factory, rel_se=0.01, max_sweeps=20
     """diag(C^-1): the network's prediction where the gate accepts it, the
     sampler's estimate (stop check over the rejected rows only) elsewhere.
 
-    ``sampler_factory(matrix)`` returns a ``Sampler`` for the matrix.
+    ``sampler_factory(matrix)`` returns a ``Sampler`` for the matrix;
+    ``burn_in`` is a sweep count or "coupled" (until the coupled paths agree
+    to 5e-5).
     Returns (estimate, source) with source 0 = network, 1 = sampler, and a
     dict of counts and sweeps."""
     X = features(matrix, device)
@@ -137,7 +139,10 @@ def estimate_diag(matrix, net, gate, sampler_factory, rel_se=0.01, max_sweeps=20
     info = {"rows": int(matrix.n), "fallback_rows": int(fb.sum()), "sweeps": 0}
     if fb.any():
         with sampler_factory(matrix) as s:
-            s.burn_in(burn_in)
+            if burn_in == "coupled":
+                s.burn_in_coupled(5e-5, 10000)
+            else:
+                s.burn_in(burn_in)
             s.request(diag=True, trace=False)
             s.set_stop_rows(np.nonzero(fb)[0])
             done, achieved = s.sample_until(rel_se, max_sweeps, check_every)

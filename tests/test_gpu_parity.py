@@ -252,6 +252,54 @@ def test_divergence_reported():
         assert ei.value.code == mc.MCINV_EDIVERGED
 
 
+@pytest.mark.parametrize("dtype,maker", [
+    ("f64", lambda: gen.pedigree(4000, seed=61)),
+    ("f32", lambda: gen.pedigree(4000, seed=61)),
+    ("c64", lambda: gen.lattice(6, k=0.12, seed=62)),
+    ("f64", lambda: gen.random_dominant(700, 4, seed=63, factor=1.1)),
+])
+def test_coupled_burn_in_matches_oracle(dtype, maker):
+    """The library evaluates the coupling through eq 12 (one noiseless chain); the
+    oracle runs Algorithm 1's two noisy paths.  Same N (64-bit: exactly; 32-bit:
+    within one sweep where the difference crosses tol within rounding), and the
+    chains end exactly as after burn_in(N)."""
+    print_case(test="coupled_burn_in", dtype=dtype)
+    m = oracle_matrix(maker(), dtype)
+    tol, seed, P = 5e-5, 17, 64
+    with _sampler(m, dtype, seed, P) as s:
+        perm, _ = s.permutation()
+        N, dz, dw = s.burn_in_coupled(tol, 500)
+        z = s.state(0)
+        assert s.info()["sweeps_done"] == N
+    N_ora, diffs = oracle.coupled_burn_in(m, seed, tol, 500)
+    if dtype in ("f64", "c128"):
+        assert N == N_ora
+        np.testing.assert_allclose([dz, dw], diffs[N - 1], rtol=1e-9)
+    else:
+        assert abs(N - N_ora) <= 1
+        if N != N_ora:
+            k = min(N, N_ora)
+            assert max(diffs[k - 1]) < tol * (1 + 1e-3)
+        np.testing.assert_allclose([dz, dw], diffs[N - 1], rtol=1e-3)
+    assert dz < tol and dw < tol and N > 3
+    with _sampler(m, dtype, seed, P) as s2:
+        s2.burn_in(N)
+        assert np.array_equal(s2.state(0), z)
+
+
+def test_coupled_burn_in_reports_divergence_and_cap():
+    C = np.array([[1.0, 2.5, 0.0], [2.0, 1.0, 1.5], [0.0, 3.0, 1.0]])
+    with _sampler(gen.from_dense(C), "f32", 1, 4) as s:
+        with pytest.raises(mc.McinvError) as ei:
+            s.burn_in_coupled(5e-5, 5000)
+        assert ei.value.code == mc.MCINV_EDIVERGED
+    with _sampler(gen.pedigree(500, seed=3), "f64", 1, 4) as s:
+        N, dz, dw = s.burn_in_coupled(1e-30, 7)
+        assert N == 7 and max(dz, dw) >= 1e-30 and s.info()["sweeps_done"] == 7
+        N0, _, _ = s.burn_in_coupled(5e-5, 0)
+        assert N0 == 0
+
+
 def test_convergence_rate_is_spectral_radius():
     from oracle import theory
     rng = np.random.default_rng(13)

@@ -170,6 +170,32 @@ def test_coupling_contraction_rate_is_spectral_radius():
     assert abs(rate - theory.spectral_radius(T)) < 0.02
 
 
+def test_coupled_burn_in_length_is_gauss_seidel_closed_form():
+    """Algorithm 1 steps 1-5 run literally (two noisy paths) stop at the first k
+    with ||G^k x*|| < tol for the dense Gauss-Seidel matrices G of C and C^dagger
+    (eq 12), x*_i = i: an off-by-one in the count, a wrong start or a w path
+    swept on C instead of C^dagger changes N or the differences."""
+    n = 12
+    C = _dense_random(n, 31, True, factor=1.15)
+    m = gen.from_dense(C)
+    order = np.arange(n)
+    N, diffs = oracle.coupled_burn_in(m, seed=8, tol=1e-6, max_sweeps=400, order=order)
+    L, D, U = theory.split(C)
+    x = np.arange(1, n + 1, dtype=np.complex128)
+    y = x.copy()
+    k_ref = None
+    for k in range(1, 401):
+        x = solve_triangular(D + L, -U @ x, lower=True)
+        y = solve_triangular(np.conj(D + U).T, -np.conj(L).T @ y, lower=True)
+        dz, dw = np.abs(x).max(), np.abs(y).max()
+        if k <= len(diffs):
+            assert abs(diffs[k - 1][0] - dz) <= 1e-10 * n and abs(diffs[k - 1][1] - dw) <= 1e-10 * n
+        if dz < 1e-6 and dw < 1e-6:
+            k_ref = k
+            break
+    assert k_ref is not None and N == k_ref and N > 5
+
+
 # --- P9: convergence condition (Sec. 2.2) -----------------------------------------
 @pytest.mark.parametrize("maker", [
     lambda: gen.random_dominant(200, seed=1000),
