@@ -89,7 +89,7 @@ def random_dominant(n=200, offdiag_per_row=4, seed=1000, factor=1.5) -> CSR:
 
 
 def pedigree(n=100_000, seed=1001, founders=0.05, lam=0.2, factor=1.5,
-             jitter=(0.8, 1.2)) -> CSR:
+             jitter=(0.8, 1.2), symmetric=False) -> CSR:
     """Pedigree-shaped real non-symmetric matrix.
 
     Animals ``0 .. nf-1`` are founders (no parents); every later animal ``i``
@@ -99,7 +99,13 @@ def pedigree(n=100_000, seed=1001, founders=0.05, lam=0.2, factor=1.5,
     ``-delta/4`` at (s,d), (d,s) (duplicates summed).  Each stored off-diagonal
     is then multiplied by an independent U(jitter) factor, and the diagonal is
     set to ``factor`` x the off-diagonal absolute row sum.
+
+    ``symmetric=True`` (needs lam = 0, where the rules are symmetric) draws one
+    jitter factor per unordered pair {i, j}, giving a symmetric positive
+    definite matrix (diagonally dominant, positive diagonal).
     """
+    if symmetric and lam != 0.0:
+        raise ValueError("a symmetric pedigree needs lam = 0")
     rng = np.random.default_rng(seed)
     nf = max(1, min(n, int(round(founders * n))))
     i = np.arange(nf, n, dtype=np.int64)
@@ -125,6 +131,10 @@ def pedigree(n=100_000, seed=1001, founders=0.05, lam=0.2, factor=1.5,
     m.sum_duplicates()
     coo = m.tocoo()
     jit = rng.uniform(jitter[0], jitter[1], size=coo.data.size)
+    if symmetric:
+        key = np.minimum(coo.row, coo.col).astype(np.int64) * n + np.maximum(coo.row, coo.col)
+        _, first, inv = np.unique(key, return_index=True, return_inverse=True)
+        jit = jit[first][inv]
     return _set_dominant_diagonal(n, coo.row.astype(np.int64), coo.col.astype(np.int64),
                                   coo.data * jit, factor)
 

@@ -99,6 +99,11 @@ typedef struct {
     int32_t  profile;      /* nonzero: time every sweep launch with HIP events       */
     int32_t  pass_tiles;   /* 256-pair tiles swept through all colours before the
                               next tiles start (cache residency); 0 = automatic   */
+    int32_t  hermitian;    /* nonzero: C is hermitian with a positive diagonal
+                              (checked by mcinv_load_csr, EINVAL otherwise); then
+                              w = z at every step and only z is swept -- the
+                              single-draw Gauss-Seidel sampler of eq 2, half the
+                              state traffic.  w reads return z; w cannot be written */
 } mcinv_config;
 
 typedef struct {

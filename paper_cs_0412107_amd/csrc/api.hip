@@ -331,7 +331,7 @@ mcinv_status run_sweeps(mcinv_ctx* c, int64_t nsw, bool sample, V* z, V* w, int6
                 a.row_end = c->color_ptr[col + 1];
                 a.tile0 = t0;
                 a.tpart = want_trace ? c->d_tpart + c->tpart_off[col] * c->comps : nullptr;
-                HIP_TRY(c, launch_sweep<V>(a, std::min(pt, T - t0), sample, c->stream));
+                HIP_TRY(c, launch_sweep<V>(a, std::min(pt, T - t0), sample, c->cfg.hermitian != 0, c->stream));
             }
         }
         for (int32_t col = cs; col < c->ncolors; ++col) {
@@ -339,7 +339,7 @@ mcinv_status run_sweeps(mcinv_ctx* c, int64_t nsw, bool sample, V* z, V* w, int6
             a.row_end = c->color_ptr[col + 1];
             a.tile0 = 0;
             a.tpart = want_trace ? c->d_tpart + c->tpart_off[col] * c->comps : nullptr;
-            HIP_TRY(c, launch_sweep<V>(a, T, sample, c->stream));
+            HIP_TRY(c, launch_sweep<V>(a, T, sample, c->cfg.hermitian != 0, c->stream));
         }
         if (prof && e1) {
             HIP_TRY(c, hipEventRecord(e1, c->stream));
@@ -408,20 +408,24 @@ mcinv_status run_sweeps(mcinv_ctx* c, int64_t nsw, bool sample, V* z, V* w, int6
     return MCINV_OK;
 }
 
+// The w state: z itself in hermitian mode (w = z at every step).
+void* w_state(mcinv_ctx* c) { return c->cfg.hermitian ? c->d_z : c->d_w; }
+
 mcinv_status dispatch_sweeps(mcinv_ctx* c, int64_t nsw, bool sample)
 {
+    void* const wst = w_state(c);
     switch (c->cfg.sweep_dtype) {
     case MCINV_R32:
-        return run_sweeps<float>(c, nsw, sample, (float*)c->d_z, (float*)c->d_w, c->ld, c->P, c->cfg.noise,
+        return run_sweeps<float>(c, nsw, sample, (float*)c->d_z, (float*)wst, c->ld, c->P, c->cfg.noise,
                                  c->d_flag, true);
     case MCINV_R64:
-        return run_sweeps<double>(c, nsw, sample, (double*)c->d_z, (double*)c->d_w, c->ld, c->P, c->cfg.noise,
+        return run_sweeps<double>(c, nsw, sample, (double*)c->d_z, (double*)wst, c->ld, c->P, c->cfg.noise,
                                   c->d_flag, true);
     case MCINV_C64:
-        return run_sweeps<Cx<float>>(c, nsw, sample, (Cx<float>*)c->d_z, (Cx<float>*)c->d_w, c->ld, c->P,
+        return run_sweeps<Cx<float>>(c, nsw, sample, (Cx<float>*)c->d_z, (Cx<float>*)wst, c->ld, c->P,
                                      c->cfg.noise, c->d_flag, true);
     default:
-        return run_sweeps<Cx<double>>(c, nsw, sample, (Cx<double>*)c->d_z, (Cx<double>*)c->d_w, c->ld, c->P,
+        return run_sweeps<Cx<double>>(c, nsw, sample, (Cx<double>*)c->d_z, (Cx<double>*)wst, c->ld, c->P,
                                       c->cfg.noise, c->d_flag, true);
     }
 }
@@ -618,6 +622,15 @@ mcinv_status mcinv_load_csr(mcinv_ctx* c, int64_t n, int64_t nnz, const int64_t*
     const std::string why = prepare_matrix(n, nnz, row_ptr, col_idx, (const double*)values,
                                            value_dtype == MCINV_C128, h, &singular);
     if (!why.empty()) return fail(c, singular ? MCINV_ESINGULAR : MCINV_EINVAL, why);
+    if (c->cfg.hermitian) {
+        // w = z needs c_ji = conj(c_ij) (then v = u exactly) and a positive real
+        // diagonal (then b = a).
+        for (int64_t q = 0; q < n; ++q)
+            if (!(h.diag[q].imag() == 0.0 && h.diag[q].real() > 0.0))
+                return fail(c, MCINV_EINVAL, "hermitian mode needs a positive real diagonal");
+        for (const MergedEntry& e : h.ent)
+            if (!(e.u == e.v)) return fail(c, MCINV_EINVAL, "hermitian mode: the matrix is not hermitian");
+    }
     const bool real_values = value_dtype == MCINV_R64;
     const int32_t ncolors = h.ncolors;
     const std::vector<int64_t>& color_ptr = h.color_ptr;
@@ -654,9 +667,9 @@ mcinv_status mcinv_load_csr(mcinv_ctx* c, int64_t n, int64_t nnz, const int64_t*
     MC_TRY(upload(c, &c->d_perm, h.perm));
     const size_t state_bytes = (size_t)n * c->ld * c->elem;
     HIP_TRY(c, hipMalloc(&c->d_z, state_bytes));
-    HIP_TRY(c, hipMalloc(&c->d_w, state_bytes));
+    if (!c->cfg.hermitian) HIP_TRY(c, hipMalloc(&c->d_w, state_bytes));
     HIP_TRY(c, hipMemsetAsync(c->d_z, 0, state_bytes, c->stream));
-    HIP_TRY(c, hipMemsetAsync(c->d_w, 0, state_bytes, c->stream));
+    if (!c->cfg.hermitian) HIP_TRY(c, hipMemsetAsync(c->d_w, 0, state_bytes, c->stream));
     HIP_TRY(c, hipMemsetAsync(c->d_flag, 0, sizeof(int32_t), c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     c->sweeps = 0;
@@ -824,7 +837,7 @@ mcinv_status mcinv_read_state(mcinv_ctx* c, int32_t which, void* host, int64_t b
     if (which != 0 && which != 1) return fail(c, MCINV_EINVAL, "which must be 0 (z) or 1 (w)");
     if (!host || bytes < c->n * c->P * (int64_t)c->elem) return fail(c, MCINV_EINVAL, "host buffer too small");
     std::vector<char> tmp((size_t)(c->n * c->ld * c->elem));
-    HIP_TRY(c, hipMemcpyAsync(tmp.data(), which ? c->d_w : c->d_z, tmp.size(), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(tmp.data(), which ? w_state(c) : c->d_z, tmp.size(), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     char* out = (char*)host;
     const size_t row_bytes = (size_t)c->P * c->elem;
@@ -838,6 +851,7 @@ mcinv_status mcinv_write_state(mcinv_ctx* c, int32_t which, const void* host, in
     MC_TRY(check_ready(c));
     if (which != 0 && which != 1) return fail(c, MCINV_EINVAL, "which must be 0 (z) or 1 (w)");
     if (!host || bytes < c->n * c->P * (int64_t)c->elem) return fail(c, MCINV_EINVAL, "host buffer too small");
+    if (which == 1 && c->cfg.hermitian) return fail(c, MCINV_EINVAL, "hermitian mode: w is z; write z");
     std::vector<char> tmp((size_t)(c->n * c->ld * c->elem), 0);
     const char* in = (const char*)host;
     const size_t row_bytes = (size_t)c->P * c->elem;
@@ -907,6 +921,7 @@ mcinv_status coupled_start(mcinv_ctx* c, int64_t ld, void** zc, void** wc, int32
 
 mcinv_status noiseless_sweeps(mcinv_ctx* c, int64_t k, void* zc, void* wc, int64_t ld, int32_t* fl)
 {
+    if (c->cfg.hermitian) wc = zc;   // C^dagger = C: the w difference is the z difference
     switch (c->cfg.sweep_dtype) {
     case MCINV_R32: return run_sweeps<float>(c, k, false, (float*)zc, (float*)wc, ld, 1, MCINV_NOISE_NONE, fl, false);
     case MCINV_R64: return run_sweeps<double>(c, k, false, (double*)zc, (double*)wc, ld, 1, MCINV_NOISE_NONE, fl, false);
@@ -949,7 +964,9 @@ mcinv_status mcinv_burn_in_coupled(mcinv_ctx* c, double tol, int64_t max_sweeps,
             s = fail(c, MCINV_EDEVICE, "hipMemsetAsync failed");
             break;
         }
-        if ((s = max_abs(c, zc, ld, dmax)) != MCINV_OK || (s = max_abs(c, wc, ld, dmax + 1)) != MCINV_OK) break;
+        if ((s = max_abs(c, zc, ld, dmax)) != MCINV_OK ||
+            (s = max_abs(c, c->cfg.hermitian ? zc : wc, ld, dmax + 1)) != MCINV_OK)
+            break;
         unsigned long long bits[2] = {0, 0};
         if (hipMemcpyAsync(bits, dmax, sizeof(bits), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
             hipStreamSynchronize(c->stream) != hipSuccess) {
@@ -1002,7 +1019,8 @@ mcinv_status mcinv_check_convergence(mcinv_ctx* c, int64_t iters, double* rho_T,
     auto norms = [&](double* nz, double* nw) -> mcinv_status {
         double m[2] = {0.0, 0.0};
         for (int which = 0; which < 2; ++which) {
-            HIP_TRY(c, hipMemcpyAsync(host.data(), which ? wc : zc, bytes, hipMemcpyDeviceToHost, c->stream));
+            const void* src = which && !c->cfg.hermitian ? wc : zc;
+            HIP_TRY(c, hipMemcpyAsync(host.data(), src, bytes, hipMemcpyDeviceToHost, c->stream));
             HIP_TRY(c, hipStreamSynchronize(c->stream));
             const int comps = c->comps;
             const bool f32 = c->cfg.sweep_dtype == MCINV_R32 || c->cfg.sweep_dtype == MCINV_C64;

@@ -33,9 +33,10 @@ struct SweepArgs {
     typename Real<V>::type thresh;
 };
 
-// Launch over pair tiles [a.tile0, a.tile0 + ntiles).
+// Launch over pair tiles [a.tile0, a.tile0 + ntiles).  herm: C is hermitian
+// with a positive diagonal and only z is swept (w = z, eq 2).
 template <typename V>
-hipError_t launch_sweep(const SweepArgs<V>& a, int64_t ntiles, bool sample, hipStream_t stream);
+hipError_t launch_sweep(const SweepArgs<V>& a, int64_t ntiles, bool sample, bool herm, hipStream_t stream);
 
 hipError_t launch_noise_values(bool fp64, uint64_t seed, uint32_t stream_id, int32_t kind, int64_t count,
                                const int64_t* row, const int64_t* sweep, const int64_t* pair, double* out,

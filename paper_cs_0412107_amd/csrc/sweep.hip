@@ -65,7 +65,10 @@ __device__ inline void prod_acc(Cx<R> z, Cx<R> w, double& re, double& im)
     im += zi * wr - zr * wi;
 }
 
-template <typename V, bool SAMPLE>
+// HERM: C is hermitian with a positive diagonal, so w = z at every step (the
+// single-draw Gauss-Seidel sampler of eq 2): only z is gathered and stored,
+// and the moments use z conj(z).
+template <typename V, bool SAMPLE, bool HERM>
 __global__ __launch_bounds__(256) void k_sweep(const SweepArgs<V> a)
 {
     using R = typename Real<V>::type;
@@ -116,14 +119,14 @@ __global__ __launch_bounds__(256) void k_sweep(const SweepArgs<V> a)
                     vs[t] = ok ? en.v : vzero<V>();
                     const int64_t off = (int64_t)en.col * a.ld + p0;
                     xs[t] = load_quad(a.z + off);
-                    ys[t] = load_quad(a.w + off);
+                    if constexpr (!HERM) ys[t] = load_quad(a.w + off);
                 }
 #pragma unroll
                 for (int t = 0; t < U; ++t)
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         az[j] = mul_add(us[t], xs[t].v[j], az[j]);
-                        aw[j] = mul_add(vs[t], ys[t].v[j], aw[j]);
+                        if constexpr (!HERM) aw[j] = mul_add(vs[t], ys[t].v[j], aw[j]);
                     }
             }
         }
@@ -135,11 +138,11 @@ __global__ __launch_bounds__(256) void k_sweep(const SweepArgs<V> a)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             zn.v[j] = noisy_update(s.a, phi[j], az[j]);
-            wn.v[j] = noisy_update(s.b, phi[j], aw[j]);
+            wn.v[j] = HERM ? zn.v[j] : noisy_update(s.b, phi[j], aw[j]);
         }
         if (active) {
             store_quad(a.z + q * a.ld + p0, zn);
-            store_quad(a.w + q * a.ld + p0, wn);
+            if constexpr (!HERM) store_quad(a.w + q * a.ld + p0, wn);
         }
 
         // Divergence guard (Sec. 2.2): a runaway or non-finite state.
@@ -201,22 +204,29 @@ __global__ __launch_bounds__(256) void k_sweep(const SweepArgs<V> a)
 }
 
 template <typename V>
-hipError_t launch_sweep(const SweepArgs<V>& a, int64_t ntiles, bool sample, hipStream_t stream)
+hipError_t launch_sweep(const SweepArgs<V>& a, int64_t ntiles, bool sample, bool herm, hipStream_t stream)
 {
     const int64_t rows = a.row_end - a.row_begin;
     if (rows <= 0 || ntiles <= 0) return hipSuccess;
     const dim3 grid((unsigned)((rows + 3) / 4), (unsigned)ntiles);
-    if (sample)
-        k_sweep<V, true><<<grid, dim3(256), 0, stream>>>(a);
-    else
-        k_sweep<V, false><<<grid, dim3(256), 0, stream>>>(a);
+    if (herm) {
+        if (sample)
+            k_sweep<V, true, true><<<grid, dim3(256), 0, stream>>>(a);
+        else
+            k_sweep<V, false, true><<<grid, dim3(256), 0, stream>>>(a);
+    } else {
+        if (sample)
+            k_sweep<V, true, false><<<grid, dim3(256), 0, stream>>>(a);
+        else
+            k_sweep<V, false, false><<<grid, dim3(256), 0, stream>>>(a);
+    }
     return hipGetLastError();
 }
 
-template hipError_t launch_sweep<float>(const SweepArgs<float>&, int64_t, bool, hipStream_t);
-template hipError_t launch_sweep<double>(const SweepArgs<double>&, int64_t, bool, hipStream_t);
-template hipError_t launch_sweep<Cx<float>>(const SweepArgs<Cx<float>>&, int64_t, bool, hipStream_t);
-template hipError_t launch_sweep<Cx<double>>(const SweepArgs<Cx<double>>&, int64_t, bool, hipStream_t);
+template hipError_t launch_sweep<float>(const SweepArgs<float>&, int64_t, bool, bool, hipStream_t);
+template hipError_t launch_sweep<double>(const SweepArgs<double>&, int64_t, bool, bool, hipStream_t);
+template hipError_t launch_sweep<Cx<float>>(const SweepArgs<Cx<float>>&, int64_t, bool, bool, hipStream_t);
+template hipError_t launch_sweep<Cx<double>>(const SweepArgs<Cx<double>>&, int64_t, bool, bool, hipStream_t);
 
 // --------------------------------------------------------------------------
 // Noise values for given (row, sweep, pair) triples, as the sweep draws them.

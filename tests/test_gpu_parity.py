@@ -300,6 +300,59 @@ def test_coupled_burn_in_reports_divergence_and_cap():
         assert N0 == 0
 
 
+def _hermitian_dense(n, seed):
+    rng = np.random.default_rng(seed)
+    B = (rng.uniform(-1, 1, (n, n)) + 1j * rng.uniform(-1, 1, (n, n))) * (rng.random((n, n)) < 0.15)
+    A = B + B.conj().T
+    np.fill_diagonal(A, 0)
+    A[np.diag_indices(n)] = 1.3 * np.abs(A).sum(axis=1) + 0.1
+    return gen.from_dense(A)
+
+
+@pytest.mark.parametrize("dtype,maker", [
+    ("f32", lambda: gen.pedigree(3000, seed=71, lam=0.0, symmetric=True)),
+    ("f64", lambda: gen.pedigree(3000, seed=71, lam=0.0, symmetric=True)),
+    ("c128", lambda: _hermitian_dense(80, 72)),
+    ("c64", lambda: _hermitian_dense(80, 72)),
+])
+def test_hermitian_mode_matches_oracle_and_two_chain_path(dtype, maker):
+    """Single-draw mode (eq 2): z must equal the oracle's z, and equal bit for bit
+    both z and w of the two-chain path (eq 5 on a hermitian C gives w = z)."""
+    print_case(test="hermitian", dtype=dtype)
+    m = oracle_matrix(maker(), dtype)
+    seed, P, G = 5, 64, 16
+    ora = make_oracle(m, dtype, seed, P, G)
+    with _sampler(m, dtype, seed, P, G, hermitian=True) as h, _sampler(m, dtype, seed, P, G) as t:
+        for k in (1, 4):
+            h.burn_in(k)
+            t.burn_in(k)
+            ora.burn_in(k)
+            zh = h.state(0)
+            assert rel_err(zh, ora.z) <= TOL[dtype]
+            assert np.array_equal(zh, t.state(0)) and np.array_equal(zh, t.state(1))
+            assert np.array_equal(h.state(1), zh)
+        h.request(diag=True, trace=True, block_rows=[0, 5, 9], block_cols=[1, 2])
+        t.request(diag=True, trace=True, block_rows=[0, 5, 9], block_cols=[1, 2])
+        h.sample(6)
+        t.sample(6)
+        for a, b in ((h.diag(), t.diag()), (h.trace(), t.trace()), (h.block(), t.block())):
+            assert np.array_equal(np.asarray(a[0]), np.asarray(b[0]))
+            assert np.array_equal(np.asarray(a[1]), np.asarray(b[1]), equal_nan=True)
+        Nh, _, _ = h.burn_in_coupled(5e-5, 300)
+        Nt, _, _ = t.burn_in_coupled(5e-5, 300)
+        assert Nh == Nt
+        with pytest.raises(mc.McinvError) as ei:
+            h.set_state(1, zh)
+        assert ei.value.code == mc.MCINV_EINVAL
+
+
+def test_hermitian_mode_rejects_non_hermitian():
+    for m in (gen.pedigree(500, seed=3), gen.diag_matrix(np.array([1.0, -2.0, 3.0]))):
+        with pytest.raises(mc.McinvError) as ei:
+            _sampler(m, "f32", 1, 4, hermitian=True)
+        assert ei.value.code == mc.MCINV_EINVAL
+
+
 def test_convergence_rate_is_spectral_radius():
     from oracle import theory
     rng = np.random.default_rng(13)
