@@ -183,6 +183,38 @@ def hermitian_form(pkg, torch, gen, w, steps=20):
     return out
 
 
+def dirac_form(pkg, torch, gen):
+    """The paper's second example, case 1: free Wilson-Dirac matrix on an 18^4
+    lattice (K = 0.1, rank 419904, 14 nonzeros per row), trace of the inverse
+    to the paper's stopping rule (Geyer standard error below 1e-5 of the
+    estimate), coupled burn-in to 5e-5; compared with the closed form."""
+    from oracle import theory  # the exact value only (a closed form), not the sampler
+    w = gen.WORKLOADS["dirac"]
+    m = gen.round_values(gen.dirac(w["N"], w["K"]), np.complex64)
+    P, G, seed = w["pairs"], w["groups"], w["noise_seed"]
+    exact = theory.dirac_free_trace(w["N"], w["K"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = pkg.Sampler(m, pairs=P, groups=G, dtype="c64", seed=seed, use_torch_stream=True)
+    N, _, _ = s.burn_in_coupled(BURN_TOL, 10000)
+    s.request(diag=False, trace=True)
+    done, ach = s.sample_until_trace(w["rel_se"], 20000, 20)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    est, se = s.trace()
+    t1 = time.perf_counter()
+    s.sample(10)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t1) * 1e3 / 10
+    s.close()
+    return {"workload": f"free Wilson-Dirac 18^4 (n={m.n}, nnz={m.nnz}), K={w['K']}, {P} pairs, complex64",
+            "seconds": t, "burn_in": N, "sample_sweeps": done, "rel_se": ach,
+            "estimate": [float(np.real(est)), float(np.imag(est))], "se": float(se), "exact": exact,
+            "z_score": float((np.real(est) - exact) / se), "ms_per_sweep": ms,
+            "nonzero_updates_per_s": 2.0 * m.nnz * P / (ms / 1e3),
+            "paper_case1": {"burn_in": 18, "sample_cycles": 10832, "chain_pairs": 1}}
+
+
 MLP_FLOP_PER_ROW_STEP = 2 * (32 * 128 + 128 * 128 + 128) + 2 * (2 * 128 + 2 * 128 * 128 + 32 * 128)
 
 
@@ -320,6 +352,7 @@ def main():
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-1%% phase")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form comparison")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate form")
+    ap.add_argument("--no-dirac", action="store_true", help="skip the free Wilson-Dirac form")
     ap.add_argument("--surrogate-train", type=int, default=192,
                     help="training matrices of the surrogate form (the full workload has 2000)")
     ap.add_argument("--surrogate-val", type=int, default=32)
@@ -435,6 +468,9 @@ def main():
         if args.workload == "pedigree":
             forms["hermitian"] = hermitian_form(pkg, torch, gen, w)
             log(f"hermitian single-draw: {forms['hermitian']['speedup_sweep']:.2f}x per sweep")
+        if args.workload == "pedigree" and not args.no_dirac:
+            forms["dirac"] = dirac_form(pkg, torch, gen)
+            log(f"dirac 18^4: {forms['dirac']['seconds']:.2f} s to 1e-5 ({forms['dirac']['sample_sweeps']} sweeps)")
         if args.workload == "pedigree" and not args.no_surrogate:
             forms["surrogate"] = surrogate_form(pkg, torch, gen, args.surrogate_train, args.surrogate_val)
         result["forms"] = forms

@@ -10,6 +10,8 @@ from .matrices import (  # noqa: F401
     random_dominant,
     pedigree,
     lattice,
+    dirac,
+    dirac_gammas,
     batched_sizes,
     batched_pedigrees,
     surrogate_params,

@@ -177,6 +177,56 @@ def lattice(L=16, k=0.1, seed=1002, constant_phase=False, dims=4) -> CSR:
     return out
 
 
+def dirac_gammas():
+    """Euclidean Dirac matrices in the Dirac representation: gamma_4 =
+    diag(1, 1, -1, -1) and gamma_k = [[0, -i sigma_k], [i sigma_k, 0]] with the
+    Pauli matrices sigma_k; hermitian, {gamma_mu, gamma_nu} = 2 delta_mu_nu.
+    Order: gamma_1, gamma_2, gamma_3, gamma_4."""
+    s = [np.array([[0, 1], [1, 0]], dtype=np.complex128),
+         np.array([[0, -1j], [1j, 0]], dtype=np.complex128),
+         np.array([[1, 0], [0, -1]], dtype=np.complex128)]
+    z = np.zeros((2, 2), dtype=np.complex128)
+    g = [np.block([[z, -1j * sk], [1j * sk, z]]) for sk in s]
+    g.append(np.diag([1.0, 1.0, -1.0, -1.0]).astype(np.complex128))
+    return g
+
+
+def dirac(N=18, K=0.1, dims=4) -> CSR:
+    """Free Wilson-Dirac fermion matrix of the paper's second example on a
+    periodic N^dims lattice: L = 1 + K sum_mu [(1 + gamma_mu) shift_+mu +
+    (1 - gamma_mu) shift_-mu], where (shift_+mu psi)_x = psi_{x + mu}.  Rank
+    4 N^dims, 14 stored entries per row (identity, two per spatial hop, one per
+    time hop since gamma_4 is diagonal).  Index = site + N^dims * spinor, site
+    = x_1 + N x_2 + N^2 x_3 + N^3 x_4 (direction 4 is time)."""
+    if dims != 4:
+        raise ValueError("the Dirac matrices are 4 x 4: dims = 4")
+    if N < 3:
+        raise ValueError("N >= 3 keeps the +mu and -mu neighbours distinct")
+    V = N ** dims
+    g = dirac_gammas()
+    site = np.arange(V, dtype=np.int64)
+    rows, cols, vals = [np.arange(4 * V, dtype=np.int64)], [np.arange(4 * V, dtype=np.int64)], \
+        [np.ones(4 * V, dtype=np.complex128)]
+    for mu in range(dims):
+        stride = N ** mu
+        x = (site // stride) % N
+        up = site + (((x + 1) % N) - x) * stride
+        dn = site + (((x - 1) % N) - x) * stride
+        for nb, sign in ((up, 1.0), (dn, -1.0)):
+            block = np.eye(4, dtype=np.complex128) + sign * g[mu]
+            for a in range(4):
+                for b in range(4):
+                    if block[a, b] != 0:
+                        rows.append(site + a * V)
+                        cols.append(nb + b * V)
+                        vals.append(np.full(V, K * block[a, b], dtype=np.complex128))
+    m = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(4 * V, 4 * V)).tocsr()
+    m.sort_indices()
+    return CSR(n=4 * V, row_ptr=m.indptr.astype(np.int64), col=m.indices.astype(np.int32),
+               val=np.ascontiguousarray(m.data))
+
+
 def batched_sizes(m=512, lo=1000, hi=50000, seed=1003):
     """Matrix orders drawn log-uniform in [lo, hi]."""
     rng = np.random.default_rng(seed)
@@ -241,4 +291,6 @@ WORKLOADS = {
                     samples=2000, dtype="f32", block=128),
     "surrogate": dict(kind="surrogate", train=2000, train_n=20000, eval_n=1_000_000,
                       seed=1004, noise_seed=0x412107 + 4),
+    "dirac": dict(kind="dirac", N=18, K=0.1, noise_seed=0x412107 + 5, pairs=1024, groups=32,
+                  rel_se=1e-5, dtype="c64"),
 }

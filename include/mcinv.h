@@ -160,6 +160,13 @@ mcinv_status mcinv_sample(mcinv_ctx* ctx, int64_t sweeps);
 mcinv_status mcinv_sample_until(mcinv_ctx* ctx, double rel_se, int64_t max_sweeps,
                                 int64_t check_every, int64_t* sweeps_done, double* achieved);
 
+/* Sample in chunks of check_every sweeps until the trace estimate's standard
+ * error (Geyer's initial positive sequence on the per-sweep series, Sec. 2.3)
+ * relative to |estimate| is <= rel_se, or max_sweeps -- the stopping rule of
+ * the paper's numerical tests.  Needs MCINV_REQ_TRACE. */
+mcinv_status mcinv_sample_until_trace(mcinv_ctx* ctx, double rel_se, int64_t max_sweeps, int64_t check_every,
+                                      int64_t* sweeps_done, double* achieved);
+
 /* Estimates and standard errors in original indexing, caller-allocated.
  * quantity: one of MCINV_REQ_DIAG (n values), MCINV_REQ_BLOCK (rows x cols,
  * row-major), MCINV_REQ_ENTRIES (n_entries), MCINV_REQ_TRACE (1 value).

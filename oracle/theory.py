@@ -65,3 +65,17 @@ def lattice_constant_phase_inverse_diag(L, k, a, b, theta, theta_p, dims=4):
                     + b[mu] * np.exp(-1j * (theta_p[mu] + grids[mu])))
     tr = np.sum(1.0 / lam)
     return tr / L ** dims, tr
+
+
+def dirac_free_trace(N, K, dims=4):
+    """tr L^-1 of the free Wilson-Dirac matrix L = 1 + K sum_mu [(1 + gamma_mu)
+    shift_+mu + (1 - gamma_mu) shift_-mu] on a periodic N^4 lattice.  Plane
+    waves e^{i p.x}, p_mu = 2 pi m / N, block-diagonalise L into the 4 x 4
+    matrices a(p) + i sum_mu b_mu(p) gamma_mu with a = 1 + 2K sum_mu cos p_mu
+    and b_mu = 2K sin p_mu; the gamma anticommutation gives their inverse as
+    (a - i b.gamma) / (a^2 + |b|^2), whose trace is 4a / (a^2 + |b|^2)."""
+    p = 2.0 * np.pi * np.arange(N) / N
+    grids = np.meshgrid(*([p] * dims), indexing="ij")
+    a = 1.0 + 2.0 * K * sum(np.cos(g) for g in grids)
+    b2 = 4.0 * K * K * sum(np.sin(g) ** 2 for g in grids)
+    return float(np.sum(4.0 * a / (a * a + b2)))

@@ -97,6 +97,10 @@ class Sampler:
     def sample_until(self, rel_se, max_sweeps, check_every=10):
         return mcinv_sample_until(self.ctx, rel_se, max_sweeps, check_every)
 
+    def sample_until_trace(self, rel_se, max_sweeps, check_every=20):
+        from ._binding import mcinv_sample_until_trace
+        return mcinv_sample_until_trace(self.ctx, rel_se, max_sweeps, check_every)
+
     def diag(self):
         return mcinv_read_estimates(self.ctx, MCINV_REQ_DIAG, self.n, self.is_complex)
 

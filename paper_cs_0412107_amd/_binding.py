@@ -123,6 +123,7 @@ SIGNATURES = {
     "mcinv_burn_in_coupled": (_I32, [_P, _D, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "mcinv_sample": (_I32, [_P, _I64]),
     "mcinv_sample_until": (_I32, [_P, _D, _I64, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_D)]),
+    "mcinv_sample_until_trace": (_I32, [_P, _D, _I64, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_D)]),
     "mcinv_read_estimates": (_I32, [_P, _U32, _P, _P, _I64]),
     "mcinv_read_state": (_I32, [_P, _I32, _P, _I64]),
     "mcinv_write_state": (_I32, [_P, _I32, _P, _I64]),
@@ -260,6 +261,14 @@ def mcinv_sample_until(ctx, rel_se, max_sweeps, check_every):
     ach = ctypes.c_double(0)
     _check(ctx, lib().mcinv_sample_until(ctx, float(rel_se), int(max_sweeps), int(check_every),
                                          ctypes.byref(done), ctypes.byref(ach)))
+    return done.value, ach.value
+
+
+def mcinv_sample_until_trace(ctx, rel_se, max_sweeps, check_every):
+    done = ctypes.c_int64(0)
+    ach = ctypes.c_double(0)
+    _check(ctx, lib().mcinv_sample_until_trace(ctx, float(rel_se), int(max_sweeps), int(check_every),
+                                               ctypes.byref(done), ctypes.byref(ach)))
     return done.value, ach.value
 
 

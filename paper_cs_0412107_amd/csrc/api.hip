@@ -791,6 +791,35 @@ mcinv_status mcinv_sample_until(mcinv_ctx* c, double rel_se, int64_t max_sweeps,
     return MCINV_OK;
 }
 
+mcinv_status mcinv_sample_until_trace(mcinv_ctx* c, double rel_se, int64_t max_sweeps, int64_t check_every,
+                                      int64_t* sweeps_done, double* achieved)
+{
+    MC_TRY(check_ready(c));
+    if (!c->requested || !(c->flags & MCINV_REQ_TRACE))
+        return fail(c, MCINV_ESTATE, "sample_until_trace needs MCINV_REQ_TRACE requested");
+    if (check_every < 1 || max_sweeps < 0) return fail(c, MCINV_EINVAL, "bad sweep counts");
+    int64_t done = 0;
+    double rel = INFINITY;
+    while (done < max_sweeps) {
+        const int64_t chunk = std::min(check_every, max_sweeps - done);
+        MC_TRY(dispatch_sweeps(c, chunk, true));
+        c->sweeps += chunk;
+        done += chunk;
+        MC_TRY(check_flag(c));
+        HIP_TRY(c, launch_geyer(c->d_series, c->samples, c->comps, 1.0 / (double)c->P, c->d_geyer, c->stream));
+        double g[6];
+        HIP_TRY(c, hipMemcpyAsync(g, c->d_geyer, sizeof(g), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        const double mag = std::sqrt(g[0] * g[0] + (c->comps == 2 ? g[1] * g[1] : 0.0));
+        rel = g[5] / mag;
+        if (!(rel >= 0.0)) rel = INFINITY;
+        if (rel <= rel_se) break;
+    }
+    if (sweeps_done) *sweeps_done = done;
+    if (achieved) *achieved = rel;
+    return MCINV_OK;
+}
+
 mcinv_status mcinv_read_estimates(mcinv_ctx* c, uint32_t quantity, double* est, double* stderr_, int64_t capacity)
 {
     MC_TRY(check_ready(c));
