@@ -81,6 +81,7 @@ typedef int32_t mcinv_status;
 #define MCINV_REQ_TRACE   2u
 #define MCINV_REQ_BLOCK   4u
 #define MCINV_REQ_ENTRIES 8u
+#define MCINV_REQ_QTRACE  16u  /* tr(Q C^-1) for the Q of mcinv_set_trace_matrix */
 
 typedef struct mcinv_ctx mcinv_ctx;
 
@@ -208,6 +209,16 @@ mcinv_status mcinv_burn_in_coupled(mcinv_ctx* ctx, double tol, int64_t max_sweep
  * difference obeys.  Returns the observed contraction rates, which tend to
  * sp(T) and sp(S) (Sec. 2.3).  Does not touch the chain state.  iters >= 2. */
 mcinv_status mcinv_check_convergence(mcinv_ctx* ctx, int64_t iters, double* rho_T, double* rho_S);
+
+/* A sparse Q for tr(Q C^-1) = E[w^dagger Q z] (eq tr; Algorithm 1, step 8
+ * accumulates this product per sweep): n x n CSR in original indices,
+ * values of value_dtype (MCINV_R64, or MCINV_C128 with a complex sweep
+ * dtype), any column order.  Request it with MCINV_REQ_QTRACE; the estimate
+ * and its Geyer standard error are read with quantity MCINV_REQ_QTRACE and
+ * mcinv_sample_until_trace stops on it when requested.  Kept until the next
+ * mcinv_load_csr.  ESTATE while MCINV_REQ_QTRACE is requested. */
+mcinv_status mcinv_set_trace_matrix(mcinv_ctx* ctx, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
+                                    const void* values, int32_t value_dtype);
 
 /* Restrict the stop check of mcinv_sample_until (max SE/|est| of the
  * diagonal) to the given original rows; count 0 restores every row.  The

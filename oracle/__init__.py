@@ -266,7 +266,23 @@ class Run:
     def sample(self, sweeps):
         if self.mom is None:
             raise OracleError("request() first")
-        self._run(int(sweeps), True)
+        if getattr(self, "Q", None) is None:
+            self._run(int(sweeps), True)
+            return
+        for _ in range(int(sweeps)):
+            self._run(1, True)
+            # eq tr with a general Q: sum over the pairs of w^dagger Q z, after this sweep
+            self.qseries.append(complex(np.sum(np.conj(self.w) * (self.Q @ self.z))))
+
+    def set_trace_matrix(self, Q):
+        """Q (scipy sparse, n x n) for tr(Q C^-1) = E[w^dagger Q z]; call before sample()."""
+        self.Q = Q.tocsr().astype(np.complex128)
+        self.qseries = []
+
+    def qtrace(self):
+        """tr(Q C^-1) estimate and Geyer standard error from the per-sweep series."""
+        x = np.array(self.qseries, dtype=np.complex128) / self.pair_ids.size
+        return geyer_ips(x)
 
     @property
     def samples_done(self):

@@ -69,8 +69,25 @@ class Sampler:
     def __exit__(self, *exc):
         self.close()
 
-    def request(self, diag=True, trace=True, block_rows=None, block_cols=None, entries=None):
-        flags = (MCINV_REQ_DIAG if diag else 0) | (MCINV_REQ_TRACE if trace else 0)
+    def set_trace_matrix(self, Q):
+        """Q (CSR with row_ptr, col, val, or a scipy sparse matrix) for tr(Q C^-1)."""
+        from ._binding import mcinv_set_trace_matrix
+        if hasattr(Q, "tocsr"):
+            Q = Q.tocsr()
+            rp, ci, v = Q.indptr, Q.indices, Q.data
+        else:
+            rp, ci, v = Q.row_ptr, Q.col, Q.val
+        mcinv_set_trace_matrix(self.ctx, self.n, rp, ci, v)
+
+    def qtrace(self):
+        from ._binding import MCINV_REQ_QTRACE
+        est, se = mcinv_read_estimates(self.ctx, MCINV_REQ_QTRACE, 1, self.is_complex)
+        return est[0], se[0]
+
+    def request(self, diag=True, trace=True, block_rows=None, block_cols=None, entries=None, qtrace=False):
+        from ._binding import MCINV_REQ_QTRACE
+        flags = (MCINV_REQ_DIAG if diag else 0) | (MCINV_REQ_TRACE if trace else 0) | \
+            (MCINV_REQ_QTRACE if qtrace else 0)
         ei = ej = None
         if block_rows is not None and block_cols is not None and len(block_rows) and len(block_cols):
             flags |= MCINV_REQ_BLOCK

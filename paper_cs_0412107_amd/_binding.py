@@ -28,6 +28,7 @@ MCINV_R32, MCINV_R64, MCINV_C64, MCINV_C128 = 0, 1, 2, 3
 MCINV_NOISE_NORMAL, MCINV_NOISE_RADEMACHER, MCINV_NOISE_NONE = 0, 1, 2
 MCINV_MOMENTS_FP64, MCINV_MOMENTS_BF16X3 = 0, 1
 MCINV_REQ_DIAG, MCINV_REQ_TRACE, MCINV_REQ_BLOCK, MCINV_REQ_ENTRIES = 1, 2, 4, 8
+MCINV_REQ_QTRACE = 16
 
 DTYPES = {"f32": MCINV_R32, "f64": MCINV_R64, "c64": MCINV_C64, "c128": MCINV_C128}
 NP_STATE = {MCINV_R32: np.float32, MCINV_R64: np.float64, MCINV_C64: np.complex64,
@@ -129,6 +130,7 @@ SIGNATURES = {
     "mcinv_write_state": (_I32, [_P, _I32, _P, _I64]),
     "mcinv_get_permutation": (_I32, [_P, _P, _P]),
     "mcinv_set_stop_rows": (_I32, [_P, _P, _I64]),
+    "mcinv_set_trace_matrix": (_I32, [_P, _I64, _P, _P, _P, _I32]),
     "mcinv_check_convergence": (_I32, [_P, _I64, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "mcinv_get_info": (_I32, [_P, ctypes.POINTER(mcinv_info)]),
     "mcinv_reset_profile": (_I32, [_P]),
@@ -290,6 +292,20 @@ def mcinv_read_state(ctx, which, n, P, sweep_dtype):
 def mcinv_write_state(ctx, which, state, sweep_dtype):
     a = np.ascontiguousarray(state, dtype=NP_STATE[sweep_dtype])
     _check(ctx, lib().mcinv_write_state(ctx, which, _ptr(a), a.nbytes))
+
+
+def mcinv_set_trace_matrix(ctx, n, row_ptr, col_idx, values):
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    if np.iscomplexobj(values):
+        v = np.ascontiguousarray(values, dtype=np.complex128).view(np.float64)
+        vd = MCINV_C128
+    else:
+        v = np.ascontiguousarray(values, dtype=np.float64)
+        vd = MCINV_R64
+    if rp.size != n + 1:
+        raise ValueError("row_ptr must have n + 1 entries")
+    _check(ctx, lib().mcinv_set_trace_matrix(ctx, int(rp[-1]), _ptr(rp), _ptr(ci), _ptr(v), vd))
 
 
 def mcinv_set_stop_rows(ctx, rows=None):

@@ -101,6 +101,14 @@ struct mcinv_ctx {
     unsigned long long* d_maxrel = nullptr;
     double* d_geyer = nullptr;
     uint8_t* d_stop = nullptr;   // rows the stop check covers (null: every row)
+    // general trace matrix Q (eq tr), position order
+    int64_t* d_qrp = nullptr;
+    int64_t* d_qcol = nullptr;
+    void* d_qval = nullptr;
+    int64_t q_nnz = -1;          // -1: no Q loaded
+    double* d_qpart = nullptr;
+    double* d_qseries = nullptr;
+    int64_t qseries_cap = 0;
 
     // profiling
     std::vector<hipEvent_t> events;
@@ -158,6 +166,9 @@ void free_requests(mcinv_ctx* c)
     dfree(c->d_tpart);
     dfree(c->d_series);
     dfree(c->d_slot_len);
+    dfree(c->d_qpart);
+    dfree(c->d_qseries);
+    c->qseries_cap = 0;
     c->series_cap = 0;
     c->requested = false;
     c->flags = 0;
@@ -174,6 +185,10 @@ void free_matrix(mcinv_ctx* c)
     dfree(c->d_w);
     dfree(c->d_perm);
     dfree(c->d_stop);
+    dfree(c->d_qrp);
+    dfree(c->d_qcol);
+    dfree(c->d_qval);
+    c->q_nnz = -1;
     dfree(c->d_est);
     dfree(c->d_se);
     c->est_cap = 0;
@@ -230,22 +245,26 @@ mcinv_status upload_matrix(mcinv_ctx* c, const Prepared& h)
 }
 
 // ------------------------------------------------------------ the sweeps --
-mcinv_status grow_series(mcinv_ctx* c, int64_t need)
+int64_t qtrace_partials(const mcinv_ctx* c) { return (c->n + 3) / 4 * c->ntiles; }
+
+mcinv_status grow_series(mcinv_ctx* c, int64_t need, double** series, int64_t* series_cap)
 {
-    if (need <= c->series_cap) return MCINV_OK;
-    int64_t cap = std::max<int64_t>(4096, c->series_cap);
+    if (need <= *series_cap) return MCINV_OK;
+    int64_t cap = std::max<int64_t>(4096, *series_cap);
     while (cap < need) cap *= 2;
     double* nb = nullptr;
     MC_TRY(dalloc(c, &nb, (size_t)(cap * c->comps)));
-    if (c->d_series && c->samples > 0)
-        HIP_TRY(c, hipMemcpyAsync(nb, c->d_series, sizeof(double) * c->samples * c->comps, hipMemcpyDeviceToDevice,
+    if (*series && c->samples > 0)
+        HIP_TRY(c, hipMemcpyAsync(nb, *series, sizeof(double) * c->samples * c->comps, hipMemcpyDeviceToDevice,
                                   c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
-    dfree(c->d_series);
-    c->d_series = nb;
-    c->series_cap = cap;
+    dfree(*series);
+    *series = nb;
+    *series_cap = cap;
     return MCINV_OK;
 }
+
+mcinv_status grow_series(mcinv_ctx* c, int64_t need) { return grow_series(c, need, &c->d_series, &c->series_cap); }
 
 hipEvent_t take_event(mcinv_ctx* c, size_t& next)
 {
@@ -351,6 +370,22 @@ mcinv_status run_sweeps(mcinv_ctx* c, int64_t nsw, bool sample, V* z, V* w, int6
             MC_TRY(grow_series(c, c->samples + 1));
             HIP_TRY(c, launch_reduce_sum(c->d_tpart, c->npart, c->comps, c->d_partial, c->d_counter,
                                          c->d_series + c->samples * c->comps, c->stream));
+        }
+        if (c->flags & MCINV_REQ_QTRACE) {
+            MC_TRY(grow_series(c, c->samples + 1, &c->d_qseries, &c->qseries_cap));
+            QTraceArgs<V> qa{};
+            qa.z = z;
+            qa.w = w;
+            qa.ld = ld;
+            qa.P = P;
+            qa.n = c->n;
+            qa.qrp = c->d_qrp;
+            qa.qcol = c->d_qcol;
+            qa.qval = (const V*)c->d_qval;
+            qa.part = c->d_qpart;
+            HIP_TRY(c, launch_qtrace<V>(qa, c->stream));
+            HIP_TRY(c, launch_reduce_sum(c->d_qpart, qtrace_partials(c), c->comps, c->d_partial, c->d_counter,
+                                         c->d_qseries + c->samples * c->comps, c->stream));
         }
         hipEvent_t m0 = nullptr, m1 = nullptr;
         const bool any_moment = (c->flags & MCINV_REQ_BLOCK) || (c->flags & MCINV_REQ_ENTRIES);
@@ -685,8 +720,10 @@ mcinv_status mcinv_set_requested(mcinv_ctx* c, uint32_t flags, const int64_t* bl
                                  const int64_t* entry_j, int64_t n_entries)
 {
     MC_TRY(check_ready(c));
-    if (flags & ~(MCINV_REQ_DIAG | MCINV_REQ_TRACE | MCINV_REQ_BLOCK | MCINV_REQ_ENTRIES))
+    if (flags & ~(MCINV_REQ_DIAG | MCINV_REQ_TRACE | MCINV_REQ_BLOCK | MCINV_REQ_ENTRIES | MCINV_REQ_QTRACE))
         return fail(c, MCINV_EINVAL, "unknown request flag");
+    if ((flags & MCINV_REQ_QTRACE) && c->q_nnz < 0)
+        return fail(c, MCINV_ESTATE, "MCINV_REQ_QTRACE needs mcinv_set_trace_matrix first");
     const bool want_block = (flags & MCINV_REQ_BLOCK) && n_block_rows > 0 && n_block_cols > 0;
     const bool want_entries = (flags & MCINV_REQ_ENTRIES) && n_entries > 0;
     if (want_block && (!block_rows || !block_cols)) return fail(c, MCINV_EINVAL, "null block index arrays");
@@ -722,6 +759,10 @@ mcinv_status mcinv_set_requested(mcinv_ctx* c, uint32_t flags, const int64_t* bl
     if (c->flags & MCINV_REQ_TRACE) {
         MC_TRY(dalloc(c, &c->d_tpart, (size_t)(c->npart * c->comps)));
         MC_TRY(grow_series(c, 4096));
+    }
+    if (c->flags & MCINV_REQ_QTRACE) {
+        MC_TRY(dalloc(c, &c->d_qpart, (size_t)(qtrace_partials(c) * c->comps)));
+        MC_TRY(grow_series(c, 4096, &c->d_qseries, &c->qseries_cap));
     }
     if (c->flags & MCINV_REQ_BLOCK) {
         MC_TRY(upload(c, &c->d_I, I));
@@ -795,8 +836,9 @@ mcinv_status mcinv_sample_until_trace(mcinv_ctx* c, double rel_se, int64_t max_s
                                       int64_t* sweeps_done, double* achieved)
 {
     MC_TRY(check_ready(c));
-    if (!c->requested || !(c->flags & MCINV_REQ_TRACE))
-        return fail(c, MCINV_ESTATE, "sample_until_trace needs MCINV_REQ_TRACE requested");
+    if (!c->requested || !(c->flags & (MCINV_REQ_TRACE | MCINV_REQ_QTRACE)))
+        return fail(c, MCINV_ESTATE, "sample_until_trace needs MCINV_REQ_TRACE or MCINV_REQ_QTRACE requested");
+    const bool use_q = (c->flags & MCINV_REQ_QTRACE) != 0;
     if (check_every < 1 || max_sweeps < 0) return fail(c, MCINV_EINVAL, "bad sweep counts");
     int64_t done = 0;
     double rel = INFINITY;
@@ -806,7 +848,8 @@ mcinv_status mcinv_sample_until_trace(mcinv_ctx* c, double rel_se, int64_t max_s
         c->sweeps += chunk;
         done += chunk;
         MC_TRY(check_flag(c));
-        HIP_TRY(c, launch_geyer(c->d_series, c->samples, c->comps, 1.0 / (double)c->P, c->d_geyer, c->stream));
+        HIP_TRY(c, launch_geyer(use_q ? c->d_qseries : c->d_series, c->samples, c->comps, 1.0 / (double)c->P,
+                                c->d_geyer, c->stream));
         double g[6];
         HIP_TRY(c, hipMemcpyAsync(g, c->d_geyer, sizeof(g), hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -837,10 +880,11 @@ mcinv_status mcinv_read_estimates(mcinv_ctx* c, uint32_t quantity, double* est, 
         M = c->ne;
         if (capacity < M) return fail(c, MCINV_EINVAL, "capacity too small");
         MC_TRY(finalize_flat(c, c->d_entries, M, c->entry_slot_stride()));
-    } else if (quantity == MCINV_REQ_TRACE) {
+    } else if (quantity == MCINV_REQ_TRACE || quantity == MCINV_REQ_QTRACE) {
         if (capacity < 1) return fail(c, MCINV_EINVAL, "capacity too small");
         if (c->samples < 1) return fail(c, MCINV_ESTATE, "no samples yet");
-        HIP_TRY(c, launch_geyer(c->d_series, c->samples, c->comps, 1.0 / (double)c->P, c->d_geyer, c->stream));
+        const double* series = quantity == MCINV_REQ_TRACE ? c->d_series : c->d_qseries;
+        HIP_TRY(c, launch_geyer(series, c->samples, c->comps, 1.0 / (double)c->P, c->d_geyer, c->stream));
         double g[6];
         HIP_TRY(c, hipMemcpyAsync(g, c->d_geyer, sizeof(g), hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -888,6 +932,69 @@ mcinv_status mcinv_write_state(mcinv_ctx* c, int32_t which, const void* host, in
         std::memcpy(tmp.data() + (size_t)c->pos[i] * c->ld * c->elem, in + (size_t)i * row_bytes, row_bytes);
     HIP_TRY(c, hipMemcpyAsync(which ? c->d_w : c->d_z, tmp.data(), tmp.size(), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return MCINV_OK;
+}
+
+}  // extern "C"
+
+template <typename V>
+static mcinv_status upload_q(mcinv_ctx* c, const std::vector<int64_t>& rp, const std::vector<int64_t>& col,
+                             const std::vector<cd>& val)
+{
+    std::vector<V> v(val.size());
+    for (size_t e = 0; e < val.size(); ++e) v[e] = cast_val<V>(val[e]);
+    dfree(c->d_qrp);
+    dfree(c->d_qcol);
+    dfree(c->d_qval);
+    MC_TRY(upload(c, &c->d_qrp, rp));
+    MC_TRY(upload(c, &c->d_qcol, col));
+    V* dv = nullptr;
+    MC_TRY(dalloc(c, &dv, std::max<size_t>(v.size(), 1)));
+    if (!v.empty()) HIP_TRY(c, hipMemcpy(dv, v.data(), sizeof(V) * v.size(), hipMemcpyHostToDevice));
+    c->d_qval = dv;
+    return MCINV_OK;
+}
+
+extern "C" {
+
+mcinv_status mcinv_set_trace_matrix(mcinv_ctx* c, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
+                                    const void* values, int32_t value_dtype)
+{
+    MC_TRY(check_ready(c));
+    if (c->requested && (c->flags & MCINV_REQ_QTRACE))
+        return fail(c, MCINV_ESTATE, "Q cannot change while MCINV_REQ_QTRACE is requested");
+    if (value_dtype != MCINV_R64 && value_dtype != MCINV_C128)
+        return fail(c, MCINV_EINVAL, "Q values must be float64 or complex128");
+    if (value_dtype == MCINV_C128 && !c->cplx) return fail(c, MCINV_EINVAL, "a complex Q needs a complex sweep dtype");
+    if (nnz < 0 || !row_ptr || (nnz > 0 && (!col_idx || !values))) return fail(c, MCINV_EINVAL, "bad Q arrays");
+    const int64_t n = c->n;
+    if (row_ptr[0] != 0 || row_ptr[n] != nnz) return fail(c, MCINV_EINVAL, "Q row_ptr[0] must be 0, row_ptr[n] nnz");
+    for (int64_t i = 0; i < n; ++i) {
+        if (row_ptr[i + 1] < row_ptr[i]) return fail(c, MCINV_EINVAL, "Q row_ptr is decreasing");
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
+            if (col_idx[e] < 0 || col_idx[e] >= n) return fail(c, MCINV_EINVAL, "Q column out of range");
+    }
+    const double* vd = (const double*)values;
+    std::vector<int64_t> rp(n + 1, 0), col;
+    std::vector<cd> val;
+    col.reserve(nnz);
+    val.reserve(nnz);
+    for (int64_t q = 0; q < n; ++q) {
+        const int64_t i = c->perm[q];
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            col.push_back(c->pos[col_idx[e]]);
+            val.push_back(value_dtype == MCINV_C128 ? cd(vd[2 * e], vd[2 * e + 1]) : cd(vd[e], 0.0));
+        }
+        rp[q + 1] = (int64_t)col.size();
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    switch (c->cfg.sweep_dtype) {
+    case MCINV_R32: MC_TRY(upload_q<float>(c, rp, col, val)); break;
+    case MCINV_R64: MC_TRY(upload_q<double>(c, rp, col, val)); break;
+    case MCINV_C64: MC_TRY(upload_q<Cx<float>>(c, rp, col, val)); break;
+    default: MC_TRY(upload_q<Cx<double>>(c, rp, col, val)); break;
+    }
+    c->q_nnz = nnz;
     return MCINV_OK;
 }
 

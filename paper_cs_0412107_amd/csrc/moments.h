@@ -35,6 +35,21 @@ hipError_t launch_entries(const V* z, const V* w, int64_t ld, const int64_t* ei,
 // acc[m] = acc[2m] + acc[2m+1] for m < half, acc[m] = 0 for half <= m < 2 half.
 hipError_t launch_merge_slots(double* acc, int64_t slot_elems, int64_t half, hipStream_t stream);
 
+// Per-sample sum over pairs of w^dagger Q z for a sparse Q in position order
+// (CSR qrp[n+1], qcol, qval); partials: ceil(n/4) x pair tiles (x comps).
+template <typename V>
+struct QTraceArgs {
+    const V* z;
+    const V* w;
+    int64_t ld, P, n;
+    const int64_t* qrp;
+    const int64_t* qcol;
+    const V* qval;
+    double* part;
+};
+template <typename V>
+hipError_t launch_qtrace(const QTraceArgs<V>& a, hipStream_t stream);
+
 // Largest magnitude of x[q * ld], q < n, into *out (double bits, atomic max;
 // clear *out first).
 template <typename V>

@@ -155,6 +155,72 @@ template hipError_t launch_entries<Cx<float>>(const Cx<float>*, const Cx<float>*
 template hipError_t launch_entries<Cx<double>>(const Cx<double>*, const Cx<double>*, int64_t, const int64_t*,
                                                const int64_t*, int64_t, int64_t, int64_t, double*, hipStream_t);
 
+// ---------------------------------------------------------------- Q trace --
+// Per-sample value of w^dagger Q z summed over the chain pairs (eq tr with a
+// general sparse Q): a wave takes one row q of Q (position order) and 256
+// pairs, forms (Q z)_q in fp64 and multiplies by conj(w_q); one fp64 partial
+// (x2 complex) per workgroup at part[(tile * gridDim.x + row block) * comps].
+template <typename V>
+__global__ __launch_bounds__(256) void k_qtrace(const QTraceArgs<V> a)
+{
+    using W = typename Wide<V>::type;
+    constexpr int comps = IsCx<V>::value ? 2 : 1;
+    __shared__ double lds[4][2];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int64_t q = (int64_t)blockIdx.x * 4 + wid;
+    const int64_t p0 = (int64_t)blockIdx.y * kPairsPerWave + lane * kPairsPerLane;
+    W t = vzero<W>();
+    if (q < a.n && p0 < a.ld) {
+        W acc[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[j] = vzero<W>();
+        for (int64_t e = a.qrp[q]; e < a.qrp[q + 1]; ++e) {
+            const W qv = widen(a.qval[e]);
+            const V* zr = a.z + a.qcol[e] * a.ld + p0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) acc[j] = mul_add(qv, widen(zr[j]), acc[j]);
+        }
+        const V* wr = a.w + q * a.ld + p0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (p0 + j < a.P) t = conj_fma(acc[j], widen(wr[j]), t);
+    }
+    double re, im = 0.0;
+    if constexpr (comps == 2) {
+        re = t.re;
+        im = t.im;
+    } else {
+        re = t;
+    }
+    for (int off = 1; off < 64; off <<= 1) {
+        re += __shfl_xor(re, off);
+        if constexpr (comps == 2) im += __shfl_xor(im, off);
+    }
+    if (lane == 0) {
+        lds[wid][0] = re;
+        lds[wid][1] = im;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int64_t slot = (int64_t)blockIdx.y * gridDim.x + blockIdx.x;
+        a.part[slot * comps] = ((lds[0][0] + lds[1][0]) + lds[2][0]) + lds[3][0];
+        if constexpr (comps == 2) a.part[slot * 2 + 1] = ((lds[0][1] + lds[1][1]) + lds[2][1]) + lds[3][1];
+    }
+}
+
+template <typename V>
+hipError_t launch_qtrace(const QTraceArgs<V>& a, hipStream_t stream)
+{
+    if (a.n <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((a.n + 3) / 4), (unsigned)((a.ld + kPairsPerWave - 1) / kPairsPerWave));
+    k_qtrace<V><<<grid, dim3(256), 0, stream>>>(a);
+    return hipGetLastError();
+}
+template hipError_t launch_qtrace<float>(const QTraceArgs<float>&, hipStream_t);
+template hipError_t launch_qtrace<double>(const QTraceArgs<double>&, hipStream_t);
+template hipError_t launch_qtrace<Cx<float>>(const QTraceArgs<Cx<float>>&, hipStream_t);
+template hipError_t launch_qtrace<Cx<double>>(const QTraceArgs<Cx<double>>&, hipStream_t);
+
 // ------------------------------------------------------------ slot merge --
 // One thread per element walks the slots upwards: slot m is written only
 // after slots 2m and 2m+1 (both >= m) were read, so the update is in place.

@@ -250,3 +250,33 @@ def test_lattice_estimates_within_error():
     assert np.mean(z) < 1.6 and np.max(z) < 5.5
     t = r.trace()
     assert abs(t["mean"] - tr) < 5 * t["se"]
+
+
+# --- eq tr with a general Q (Algorithm 1, step 8) ---------------------------------
+def test_qtrace_estimates_tr_QCinv_not_its_conjugate():
+    """E[w^dagger Q z] = tr(Q C^-1).  With complex non-hermitian C and Q the
+    conjugate reading tr(Q C^-dagger) is many standard errors away."""
+    import scipy.sparse as sp
+    n = 10
+    C = _dense_random(n, 41, True, factor=1.3)
+    rng = np.random.default_rng(42)
+    Qd = (rng.uniform(-1, 1, (n, n)) + 1j * rng.uniform(-1, 1, (n, n))) * (rng.random((n, n)) < 0.3)
+    Qd += 3j * np.eye(n)
+    Ci = np.linalg.inv(C)
+    exact = np.trace(Qd @ Ci)
+    wrong = np.trace(Qd @ Ci.conj().T)
+    run = oracle.Run(gen.from_dense(C), seed=3, pairs=64)
+    run.burn_in(30)
+    run.request(600, diag=False, trace=True)
+    run.set_trace_matrix(sp.csr_matrix(Qd))
+    run.sample(600)
+    g = run.qtrace()
+    assert abs(g["mean"] - exact) <= 4.5 * g["se"]
+    assert abs(g["mean"] - wrong) >= 10 * g["se"]
+    # Q = I reproduces the plain trace series of eq tr
+    run2 = oracle.Run(gen.from_dense(C), seed=3, pairs=64)
+    run2.burn_in(30)
+    run2.request(50, diag=False, trace=True)
+    run2.set_trace_matrix(sp.identity(n, format="csr"))
+    run2.sample(50)
+    assert np.allclose(np.array(run2.qseries), run2.series[:50], rtol=1e-13, atol=0)
