@@ -220,6 +220,18 @@ mcinv_status mcinv_check_convergence(mcinv_ctx* ctx, int64_t iters, double* rho_
 mcinv_status mcinv_set_trace_matrix(mcinv_ctx* ctx, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
                                     const void* values, int32_t value_dtype);
 
+/* Checkpoint / resume.  mcinv_save writes the chain state, the requested
+ * set, every moment accumulator, the trace series and the counters to a file;
+ * mcinv_restore reads it into a context created with the same configuration
+ * (pairs, groups, dtype, seed, stream_id, noise, hermitian) on which the same
+ * matrix has been loaded (the colour order is fingerprinted; the values are
+ * the caller's responsibility) and, if the checkpoint requested
+ * MCINV_REQ_QTRACE, the same Q set.  The restored context continues exactly
+ * as the saved one would (same noise counters, same sums).  EINVAL on a
+ * mismatch, an unreadable or truncated file. */
+mcinv_status mcinv_save(mcinv_ctx* ctx, const char* path);
+mcinv_status mcinv_restore(mcinv_ctx* ctx, const char* path);
+
 /* Restrict the stop check of mcinv_sample_until (max SE/|est| of the
  * diagonal) to the given original rows; count 0 restores every row.  The
  * estimates of all rows are still computed.  Cleared by mcinv_load_csr. */

@@ -141,6 +141,16 @@ class Sampler:
     def permutation(self):
         return mcinv_get_permutation(self.ctx, self.n)
 
+    def save(self, path):
+        from ._binding import mcinv_save
+        mcinv_save(self.ctx, path)
+
+    def restore(self, path):
+        """Load a checkpoint.  Call ``request`` with the checkpoint's arguments
+        first so that this wrapper knows the block and entry sizes."""
+        from ._binding import mcinv_restore
+        mcinv_restore(self.ctx, path)
+
     def set_stop_rows(self, rows=None):
         """Restrict ``sample_until``'s stop check to these original rows (None: all)."""
         from ._binding import mcinv_set_stop_rows

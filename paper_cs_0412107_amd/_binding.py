@@ -131,6 +131,8 @@ SIGNATURES = {
     "mcinv_get_permutation": (_I32, [_P, _P, _P]),
     "mcinv_set_stop_rows": (_I32, [_P, _P, _I64]),
     "mcinv_set_trace_matrix": (_I32, [_P, _I64, _P, _P, _P, _I32]),
+    "mcinv_save": (_I32, [_P, ctypes.c_char_p]),
+    "mcinv_restore": (_I32, [_P, ctypes.c_char_p]),
     "mcinv_check_convergence": (_I32, [_P, _I64, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "mcinv_get_info": (_I32, [_P, ctypes.POINTER(mcinv_info)]),
     "mcinv_reset_profile": (_I32, [_P]),
@@ -306,6 +308,14 @@ def mcinv_set_trace_matrix(ctx, n, row_ptr, col_idx, values):
     if rp.size != n + 1:
         raise ValueError("row_ptr must have n + 1 entries")
     _check(ctx, lib().mcinv_set_trace_matrix(ctx, int(rp[-1]), _ptr(rp), _ptr(ci), _ptr(v), vd))
+
+
+def mcinv_save(ctx, path):
+    _check(ctx, lib().mcinv_save(ctx, os.fsencode(path)))
+
+
+def mcinv_restore(ctx, path):
+    _check(ctx, lib().mcinv_restore(ctx, os.fsencode(path)))
 
 
 def mcinv_set_stop_rows(ctx, rows=None):

@@ -1016,6 +1016,196 @@ mcinv_status mcinv_set_stop_rows(mcinv_ctx* c, const int64_t* rows, int64_t coun
     return MCINV_OK;
 }
 
+// ------------------------------------------------------------ checkpoint --
+// File layout (native byte order): CkptHeader, slot_len[nslots], the request
+// lists (I, J, entry i, entry j as positions), z, w (absent in hermitian
+// mode), the diagonal / block / entry accumulators that are requested, the
+// trace series and the Q-trace series (samples x comps each, when requested).
+struct CkptHeader {
+    char magic[8];
+    int64_t version, n, nnz, n_off, P, ld, G, dtype, hermitian, noise, stream_id;
+    uint64_t seed, fingerprint;
+    int64_t flags, nI, nJ, ne, sweeps, samples, batch_len, nslots, q_nnz, requested;
+};
+
+}  // extern "C"
+
+static uint64_t fingerprint(const mcinv_ctx* c)
+{
+    uint64_t h = 1469598103934665603ull;  // FNV-1a over the colour order and pattern sizes
+    auto mix = [&](int64_t v) {
+        for (int b = 0; b < 8; ++b) {
+            h ^= (uint64_t)((v >> (8 * b)) & 0xff);
+            h *= 1099511628211ull;
+        }
+    };
+    mix(c->n);
+    mix(c->nnz);
+    mix(c->n_off);
+    for (int64_t v : c->perm) mix(v);
+    for (int64_t v : c->color_ptr) mix(v);
+    return h;
+}
+
+static bool write_all(FILE* f, const void* p, size_t bytes) { return bytes == 0 || fwrite(p, 1, bytes, f) == bytes; }
+static bool read_all(FILE* f, void* p, size_t bytes) { return bytes == 0 || fread(p, 1, bytes, f) == bytes; }
+
+// Device buffer <-> file through a host copy.
+static mcinv_status dev_to_file(mcinv_ctx* c, FILE* f, const void* d, size_t bytes)
+{
+    if (bytes == 0) return MCINV_OK;
+    std::vector<char> h(bytes);
+    HIP_TRY(c, hipMemcpyAsync(h.data(), d, bytes, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (!write_all(f, h.data(), bytes)) return fail(c, MCINV_EINVAL, "checkpoint write failed");
+    return MCINV_OK;
+}
+
+static mcinv_status file_to_dev(mcinv_ctx* c, FILE* f, void* d, size_t bytes)
+{
+    if (bytes == 0) return MCINV_OK;
+    std::vector<char> h(bytes);
+    if (!read_all(f, h.data(), bytes)) return fail(c, MCINV_EINVAL, "checkpoint file is truncated");
+    HIP_TRY(c, hipMemcpyAsync(d, h.data(), bytes, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return MCINV_OK;
+}
+
+static mcinv_status save_body(mcinv_ctx* c, FILE* f)
+{
+    CkptHeader hd{};
+    std::memcpy(hd.magic, "MCINVCK1", 8);
+    hd.version = 1;
+    hd.n = c->n;
+    hd.nnz = c->nnz;
+    hd.n_off = c->n_off;
+    hd.P = c->P;
+    hd.ld = c->ld;
+    hd.G = c->G;
+    hd.dtype = c->cfg.sweep_dtype;
+    hd.hermitian = c->cfg.hermitian ? 1 : 0;
+    hd.noise = c->cfg.noise;
+    hd.stream_id = c->cfg.stream_id;
+    hd.seed = c->cfg.seed;
+    hd.fingerprint = fingerprint(c);
+    hd.flags = c->flags;
+    hd.nI = c->nI;
+    hd.nJ = c->nJ;
+    hd.ne = c->ne;
+    hd.sweeps = c->sweeps;
+    hd.samples = c->samples;
+    hd.batch_len = c->batch_len;
+    hd.nslots = c->nslots;
+    hd.q_nnz = c->q_nnz;
+    hd.requested = c->requested ? 1 : 0;
+    if (!write_all(f, &hd, sizeof(hd)) || !write_all(f, c->slot_len.data(), sizeof(double) * c->slot_len.size()))
+        return fail(c, MCINV_EINVAL, "checkpoint write failed");
+    MC_TRY(dev_to_file(c, f, c->d_I, sizeof(int64_t) * (size_t)c->nI));
+    MC_TRY(dev_to_file(c, f, c->d_J, sizeof(int64_t) * (size_t)c->nJ));
+    MC_TRY(dev_to_file(c, f, c->d_ei, sizeof(int64_t) * (size_t)c->ne));
+    MC_TRY(dev_to_file(c, f, c->d_ej, sizeof(int64_t) * (size_t)c->ne));
+    const size_t state = (size_t)c->n * c->ld * c->elem;
+    MC_TRY(dev_to_file(c, f, c->d_z, state));
+    if (!c->cfg.hermitian) MC_TRY(dev_to_file(c, f, c->d_w, state));
+    if (c->requested) {
+        if (c->flags & MCINV_REQ_DIAG)
+            MC_TRY(dev_to_file(c, f, c->d_diag, sizeof(double) * (size_t)(c->nslots * c->diag_slot_stride())));
+        if (c->flags & MCINV_REQ_BLOCK)
+            MC_TRY(dev_to_file(c, f, c->d_block, sizeof(double) * (size_t)(c->nslots * c->block_slot_stride())));
+        if (c->flags & MCINV_REQ_ENTRIES)
+            MC_TRY(dev_to_file(c, f, c->d_entries, sizeof(double) * (size_t)(c->nslots * c->entry_slot_stride())));
+        if (c->flags & MCINV_REQ_TRACE)
+            MC_TRY(dev_to_file(c, f, c->d_series, sizeof(double) * (size_t)(c->samples * c->comps)));
+        if (c->flags & MCINV_REQ_QTRACE)
+            MC_TRY(dev_to_file(c, f, c->d_qseries, sizeof(double) * (size_t)(c->samples * c->comps)));
+    }
+    return MCINV_OK;
+}
+
+static mcinv_status restore_body(mcinv_ctx* c, FILE* f)
+{
+    CkptHeader hd{};
+    if (!read_all(f, &hd, sizeof(hd)) || std::memcmp(hd.magic, "MCINVCK1", 8) != 0 || hd.version != 1)
+        return fail(c, MCINV_EINVAL, "not an mcinv checkpoint");
+    if (hd.n != c->n || hd.nnz != c->nnz || hd.n_off != c->n_off || hd.fingerprint != fingerprint(c))
+        return fail(c, MCINV_EINVAL, "checkpoint was taken on a different matrix");
+    if (hd.P != c->P || hd.G != c->G || hd.dtype != c->cfg.sweep_dtype || hd.hermitian != (c->cfg.hermitian ? 1 : 0) ||
+        hd.noise != c->cfg.noise || hd.stream_id != (int64_t)c->cfg.stream_id || hd.seed != c->cfg.seed ||
+        hd.nslots != c->nslots)
+        return fail(c, MCINV_EINVAL, "checkpoint was taken with a different configuration");
+    if ((hd.flags & MCINV_REQ_QTRACE) && c->q_nnz != hd.q_nnz)
+        return fail(c, MCINV_ESTATE, "set the same trace matrix Q before restoring");
+    std::vector<double> slot_len((size_t)hd.nslots);
+    if (!read_all(f, slot_len.data(), sizeof(double) * slot_len.size()))
+        return fail(c, MCINV_EINVAL, "checkpoint file is truncated");
+    std::vector<int64_t> I(hd.nI), J(hd.nJ), ei(hd.ne), ej(hd.ne);
+    if (!read_all(f, I.data(), sizeof(int64_t) * I.size()) || !read_all(f, J.data(), sizeof(int64_t) * J.size()) ||
+        !read_all(f, ei.data(), sizeof(int64_t) * ei.size()) || !read_all(f, ej.data(), sizeof(int64_t) * ej.size()))
+        return fail(c, MCINV_EINVAL, "checkpoint file is truncated");
+    for (auto* v : {&I, &J, &ei, &ej})
+        for (int64_t& x : *v) {
+            if (x < 0 || x >= c->n) return fail(c, MCINV_EINVAL, "corrupt checkpoint");
+            x = c->perm[x];   // positions -> original indices
+        }
+    if (hd.requested) {
+        MC_TRY(mcinv_set_requested(c, (uint32_t)hd.flags, I.data(), hd.nI, J.data(), hd.nJ, ei.data(), ej.data(),
+                                   hd.ne));
+    } else {
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        free_requests(c);
+    }
+    const size_t state = (size_t)c->n * c->ld * c->elem;
+    MC_TRY(file_to_dev(c, f, c->d_z, state));
+    if (!c->cfg.hermitian) MC_TRY(file_to_dev(c, f, c->d_w, state));
+    if (hd.requested) {
+        if (c->flags & MCINV_REQ_DIAG)
+            MC_TRY(file_to_dev(c, f, c->d_diag, sizeof(double) * (size_t)(c->nslots * c->diag_slot_stride())));
+        if (c->flags & MCINV_REQ_BLOCK)
+            MC_TRY(file_to_dev(c, f, c->d_block, sizeof(double) * (size_t)(c->nslots * c->block_slot_stride())));
+        if (c->flags & MCINV_REQ_ENTRIES)
+            MC_TRY(file_to_dev(c, f, c->d_entries, sizeof(double) * (size_t)(c->nslots * c->entry_slot_stride())));
+        if (c->flags & MCINV_REQ_TRACE) {
+            MC_TRY(grow_series(c, std::max<int64_t>(hd.samples, 1)));
+            MC_TRY(file_to_dev(c, f, c->d_series, sizeof(double) * (size_t)(hd.samples * c->comps)));
+        }
+        if (c->flags & MCINV_REQ_QTRACE) {
+            MC_TRY(grow_series(c, std::max<int64_t>(hd.samples, 1), &c->d_qseries, &c->qseries_cap));
+            MC_TRY(file_to_dev(c, f, c->d_qseries, sizeof(double) * (size_t)(hd.samples * c->comps)));
+        }
+    }
+    c->sweeps = hd.sweeps;
+    c->samples = hd.samples;
+    c->batch_len = hd.batch_len;
+    c->slot_len = slot_len;
+    HIP_TRY(c, hipMemsetAsync(c->d_flag, 0, sizeof(int32_t), c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return MCINV_OK;
+}
+
+extern "C" {
+
+mcinv_status mcinv_save(mcinv_ctx* c, const char* path)
+{
+    MC_TRY(check_ready(c));
+    if (!path) return fail(c, MCINV_EINVAL, "null path");
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return fail(c, MCINV_EINVAL, std::string("cannot open ") + path + " for writing");
+    const mcinv_status s = save_body(c, f);
+    if (std::fclose(f) != 0 && s == MCINV_OK) return fail(c, MCINV_EINVAL, "checkpoint write failed");
+    return s;
+}
+
+mcinv_status mcinv_restore(mcinv_ctx* c, const char* path)
+{
+    MC_TRY(check_ready(c));
+    if (!path) return fail(c, MCINV_EINVAL, "null path");
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return fail(c, MCINV_EINVAL, std::string("cannot open ") + path);
+    const mcinv_status s = restore_body(c, f);
+    std::fclose(f);
+    return s;
+}
+
 mcinv_status mcinv_get_permutation(mcinv_ctx* c, int64_t* perm, int32_t* color_of_row)
 {
     MC_TRY(check_ready(c));

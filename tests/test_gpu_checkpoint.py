@@ -1,0 +1,111 @@
+"""Checkpoint / resume through the C-ABI: a context restored from a file
+continues bit for bit as the saved one (states, every estimate and standard
+error), in both moment layouts (chain groups and time batches), in hermitian
+mode and with a Q trace; mismatched configurations and damaged files are
+rejected."""
+
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import gen
+from gpu_util import oracle_matrix, print_case
+
+pytestmark = pytest.mark.gpu
+
+mc = pytest.importorskip("paper_cs_0412107_amd")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _estimates(s, with_q):
+    out = [s.diag(), s.trace(), s.block(), s.entries(), (s.state(0), s.state(1))]
+    if with_q:
+        out.append(s.qtrace())
+    return out
+
+
+def _same(a, b):
+    for x, y in zip(a, b):
+        for u, v in zip(x, y):
+            assert np.array_equal(np.asarray(u), np.asarray(v), equal_nan=True)
+
+
+@pytest.mark.parametrize("dtype,G,herm", [("f32", 16, False), ("f64", 1, False), ("c64", 4, False),
+                                          ("f32", 16, True)])
+def test_resume_is_bit_identical(tmp_path, dtype, G, herm):
+    print_case(test="checkpoint", dtype=dtype, G=G, herm=herm)
+    if dtype == "c64":
+        m = gen.lattice(6, k=0.12, seed=91)
+    elif herm:
+        m = gen.pedigree(1500, seed=92, lam=0.0, symmetric=True)
+    else:
+        m = gen.pedigree(1500, seed=92)
+    m = oracle_matrix(m, dtype)
+    rows = np.array([3, 7, 100, 999])
+    ent = [(0, 1), (5, 5), (77, 3)]
+    Q = sp.random(m.n, m.n, density=3.0 / m.n, random_state=np.random.default_rng(1), format="csr") + \
+        sp.identity(m.n)
+    path = str(tmp_path / "ck.bin")
+
+    def make():
+        s = mc.Sampler(m, pairs=64, groups=G, dtype=dtype, seed=123, hermitian=herm)
+        s.set_trace_matrix(Q)
+        s.request(diag=True, trace=True, block_rows=rows, block_cols=rows[::-1], entries=ent, qtrace=True)
+        return s
+
+    with make() as a:
+        a.burn_in(4)
+        a.request(diag=True, trace=True, block_rows=rows, block_cols=rows[::-1], entries=ent, qtrace=True)
+        a.sample(37)          # time batches merge along the way when G < 16
+        a.save(path)
+        a.sample(29)
+        ref = _estimates(a, True)
+        info_a = a.info()
+    with make() as b:
+        b.restore(path)
+        b.sample(29)
+        got = _estimates(b, True)
+        info_b = b.info()
+    _same(got, ref)
+    for k in ("sweeps_done", "samples_done", "batch_len", "n_batches"):
+        assert info_a[k] == info_b[k], k
+
+
+def test_restore_rejects_mismatch(tmp_path):
+    m = oracle_matrix(gen.pedigree(800, seed=93), "f32")
+    path = str(tmp_path / "ck.bin")
+    with mc.Sampler(m, pairs=32, dtype="f32", seed=1) as a:
+        a.burn_in(2)
+        a.save(path)
+    for kw in ({"seed": 2}, {"pairs": 64}):
+        args = dict(pairs=32, dtype="f32", seed=1)
+        args.update(kw)
+        with mc.Sampler(m, **args) as b:
+            with pytest.raises(mc.McinvError) as ei:
+                b.restore(path)
+            assert ei.value.code == mc.MCINV_EINVAL
+    with mc.Sampler(oracle_matrix(gen.pedigree(800, seed=94), "f32"), pairs=32, dtype="f32", seed=1) as b:
+        with pytest.raises(mc.McinvError) as ei:
+            b.restore(path)
+        assert ei.value.code == mc.MCINV_EINVAL
+    with open(path, "rb") as f:
+        data = f.read()
+    cut = str(tmp_path / "cut.bin")
+    with open(cut, "wb") as f:
+        f.write(data[: len(data) // 2])
+    with mc.Sampler(m, pairs=32, dtype="f32", seed=1) as b:
+        with pytest.raises(mc.McinvError) as ei:
+            b.restore(cut)
+        assert ei.value.code == mc.MCINV_EINVAL
+        with pytest.raises(mc.McinvError):
+            b.restore(os.path.join(str(tmp_path), "missing.bin"))
+        b.restore(path)
+        assert b.info()["sweeps_done"] == 2

@@ -203,3 +203,40 @@ def test_training_beats_neumann_baselines_and_gate_falls_back():
         if acc.any():
             assert np.sqrt(np.mean(rel[acc] ** 2)) <= 0.02
         gate.close()
+
+
+def test_features_full_size_sampled_rows():
+    """The held-out surrogate workload (n = 1e6): the features of sampled rows
+    against the oracle evaluated on each row's two-hop neighbourhood.  A row's
+    features read only its neighbours' full rows and columns and the entries
+    among its neighbours' neighbours, so the submatrix induced on that ball
+    gives the row's features exactly."""
+    w = gen.WORKLOADS["surrogate"]
+    q = gen.surrogate_params(3, seed=w["seed"])[-1]
+    m = gen.round_values(gen.pedigree(w["eval_n"], seed=q["seed"], founders=q["founders"], lam=q["lam"],
+                                      factor=q["factor"]), np.float32)
+    print_case(test="features_full", n=m.n)
+    got = sur.features(m)
+    A = m.to_scipy().tocsr()
+    Sg = ((abs(A) + abs(A).T) > 0).tocsr()
+    rng = np.random.default_rng(5)
+    rows = np.r_[rng.integers(0, m.n, 10), [0, m.n - 1]]
+    for i in rows:
+        ball = {int(i)}
+        frontier = [int(i)]
+        for _ in range(2):
+            nxt = []
+            for u in frontier:
+                for v in Sg.indices[Sg.indptr[u]:Sg.indptr[u + 1]]:
+                    if int(v) not in ball:
+                        ball.add(int(v))
+                        nxt.append(int(v))
+            frontier = nxt
+        idx = np.array(sorted(ball))
+        sub = A[idx][:, idx].tocsr()
+        sub.sort_indices()
+        subm = gen.CSR(n=idx.size, row_ptr=sub.indptr.astype(np.int64), col=sub.indices.astype(np.int32),
+                       val=np.ascontiguousarray(sub.data))
+        ref = S.features(subm)[int(np.searchsorted(idx, i))]
+        np.testing.assert_allclose(got[i], ref.astype(np.float32), rtol=2e-7, atol=1e-9)
+    assert np.all(np.isfinite(got))
