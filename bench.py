@@ -109,7 +109,7 @@ def batched_forms(pkg, torch, gen, rel=0.01, check=10):
     t0 = time.perf_counter()
     b = pkg.BatchSampler(mats, pairs=P, groups=G, seed=seed, use_torch_stream=True)
     sched, r, g, tune_ms = b.autotune(1)
-    b.burn_in(burn)
+    burn_b, _ = b.burn_in_coupled(BURN_TOL, 10000)
     b.request(diag=True, block_dim=w["block"], expected_samples=200)
     done, ach = b.sample_until(rel, 20000, check)
     torch.cuda.synchronize()
@@ -130,7 +130,7 @@ def batched_forms(pkg, torch, gen, rel=0.01, check=10):
     for j, x in enumerate(mats):
         s = pkg.Sampler(x, pairs=P, groups=G, dtype="f32", seed=seed, stream_id=j, moments="bf16x3",
                         use_torch_stream=True)
-        s.burn_in(burn)
+        s.burn_in_coupled(BURN_TOL, 10000)
         s.request(diag=True, trace=False)
         dj, aj = s.sample_until(rel, 20000, check)
         worst = max(worst, aj)
@@ -142,6 +142,7 @@ def batched_forms(pkg, torch, gen, rel=0.01, check=10):
     t_plain = time.perf_counter() - t1
     return {"workload": f"{len(mats)} pedigree matrices, n log-uniform in [{w['lo']}, {w['hi']}] "
                         f"(sum n = {sum(x.n for x in mats)}, nnz = {nnz}), {P} pairs each, fp32",
+            "burn_in": f"coupled to {BURN_TOL:g} (batched: {burn_b} sweeps for all matrices; plain: per matrix)",
             "batched_seconds": t_batch, "batched_sample_sweeps": done, "batched_max_rel_se": ach,
             "autotune": {"schedule": ["phased graph", "persistent"][sched], "rows_per_item": r, "grab": g,
                          "ms_per_sweep": tune_ms},
@@ -240,7 +241,7 @@ def surrogate_form(pkg, torch, gen, n_train, n_val, rel_label=0.005, rel=0.01, s
     t0 = time.perf_counter()
     b = pkg.BatchSampler(mats, pairs=bw["pairs"], groups=bw["groups"], seed=w["noise_seed"], use_torch_stream=True)
     b.autotune(1)
-    b.burn_in(bw["burn_in"])
+    b.burn_in_coupled(BURN_TOL, 10000)
     b.request(diag=True)
     lab_sweeps, lab_ach = b.sample_until(rel_label, 40000, 50)
     torch.cuda.synchronize()

@@ -322,6 +322,15 @@ mcinv_status mcinv_batch_set_block(mcinv_batch* b, int64_t m, const int64_t* row
 mcinv_status mcinv_batch_burn_in(mcinv_batch* b, int64_t sweeps);
 mcinv_status mcinv_batch_sample(mcinv_batch* b, int64_t sweeps);
 
+/* Burn-in by coupling for every matrix (as mcinv_burn_in_coupled): the
+ * noiseless difference iteration of eq 12 runs for all matrices together
+ * until the largest coupled difference over all matrices is below tol, then
+ * every matrix advances by that common number N of sweeps (a matrix whose own
+ * coupling converged earlier burns in longer, which only lowers its bias).
+ * *max_diff: the largest difference at N.  Outputs may be NULL. */
+mcinv_status mcinv_batch_burn_in_coupled(mcinv_batch* b, double tol, int64_t max_sweeps, int64_t* sweeps_done,
+                                         double* max_diff);
+
 /* Sample in chunks until max over all matrices and rows of SE/|est| of the
  * diagonal is <= rel_se (or max_sweeps). */
 mcinv_status mcinv_batch_sample_until(mcinv_batch* b, double rel_se, int64_t max_sweeps, int64_t check_every,

@@ -211,6 +211,11 @@ class BatchSampler:
     def burn_in(self, sweeps):
         mcinv_batch_burn_in(self.b, sweeps)
 
+    def burn_in_coupled(self, tol=5e-5, max_sweeps=10000):
+        """Coupled burn-in of every matrix; returns (sweeps, largest difference)."""
+        from ._binding import mcinv_batch_burn_in_coupled
+        return mcinv_batch_burn_in_coupled(self.b, tol, max_sweeps)
+
     def sample(self, sweeps):
         mcinv_batch_sample(self.b, sweeps)
 

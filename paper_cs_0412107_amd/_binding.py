@@ -145,6 +145,7 @@ SIGNATURES = {
     "mcinv_batch_set_block": (_I32, [_P, _I64, _P, _P]),
     "mcinv_batch_burn_in": (_I32, [_P, _I64]),
     "mcinv_batch_sample": (_I32, [_P, _I64]),
+    "mcinv_batch_burn_in_coupled": (_I32, [_P, _D, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_D)]),
     "mcinv_batch_sample_until": (_I32, [_P, _D, _I64, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_D)]),
     "mcinv_batch_read_estimates": (_I32, [_P, _I64, _U32, _P, _P, _I64]),
     "mcinv_batch_read_state": (_I32, [_P, _I64, _I32, _P, _I64]),
@@ -405,6 +406,13 @@ def mcinv_batch_set_block(b, m, rows, cols):
 
 def mcinv_batch_burn_in(b, sweeps):
     _bcheck(b, lib().mcinv_batch_burn_in(b, int(sweeps)))
+
+
+def mcinv_batch_burn_in_coupled(b, tol=5e-5, max_sweeps=10000):
+    n = ctypes.c_int64(0)
+    d = ctypes.c_double(0)
+    _bcheck(b, lib().mcinv_batch_burn_in_coupled(b, float(tol), int(max_sweeps), ctypes.byref(n), ctypes.byref(d)))
+    return n.value, d.value
 
 
 def mcinv_batch_sample(b, sweeps):

@@ -26,6 +26,7 @@
 #include "../../include/mcinv.h"
 #include "device_common.h"
 #include "prep.h"
+#include "coupling.h"
 #include "moments.h"
 #include "sweep.h"
 
@@ -1218,7 +1219,7 @@ mcinv_status mcinv_get_permutation(mcinv_ctx* c, int64_t* perm, int32_t* color_o
 // 1-based original index: Algorithm 1, step 1) obeys eq 12: noiseless
 // Gauss-Seidel sweeps on C d = 0 (z) and C^dagger d = 0 (w), the same for
 // every chain pair.  Allocates the two [n][ld] difference chains holding x*.
-mcinv_status coupled_start(mcinv_ctx* c, int64_t ld, void** zc, void** wc, int32_t** fl)
+static mcinv_status coupled_start(mcinv_ctx* c, int64_t ld, void** zc, void** wc, int32_t** fl)
 {
     const size_t bytes = (size_t)c->n * ld * c->elem;
     *zc = *wc = nullptr;
@@ -1245,7 +1246,7 @@ mcinv_status coupled_start(mcinv_ctx* c, int64_t ld, void** zc, void** wc, int32
     return MCINV_OK;
 }
 
-mcinv_status noiseless_sweeps(mcinv_ctx* c, int64_t k, void* zc, void* wc, int64_t ld, int32_t* fl)
+static mcinv_status noiseless_sweeps(mcinv_ctx* c, int64_t k, void* zc, void* wc, int64_t ld, int32_t* fl)
 {
     if (c->cfg.hermitian) wc = zc;   // C^dagger = C: the w difference is the z difference
     switch (c->cfg.sweep_dtype) {
@@ -1259,7 +1260,7 @@ mcinv_status noiseless_sweeps(mcinv_ctx* c, int64_t k, void* zc, void* wc, int64
     }
 }
 
-mcinv_status max_abs(mcinv_ctx* c, const void* x, int64_t ld, unsigned long long* out)
+static mcinv_status max_abs(mcinv_ctx* c, const void* x, int64_t ld, unsigned long long* out)
 {
     switch (c->cfg.sweep_dtype) {
     case MCINV_R32: HIP_TRY(c, launch_max_abs<float>((const float*)x, c->n, ld, out, c->stream)); break;
@@ -1270,57 +1271,80 @@ mcinv_status max_abs(mcinv_ctx* c, const void* x, int64_t ld, unsigned long long
     return MCINV_OK;
 }
 
+}  // extern "C"
+
+template <typename V>
+static mcinv_status coupling_sweep(mcinv_ctx* c, void* dz, void* dw)
+{
+    for (int32_t col = 0; col < c->ncolors; ++col)
+        HIP_TRY(c, launch_coupling_sweep<V>(c->d_rows, (const Entry<V>*)c->d_ent, c->color_ptr[col],
+                                            c->color_ptr[col + 1], c->cfg.hermitian != 0, (V*)dz, (V*)dw,
+                                            c->stream));
+    return MCINV_OK;
+}
+
+static mcinv_status coupling_sweep_any(mcinv_ctx* c, void* dz, void* dw)
+{
+    switch (c->cfg.sweep_dtype) {
+    case MCINV_R32: return coupling_sweep<float>(c, dz, dw);
+    case MCINV_R64: return coupling_sweep<double>(c, dz, dw);
+    case MCINV_C64: return coupling_sweep<Cx<float>>(c, dz, dw);
+    default: return coupling_sweep<Cx<double>>(c, dz, dw);
+    }
+}
+
+extern "C" {
+
 mcinv_status mcinv_burn_in_coupled(mcinv_ctx* c, double tol, int64_t max_sweeps, int64_t* sweeps_done,
                                    double* diff_z, double* diff_w)
 {
     MC_TRY(check_ready(c));
     if (!(tol > 0.0) || max_sweeps < 0) return fail(c, MCINV_EINVAL, "tol must be > 0 and max_sweeps >= 0");
-    const int64_t ld = 4;
-    void *zc = nullptr, *wc = nullptr;
+    // one difference value per row (ld = 1): x*_i - 0 with x*_i = i, 1-based
+    void *dz = nullptr, *dw = nullptr;
     int32_t* fl = nullptr;
     unsigned long long* dmax = nullptr;
-    mcinv_status s = coupled_start(c, ld, &zc, &wc, &fl);
+    mcinv_status s = coupled_start(c, 1, &dz, &dw, &fl);
     if (s == MCINV_OK && hipMalloc((void**)&dmax, 2 * sizeof(unsigned long long)) != hipSuccess)
         s = fail(c, MCINV_ENOMEM, "device allocation failed");
+    void* dw_eff = c->cfg.hermitian ? dz : dw;  // C^dagger = C: the w difference is the z difference
     int64_t N = max_sweeps;
-    double dz = INFINITY, dw = INFINITY;
+    double dzm = INFINITY, dwm = INFINITY;
     for (int64_t k = 1; k <= max_sweeps && s == MCINV_OK; ++k) {
-        if ((s = noiseless_sweeps(c, 1, zc, wc, ld, fl)) != MCINV_OK) break;
+        if ((s = coupling_sweep_any(c, dz, dw)) != MCINV_OK) break;
         if (hipMemsetAsync(dmax, 0, 2 * sizeof(unsigned long long), c->stream) != hipSuccess) {
             s = fail(c, MCINV_EDEVICE, "hipMemsetAsync failed");
             break;
         }
-        if ((s = max_abs(c, zc, ld, dmax)) != MCINV_OK ||
-            (s = max_abs(c, c->cfg.hermitian ? zc : wc, ld, dmax + 1)) != MCINV_OK)
-            break;
+        if ((s = max_abs(c, dz, 1, dmax)) != MCINV_OK || (s = max_abs(c, dw_eff, 1, dmax + 1)) != MCINV_OK) break;
         unsigned long long bits[2] = {0, 0};
         if (hipMemcpyAsync(bits, dmax, sizeof(bits), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
             hipStreamSynchronize(c->stream) != hipSuccess) {
             s = fail(c, MCINV_EDEVICE, "copying the coupling difference failed");
             break;
         }
-        std::memcpy(&dz, &bits[0], sizeof(double));
-        std::memcpy(&dw, &bits[1], sizeof(double));
-        if (!std::isfinite(dz) || !std::isfinite(dw)) {
+        std::memcpy(&dzm, &bits[0], sizeof(double));
+        std::memcpy(&dwm, &bits[1], sizeof(double));
+        if (!std::isfinite(dzm) || !std::isfinite(dwm)) {
             s = fail(c, MCINV_EDIVERGED, "coupled paths diverge: the Gauss-Seidel iteration of eq 12 does not "
                                          "contract (sp(T) or sp(S) >= 1)");
             break;
         }
-        if (dz < tol && dw < tol) {
+        if (dzm < tol && dwm < tol) {
             N = k;
             break;
         }
     }
-    (void)hipFree(zc);
-    (void)hipFree(wc);
+    (void)hipFree(dz);
+    (void)hipFree(dw);
     (void)hipFree(fl);
     (void)hipFree(dmax);
     if (s != MCINV_OK) return s;
     MC_TRY(dispatch_sweeps(c, N, false));
     c->sweeps += N;
     if (sweeps_done) *sweeps_done = N;
-    if (diff_z) *diff_z = dz;
-    if (diff_w) *diff_w = dw;
+    if (diff_z) *diff_z = dzm;
+    if (diff_w) *diff_w = dwm;
     return check_flag(c);
 }
 

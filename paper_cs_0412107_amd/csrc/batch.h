@@ -79,6 +79,9 @@ hipError_t launch_batch(const BatchArgs& a, int grid, hipStream_t stream);
 hipError_t launch_batch_phase(const BatchArgs& a, const BItem* items, int64_t nitems, bool block_phase,
                               hipStream_t stream);
 hipError_t launch_batch_tick(BatchClock* clock, bool sample, hipStream_t stream);
+// out[row_mat[q]] = max |x[q * ld]| (double bits, atomic max; clear out first).
+hipError_t launch_batch_max_abs(const float* x, int64_t nrows, int32_t ld, const int32_t* row_mat,
+                                unsigned long long* out, hipStream_t stream);
 int batch_kernel_occupancy();  // workgroups per CU the batch kernel can keep resident
 
 }  // namespace mcinv

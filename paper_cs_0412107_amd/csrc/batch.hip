@@ -233,6 +233,33 @@ hipError_t launch_batch_phase(const BatchArgs& a, const BItem* items, int64_t ni
     return hipGetLastError();
 }
 
+// Per matrix: max over its rows of |x[q * ld]| (lane 0), as double bits.
+__global__ __launch_bounds__(256) void k_batch_max_abs(const float* x, int64_t nrows, int32_t ld,
+                                                       const int32_t* row_mat, unsigned long long* out)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool ok = q < nrows;
+    double v = ok ? fabs((double)x[q * ld]) : 0.0;
+    if (!(v < __builtin_inf())) v = __builtin_inf();
+    // rows of one matrix are contiguous: lanes whose matrix is the wave's
+    // first one reduce across the wave first, the few others (a matrix
+    // boundary inside the wave) go straight to memory
+    const int32_t m = ok ? row_mat[q] : -1;
+    const int32_t m0 = __shfl(m, 0);
+    double r = (m == m0) ? v : 0.0;
+    for (int off = 32; off > 0; off >>= 1) r = fmax(r, __shfl_xor(r, off));
+    if ((threadIdx.x & 63) == 0 && m0 >= 0) atomicMax(out + m0, (unsigned long long)__double_as_longlong(r));
+    if (ok && m != m0) atomicMax(out + m, (unsigned long long)__double_as_longlong(v));
+}
+
+hipError_t launch_batch_max_abs(const float* x, int64_t nrows, int32_t ld, const int32_t* row_mat,
+                                unsigned long long* out, hipStream_t stream)
+{
+    if (nrows <= 0) return hipSuccess;
+    k_batch_max_abs<<<dim3((unsigned)((nrows + 255) / 256)), dim3(256), 0, stream>>>(x, nrows, ld, row_mat, out);
+    return hipGetLastError();
+}
+
 hipError_t launch_batch_tick(BatchClock* clock, bool sample, hipStream_t stream)
 {
     k_batch_tick<<<dim3(1), dim3(64), 0, stream>>>(clock, sample ? 1 : 0);

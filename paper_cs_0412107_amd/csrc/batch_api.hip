@@ -625,6 +625,96 @@ mcinv_status mcinv_batch_burn_in(mcinv_batch* b, int64_t sweeps)
     return MCINV_OK;
 }
 
+mcinv_status mcinv_batch_burn_in_coupled(mcinv_batch* b, double tol, int64_t max_sweeps, int64_t* sweeps_done,
+                                         double* max_diff)
+{
+    BTRY(check_batch(b));
+    if (!(tol > 0.0) || max_sweeps < 0) return bfail(b, MCINV_EINVAL, "tol must be > 0 and max_sweeps >= 0");
+    // Difference chains of every matrix (eq 12: noiseless Gauss-Seidel from
+    // x*_i = i, 1-based original index), 16 lanes per row, phased launches.
+    constexpr int32_t kLd = 16;
+    const size_t cnt = (size_t)b->nrows * kLd;
+    std::vector<float> init(cnt);
+    std::vector<int32_t> row_m((size_t)b->nrows);
+    for (int64_t m = 0; m < b->M; ++m)
+        for (int64_t q = 0; q < b->prep[m].n; ++q) {
+            const int64_t g = b->row0[m] + q;
+            row_m[g] = (int32_t)m;
+            for (int32_t l = 0; l < kLd; ++l) init[g * kLd + l] = (float)(b->prep[m].perm[q] + 1);
+        }
+    float *dz = nullptr, *dw = nullptr;
+    int32_t *d_rowm = nullptr, *flag2 = nullptr;
+    BatchClock* clock2 = nullptr;
+    unsigned long long* dmax = nullptr;
+    auto release = [&]() {
+        bfree(dz);
+        bfree(dw);
+        bfree(d_rowm);
+        bfree(flag2);
+        bfree(clock2);
+        bfree(dmax);
+    };
+    mcinv_status st = MCINV_OK;
+    if ((st = balloc(b, &dz, cnt)) != MCINV_OK || (st = balloc(b, &dw, cnt)) != MCINV_OK ||
+        (st = bupload(b, &d_rowm, row_m)) != MCINV_OK || (st = balloc(b, &flag2, 1)) != MCINV_OK ||
+        (st = balloc(b, &clock2, 1)) != MCINV_OK || (st = balloc(b, &dmax, (size_t)(2 * b->M))) != MCINV_OK) {
+        release();
+        return st;
+    }
+    hipError_t e = hipMemcpyAsync(dz, init.data(), sizeof(float) * cnt, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(dw, init.data(), sizeof(float) * cnt, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(flag2, 0, sizeof(int32_t), b->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(clock2, 0, sizeof(BatchClock), b->stream);
+    BatchArgs a = make_args(b, 1, false);
+    a.z = dz;
+    a.w = dw;
+    a.P = kLd;
+    a.lane_shift = 2;
+    a.G = 1;
+    a.noise = kNoiseNone;
+    a.clock = clock2;
+    a.flag = flag2;
+    a.diag = nullptr;
+    a.block = nullptr;
+    const std::vector<int64_t>& off = b->phase_off[0];
+    std::vector<unsigned long long> bits((size_t)(2 * b->M));
+    int64_t N = max_sweeps;
+    double worst = INFINITY;
+    for (int64_t k = 1; k <= max_sweeps && e == hipSuccess; ++k) {
+        for (size_t p = 0; p + 1 < off.size() && e == hipSuccess; ++p)
+            e = launch_batch_phase(a, a.items + off[p], off[p + 1] - off[p], b->phase_block[0][p], b->stream);
+        if (e == hipSuccess) e = launch_batch_tick(clock2, false, b->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(dmax, 0, sizeof(unsigned long long) * 2 * b->M, b->stream);
+        if (e == hipSuccess) e = launch_batch_max_abs(dz, b->nrows, kLd, d_rowm, dmax, b->stream);
+        if (e == hipSuccess) e = launch_batch_max_abs(dw, b->nrows, kLd, d_rowm, dmax + b->M, b->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(bits.data(), dmax, sizeof(unsigned long long) * bits.size(), hipMemcpyDeviceToHost,
+                               b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) break;
+        worst = 0.0;
+        for (unsigned long long u : bits) {
+            double d;
+            std::memcpy(&d, &u, sizeof(double));
+            worst = std::max(worst, d);
+        }
+        if (!std::isfinite(worst)) {
+            release();
+            return bfail(b, MCINV_EDIVERGED, "coupled paths diverge (sp(T) or sp(S) >= 1 for some matrix)");
+        }
+        if (worst < tol) {
+            N = k;
+            break;
+        }
+    }
+    release();
+    if (e != hipSuccess) return bfail(b, MCINV_EDEVICE, std::string("coupled burn-in: ") + hipGetErrorString(e));
+    BTRY(mcinv_batch_burn_in(b, N));
+    if (sweeps_done) *sweeps_done = N;
+    if (max_diff) *max_diff = worst;
+    return MCINV_OK;
+}
+
 mcinv_status mcinv_batch_sample(mcinv_batch* b, int64_t sweeps)
 {
     BTRY(check_batch(b));

@@ -323,6 +323,18 @@ __global__ __launch_bounds__(256) void k_mlp_wgrad(const bf16_t* XT, const bf16_
     }
 }
 
+// psum[k] = sum over the forward/backward workgroups of part[b][k]: one
+// wave per k, lane l summing b = l, l + 64, ... in order, then a fixed
+// butterfly across the lanes.
+__global__ __launch_bounds__(64) void k_mlp_reduce_parts(const float* part, int32_t blocks, float* psum)
+{
+    const int k = blockIdx.x, lane = threadIdx.x;
+    float v = 0.f;
+    for (int b = lane; b < blocks; b += 64) v += part[(int64_t)b * kPart + k];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) psum[k] = v;
+}
+
 struct UpdateArgs {
     float* P;                // master parameters
     float* m;                // Adam first moments
@@ -330,8 +342,7 @@ struct UpdateArgs {
     float* grads;            // the assembled gradient [kParams]
     const float* wpart;      // weight-gradient partials [nks][ob2]
     int32_t nks;
-    const float* part;       // [blocks][kPart]
-    int32_t blocks;
+    const float* psum;       // [kPart] summed workgroup partials
     int32_t apply;           // 0: only assemble the gradient
     float lr, beta1, beta2, eps;
     float bc1, bc2;          // 1 - beta^t
@@ -344,11 +355,7 @@ struct UpdateArgs {
 __global__ __launch_bounds__(256) void k_mlp_update(const UpdateArgs u)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p == 0 && u.loss_out) {
-        float l = 0.f;
-        for (int b = 0; b < u.blocks; ++b) l += u.part[(int64_t)b * kPart + 3 * kH + 1];
-        *u.loss_out = l;
-    }
+    if (p == 0 && u.loss_out) *u.loss_out = u.psum[3 * kH + 1];
     if (p >= kParams) return;
     float g;
     if ((p >= oW1 && p < ob1) || (p >= oW2 && p < ob2)) {
@@ -365,8 +372,7 @@ __global__ __launch_bounds__(256) void k_mlp_update(const UpdateArgs u)
             k = 2 * kH + (p - ow3);    // dw3
         else
             k = 3 * kH;                // db3
-        g = 0.f;
-        for (int b = 0; b < u.blocks; ++b) g += u.part[(int64_t)b * kPart + k];
+        g = u.psum[k];
         u.grads[p] = g;
     }
     if (!u.apply) return;
@@ -436,7 +442,8 @@ struct mcinv_mlp {
     int64_t N = 0;
     // step buffers
     int32_t Rcap = 0;
-    float* wpart = nullptr;  // [kMaxKs][ob2]
+    float* wpart = nullptr;  // [ks][ob2]
+    float* psum = nullptr;   // [kPart]
     int64_t* idx = nullptr;
     bf16_t* XT = nullptr;
     bf16_t* h1T = nullptr;
@@ -546,8 +553,9 @@ mcinv_status run_step(mcinv_mlp* m, int32_t R, bool apply, float lr, float* loss
     u.grads = m->grads;
     u.wpart = m->wpart;
     u.nks = nks;
-    u.part = m->part;
-    u.blocks = blocks;
+    k_mlp_reduce_parts<<<dim3(kPart), dim3(64), 0, m->stream>>>(m->part, blocks, m->psum);
+    MHIP(m, hipGetLastError());
+    u.psum = m->psum;
     u.apply = apply ? 1 : 0;
     u.lr = lr;
     u.beta1 = 0.9f;
@@ -594,7 +602,8 @@ mcinv_status mcinv_mlp_create(int32_t device, mcinv_mlp** out)
         hipMalloc((void**)&m->W2, sizeof(bf16_t) * kH * kH) != hipSuccess ||
         hipMalloc((void**)&m->mean, sizeof(float) * kF) != hipSuccess ||
         hipMalloc((void**)&m->inv_std, sizeof(float) * kF) != hipSuccess ||
-        hipMalloc((void**)&m->loss, sizeof(float) * 1) != hipSuccess)
+        hipMalloc((void**)&m->loss, sizeof(float) * 1) != hipSuccess ||
+        hipMalloc((void**)&m->psum, sizeof(float) * kPart) != hipSuccess)
         return fail_alloc();
     std::vector<float> zero(kParams, 0.0f), one(kF, 1.0f);
     if (hipMemcpy(m->P, zero.data(), sizeof(float) * kParams, hipMemcpyHostToDevice) != hipSuccess ||
@@ -622,6 +631,7 @@ void mcinv_mlp_destroy(mcinv_mlp* m)
     mfree(m->mean);
     mfree(m->inv_std);
     mfree(m->loss);
+    mfree(m->psum);
     mfree(m->X);
     mfree(m->y);
     mfree(m->w);

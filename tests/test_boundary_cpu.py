@@ -33,6 +33,9 @@ def test_library_exports_every_declared_symbol():
     out = subprocess.run(["nm", "-D", "--defined-only", pkg._binding.LIB_PATH], capture_output=True, text=True).stdout
     exported = set(re.findall(r"\bT (mcinv_\w+)", out))
     assert set(_declared()) <= exported
+    # and nothing else with C linkage: every unmangled global function is declared
+    unmangled = {m for m in re.findall(r"\bT (\w+)", out) if not m.startswith("_")}
+    assert unmangled == set(_declared()), sorted(unmangled ^ set(_declared()))
 
 
 def test_binding_covers_header():

@@ -153,3 +153,26 @@ def test_batch_errors(mats):
         with pytest.raises(mc.McinvError) as ei:
             bs.request(diag=True, block_dim=129)
         assert ei.value.code == mc.MCINV_EINVAL
+
+
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_batched_coupled_burn_in_equals_single_path(mats, schedule):
+    """The batch burns in for the largest of the matrices' own coupling
+    lengths (the difference iteration is the single path's, bit for bit), and
+    every matrix's chains then equal the single path after that many sweeps."""
+    print_case(test="batch_coupled", schedule=schedule)
+    P, G, seed, tol = 64, 16, 31, 5e-5
+    sub = mats[:6]
+    Ns = []
+    for j, x in enumerate(sub):
+        with mc.Sampler(x, pairs=P, groups=G, dtype="f32", seed=seed, stream_id=j) as s:
+            n, dz, dw = s.burn_in_coupled(tol, 500)
+            Ns.append(n)
+    with mc.BatchSampler(sub, pairs=P, groups=G, seed=seed, schedule=schedule) as b:
+        N, worst = b.burn_in_coupled(tol, 500)
+        assert N == max(Ns) and worst < tol
+        for j in (0, 2, 5):
+            with mc.Sampler(sub[j], pairs=P, groups=G, dtype="f32", seed=seed, stream_id=j) as s:
+                s.burn_in(N)
+                assert np.array_equal(b.state(j, 0), s.state(0))
+                assert np.array_equal(b.state(j, 1), s.state(1))
