@@ -248,3 +248,16 @@ def test_label_weights_library_matches_oracle():
     w = S.label_weights(se, 1e-6)
     assert abs(w.mean() - 1) < 1e-12 and np.all(np.diff(w[np.argsort(se)]) <= 0)
     np.testing.assert_allclose(mc.mcinv_mlp_label_weights(se, 1e-6), w, rtol=1e-6)
+
+
+def test_fit_normalization_standardises():
+    """After (x - mean) * inv_std every non-constant column has mean 0 and
+    population variance 1; a constant column gets inv_std 1 (so it maps to 0)."""
+    rng = np.random.default_rng(13)
+    X = (rng.standard_normal((4000, 32)) * rng.uniform(0.01, 50, 32) + rng.uniform(-5, 5, 32)).astype(np.float32)
+    X[:, 31] = 1.0
+    mean, inv = S.fit_normalization(X)
+    Z = S.normalize(X, mean, inv)
+    assert np.allclose(Z[:, :31].mean(axis=0), 0, atol=1e-5)
+    assert np.allclose(Z[:, :31].var(axis=0), 1, rtol=1e-5)
+    assert inv[31] == 1.0 and np.all(Z[:, 31] == 0)
