@@ -72,15 +72,23 @@ def profiled_traffic(workload):
 BURN_TOL = 5e-5   # coupling tolerance of the paper's numerical tests
 
 
+def tuned_order(pkg, m, P, G, dtype, hermitian=False):
+    """The faster sweep workgroup order for this matrix and pair count, timed
+    on a scratch context (setup; not part of any timed region)."""
+    with pkg.Sampler(m, pairs=P, groups=G, dtype=dtype, seed=0, hermitian=hermitian) as s:
+        order, _, _ = s.tune_launch(2)
+    return order
+
+
 def time_to_1pct(pkg, torch, m, P, G, seed, dtype, moments, burn_in, rel=0.01, check=10, max_sweeps=20000,
-                 hermitian=False):
+                 hermitian=False, xcd_order=0):
     """Wall time from a fresh context to max_i SE_i/|est_i| <= rel on the whole
     diagonal: burn-in (a fixed count, or "coupled": until the coupled paths
     agree to BURN_TOL), then sampling checked every `check` sweeps."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s = pkg.Sampler(m, pairs=P, groups=G, dtype=dtype, seed=seed, moments=moments, use_torch_stream=True,
-                    hermitian=hermitian)
+                    hermitian=hermitian, xcd_order=xcd_order)
     if burn_in == "coupled":
         nb, _, _ = s.burn_in_coupled(BURN_TOL, 10000)
         burn_desc = f"coupled to {BURN_TOL:g}"
@@ -93,7 +101,7 @@ def time_to_1pct(pkg, torch, m, P, G, seed, dtype, moments, burn_in, rel=0.01, c
     t = time.perf_counter() - t0
     s.close()
     return {"seconds": t, "burn_in": nb, "burn_in_rule": burn_desc, "sample_sweeps": done, "max_rel_se": ach,
-            "form": f"{dtype} sweeps, {moments} blocks"}
+            "form": f"{dtype} sweeps, {moments} blocks", "xcd_order": xcd_order}
 
 
 def batched_forms(pkg, torch, gen, rel=0.01, check=10):
@@ -194,9 +202,10 @@ def dirac_form(pkg, torch, gen):
     m = gen.round_values(gen.dirac(w["N"], w["K"]), np.complex64)
     P, G, seed = w["pairs"], w["groups"], w["noise_seed"]
     exact = theory.dirac_free_trace(w["N"], w["K"])
+    order = tuned_order(pkg, m, P, G, "c64")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    s = pkg.Sampler(m, pairs=P, groups=G, dtype="c64", seed=seed, use_torch_stream=True)
+    s = pkg.Sampler(m, pairs=P, groups=G, dtype="c64", seed=seed, use_torch_stream=True, xcd_order=order)
     N, _, _ = s.burn_in_coupled(BURN_TOL, 10000)
     s.request(diag=False, trace=True)
     done, ach = s.sample_until_trace(w["rel_se"], 20000, 20)
@@ -212,6 +221,7 @@ def dirac_form(pkg, torch, gen):
             "seconds": t, "burn_in": N, "sample_sweeps": done, "rel_se": ach,
             "estimate": [float(np.real(est)), float(np.imag(est))], "se": float(se), "exact": exact,
             "z_score": float((np.real(est) - exact) / se), "ms_per_sweep": ms,
+            "xcd_order": ["natural", "XCD-contiguous"][order],
             "nonzero_updates_per_s": 2.0 * m.nnz * P / (ms / 1e3),
             "paper_case1": {"burn_in": 18, "sample_cycles": 10832, "chain_pairs": 1}}
 
@@ -390,6 +400,7 @@ def main():
                     moments="bf16x3" if dtype == "f32" else "fp64")
     info0 = s.info()
     s.burn_in(w["burn_in"])
+    order, ms_nat, ms_xcd = s.tune_launch(2)   # setup: picks the faster workgroup order
     s.request(diag=True, trace=True, block_rows=blk, block_cols=blk)
     s.sample(args.warmup)
     s.reset_profile()
@@ -433,7 +444,9 @@ def main():
         "config": {"workload": desc,
                    "n": n, "nnz": int(m.nnz), "pairs": P, "groups": G, "colors": info0["n_colors"],
                    "step": "one sampling sweep (all colours, fused diag/trace moments, trace reduction"
-                           + (", block moments)" if blk is not None else ")")},
+                           + (", block moments)" if blk is not None else ")"),
+                   "launch_order": {"chosen": ["natural", "XCD-contiguous"][order],
+                                    "burn_in_ms_per_sweep": {"natural": ms_nat, "XCD-contiguous": ms_xcd}}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(args.workload),
                      "algorithmic_bytes_per_launch": B / launches,
@@ -455,9 +468,10 @@ def main():
             forms["plain_fp64"] = time_to_1pct(pkg, torch, gen.pedigree(n, seed=w["seed"]), P, G, seed + 1,
                                                "f64", "fp64", w["burn_in"])
         forms["precision"] = time_to_1pct(pkg, torch, m, P, G, seed + 1, dtype,
-                                          "bf16x3" if dtype == "f32" else "fp64", w["burn_in"])
+                                          "bf16x3" if dtype == "f32" else "fp64", w["burn_in"], xcd_order=order)
         forms["precision_coupled"] = time_to_1pct(pkg, torch, m, P, G, seed + 1, dtype,
-                                                  "bf16x3" if dtype == "f32" else "fp64", "coupled")
+                                                  "bf16x3" if dtype == "f32" else "fp64", "coupled",
+                                                  xcd_order=order)
         if "plain_fp64" in forms:
             for k in ("precision", "precision_coupled"):
                 forms[k]["speedup_vs_plain"] = forms["plain_fp64"]["seconds"] / forms[k]["seconds"]

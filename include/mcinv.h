@@ -100,6 +100,9 @@ typedef struct {
     int32_t  profile;      /* nonzero: time every sweep launch with HIP events       */
     int32_t  pass_tiles;   /* 256-pair tiles swept through all colours before the
                               next tiles start (cache residency); 0 = automatic   */
+    int32_t  xcd_order;    /* sweep workgroup order: 0 natural (round-robin over the
+                              8 XCDs), 1 contiguous (tile, row block) ranges per XCD;
+                              mcinv_tune_launch picks the faster one              */
     int32_t  hermitian;    /* nonzero: C is hermitian with a positive diagonal
                               (checked by mcinv_load_csr, EINVAL otherwise); then
                               w = z at every step and only z is swept -- the
@@ -203,6 +206,14 @@ mcinv_status mcinv_get_permutation(mcinv_ctx* ctx, int64_t* perm, int32_t* color
  * EDIVERGED when the difference becomes non-finite.  Outputs may be NULL. */
 mcinv_status mcinv_burn_in_coupled(mcinv_ctx* ctx, double tol, int64_t max_sweeps, int64_t* sweeps_done,
                                    double* diff_z, double* diff_w);
+
+/* Time sweeps_per_trial burn-in sweeps (after one warm-up sweep) under each
+ * workgroup order (natural, XCD-contiguous) and keep the faster one.  The
+ * chains advance as in mcinv_burn_in (2 + 2 sweeps_per_trial sweeps; the
+ * order never changes the arithmetic, so results do not depend on it).
+ * Outputs may be NULL. */
+mcinv_status mcinv_tune_launch(mcinv_ctx* ctx, int32_t sweeps_per_trial, int32_t* xcd_order, double* ms_natural,
+                               double* ms_xcd);
 
 /* Noiseless sweeps from x_i = i (Algorithm 1's second start) on C x = 0 and
  * C^dagger y = 0: the Gauss-Seidel iterations eq 12 shows the chain

@@ -38,14 +38,15 @@ class Sampler:
 
     def __init__(self, matrix, pairs, groups=1, dtype="f32", seed=0, noise=MCINV_NOISE_NORMAL,
                  moments="fp64", device=0, stream_id=0, use_torch_stream=False, profile=False, pass_tiles=0,
-                 hermitian=False):
+                 hermitian=False, xcd_order=0):
         self.dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
         self.is_complex = self.dtype in (DTYPES["c64"], DTYPES["c128"])
         mom = MCINV_MOMENTS_BF16X3 if moments == "bf16x3" else MCINV_MOMENTS_FP64
         stream = torch_stream() if use_torch_stream else None
         self.ctx = mcinv_create(device=device, sweep_dtype=self.dtype, moments=mom, noise=noise,
                                 n_pairs=pairs, n_groups=groups, stream_id=stream_id, seed=seed,
-                                stream=stream, profile=profile, pass_tiles=pass_tiles, hermitian=hermitian)
+                                stream=stream, profile=profile, pass_tiles=pass_tiles, hermitian=hermitian,
+                                xcd_order=xcd_order)
         self.n = matrix.n
         self.P = pairs
         self.nI = self.nJ = self.ne = 0
@@ -155,6 +156,11 @@ class Sampler:
         """Restrict ``sample_until``'s stop check to these original rows (None: all)."""
         from ._binding import mcinv_set_stop_rows
         mcinv_set_stop_rows(self.ctx, rows)
+
+    def tune_launch(self, sweeps_per_trial=2):
+        """Pick the faster sweep workgroup order; returns (order, ms natural, ms XCD-contiguous)."""
+        from ._binding import mcinv_tune_launch
+        return mcinv_tune_launch(self.ctx, sweeps_per_trial)
 
     def check_convergence(self, iters=200):
         return mcinv_check_convergence(self.ctx, iters)

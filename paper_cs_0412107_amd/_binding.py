@@ -54,6 +54,7 @@ class mcinv_config(ctypes.Structure):
         ("stream", ctypes.c_void_p),
         ("profile", ctypes.c_int32),
         ("pass_tiles", ctypes.c_int32),
+        ("xcd_order", ctypes.c_int32),
         ("hermitian", ctypes.c_int32),
     ]
 
@@ -133,6 +134,7 @@ SIGNATURES = {
     "mcinv_set_trace_matrix": (_I32, [_P, _I64, _P, _P, _P, _I32]),
     "mcinv_save": (_I32, [_P, ctypes.c_char_p]),
     "mcinv_restore": (_I32, [_P, ctypes.c_char_p]),
+    "mcinv_tune_launch": (_I32, [_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "mcinv_check_convergence": (_I32, [_P, _I64, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "mcinv_get_info": (_I32, [_P, ctypes.POINTER(mcinv_info)]),
     "mcinv_reset_profile": (_I32, [_P]),
@@ -208,9 +210,9 @@ def mcinv_last_error(ctx=None):
 
 def mcinv_create(device=0, sweep_dtype=MCINV_R32, moments=MCINV_MOMENTS_FP64, noise=MCINV_NOISE_NORMAL,
                  n_pairs=1, n_groups=1, stream_id=0, seed=0, stream=None, profile=False, pass_tiles=0,
-                 hermitian=False):
+                 hermitian=False, xcd_order=0):
     cfg = mcinv_config(device, sweep_dtype, moments, noise, n_pairs, n_groups, stream_id,
-                       seed & 0xFFFFFFFFFFFFFFFF, stream, 1 if profile else 0, int(pass_tiles),
+                       seed & 0xFFFFFFFFFFFFFFFF, stream, 1 if profile else 0, int(pass_tiles), int(xcd_order),
                        1 if hermitian else 0)
     h = ctypes.c_void_p()
     _check(None, lib().mcinv_create(ctypes.byref(cfg), ctypes.byref(h)))
@@ -329,6 +331,15 @@ def mcinv_get_permutation(ctx, n):
     color = np.empty(n, dtype=np.int32)
     _check(ctx, lib().mcinv_get_permutation(ctx, _ptr(perm), _ptr(color)))
     return perm, color
+
+
+def mcinv_tune_launch(ctx, sweeps_per_trial=2):
+    o = ctypes.c_int32(0)
+    a = ctypes.c_double(0)
+    b = ctypes.c_double(0)
+    _check(ctx, lib().mcinv_tune_launch(ctx, int(sweeps_per_trial), ctypes.byref(o), ctypes.byref(a),
+                                        ctypes.byref(b)))
+    return o.value, a.value, b.value
 
 
 def mcinv_check_convergence(ctx, iters):

@@ -19,9 +19,6 @@
 #include "sweep.h"
 
 // Tuning knobs (compile time).
-#ifndef MCINV_XCD_REMAP
-#define MCINV_XCD_REMAP 0        // contiguous (tile, row block) ranges per XCD
-#endif
 #ifndef MCINV_GATHER_U4
 #define MCINV_GATHER_U4 4        // neighbours per gather chunk, 4-byte state
 #endif
@@ -77,17 +74,19 @@ __global__ __launch_bounds__(256) void k_sweep(const SweepArgs<V> a)
 
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-#if MCINV_XCD_REMAP
-    // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs, so give
-    // XCD x one contiguous range of (tile, row block) indices of this launch.
-    const uint32_t total = gridDim.x * gridDim.y;
-    const uint32_t lin = blockIdx.x + gridDim.x * blockIdx.y;
-    const uint32_t xcd = lin % 8u, idx = lin / 8u, per = total / 8u, extra = total % 8u;
-    const uint32_t remap = xcd * per + (xcd < extra ? xcd : extra) + idx;
-    const uint32_t bx = remap % gridDim.x, by = remap / gridDim.x;
-#else
-    const uint32_t bx = blockIdx.x, by = blockIdx.y;
-#endif
+    uint32_t bx = blockIdx.x, by = blockIdx.y;
+    if (a.xcd_order) {
+        // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs, so
+        // give XCD x one contiguous range of (tile, row block) indices of this
+        // launch (each XCD's L2 then holds the neighbour slices of its own
+        // tiles; pays off on structured patterns, see the launch autotuner).
+        const uint32_t total = gridDim.x * gridDim.y;
+        const uint32_t lin = blockIdx.x + gridDim.x * blockIdx.y;
+        const uint32_t xcd = lin % 8u, idx = lin / 8u, per = total / 8u, extra = total % 8u;
+        const uint32_t remap = xcd * per + (xcd < extra ? xcd : extra) + idx;
+        bx = remap % gridDim.x;
+        by = remap / gridDim.x;
+    }
     const int64_t tile = a.tile0 + by;
     const int64_t q = a.row_begin + (int64_t)bx * 4 + wid;
     const int64_t p0 = tile * kPairsPerWave + lane * kPairsPerLane;
