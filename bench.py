@@ -451,7 +451,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": profiled_traffic(args.workload),
                      "algorithmic_bytes_per_launch": B / launches,
                      "avg_launch_ms": sweep_ms / launches,
-                     "kernel": f"k_sweep<{'float' if dtype == 'f32' else 'Cx<float>'}, true> "
+                     "kernel": f"k_sweep<{'float' if dtype == 'f32' else 'Cx<float>'}, true, false> "
                                "(all colour launches of one sweep)",
                      "algorithmic_bytes_per_sweep": B, "sweep_kernel_ms": sweep_ms,
                      "launches_per_sweep": launches},
