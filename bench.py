@@ -229,7 +229,7 @@ def dirac_form(pkg, torch, gen):
 MLP_FLOP_PER_ROW_STEP = 2 * (32 * 128 + 128 * 128 + 128) + 2 * (2 * 128 + 2 * 128 * 128 + 32 * 128)
 
 
-def surrogate_form(pkg, torch, gen, n_train, n_val, rel_label=0.005, rel=0.01, steps=2000, batch=16384):
+def surrogate_form(pkg, torch, gen, n_train, n_val, rel_label=0.005, rel=0.01, steps=2000, batch=65536):
     """Learned-surrogate workload: pedigree matrices with random generator
     parameters (n = 2e4) labelled by the batched sampler to rel_label, 32
     features per row, the network trained on the labelled rows, a gate fitted
@@ -253,7 +253,13 @@ def surrogate_form(pkg, torch, gen, n_train, n_val, rel_label=0.005, rel=0.01, s
     b.autotune(1)
     b.burn_in_coupled(BURN_TOL, 10000)
     b.request(diag=True)
-    lab_sweeps, lab_ach = b.sample_until(rel_label, 40000, 50)
+    lab_sweeps, lab_ach = 0, float("inf")
+    while lab_sweeps < 40000:
+        d, lab_ach = b.sample_until(rel_label, 1000, 50)
+        lab_sweeps += d
+        log(f"surrogate: labelling, {lab_sweeps} sample sweeps, max rel SE {lab_ach:.4f}")
+        if lab_ach <= rel_label:
+            break
     torch.cuda.synchronize()
     t_label = time.perf_counter() - t0
     Y, YSE = [], []
@@ -266,7 +272,11 @@ def surrogate_form(pkg, torch, gen, n_train, n_val, rel_label=0.005, rel=0.01, s
     log(f"surrogate: labels in {t_label:.1f} s ({lab_sweeps} sample sweeps, max rel SE {lab_ach:.4f}); features ...")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    F = [sur.features(x) for x in mats]
+    F = []
+    for j, x in enumerate(mats):
+        F.append(sur.features(x))
+        if j % 500 == 499:
+            log(f"surrogate: features of {j + 1} matrices")
     t_feat = time.perf_counter() - t0
     Xtr, ytr, setr = np.concatenate(F[:n_train]), np.concatenate(Y[:n_train]), np.concatenate(YSE[:n_train])
     Xv, yv, sev = np.concatenate(F[n_train:]), np.concatenate(Y[n_train:]), np.concatenate(YSE[n_train:])
@@ -472,9 +482,14 @@ def main():
         forms["precision_coupled"] = time_to_1pct(pkg, torch, m, P, G, seed + 1, dtype,
                                                   "bf16x3" if dtype == "f32" else "fp64", "coupled",
                                                   xcd_order=order)
+        if args.workload == "pedigree":
+            forms["plain_fp64_coupled"] = time_to_1pct(pkg, torch, gen.pedigree(n, seed=w["seed"]), P, G, seed + 1,
+                                                       "f64", "fp64", "coupled", xcd_order=order)
         if "plain_fp64" in forms:
             for k in ("precision", "precision_coupled"):
                 forms[k]["speedup_vs_plain"] = forms["plain_fp64"]["seconds"] / forms[k]["seconds"]
+            forms["precision_coupled"]["speedup_vs_plain_coupled"] = \
+                forms["plain_fp64_coupled"]["seconds"] / forms["precision_coupled"]["seconds"]
         log(f"time to 1%: {forms['precision']['seconds']:.2f} s (burn-in {w['burn_in']}), "
             f"{forms['precision_coupled']['seconds']:.3f} s (coupled burn-in, "
             f"{forms['precision_coupled']['burn_in']} sweeps)")

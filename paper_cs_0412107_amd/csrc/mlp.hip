@@ -43,16 +43,6 @@ typedef unsigned short bf16_t;
 
 __device__ inline bf16_t to_bf16(float x) { return bf16_rne(x); }
 
-__device__ inline float gelu_f(float x)
-{
-    return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f));
-}
-
-__device__ inline float gelu_prime_f(float x)
-{
-    return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
-}
-
 __device__ inline bf16x8 load_bf16x8(const bf16_t* p)
 {
     const uint4 u = *reinterpret_cast<const uint4*>(p);
@@ -82,15 +72,41 @@ struct MlpArgs {
     float inv_denom;         // loss = sum_r w_r (out_r - y_r)^2 * inv_denom
 };
 
+// Write a wave's 16 rows x ncols block (bf16, row-major in LDS) to the
+// transposed buffer dst[col][R] at rows r0w..r0w+15: lane l takes columns
+// l, l + 64, ... and stores each column's 16 values as one 32-byte segment
+// (r0w is a multiple of 16 and R a multiple of 64, so segments are aligned).
+__device__ inline void store_transposed(const bf16_t (*src)[kActLd], int ncols, bf16_t* dst, int64_t R, int64_t r0w,
+                                        int lane)
+{
+    for (int c = lane; c < ncols; c += 64) {
+        u16x8 lo, hi;
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+            lo[r] = src[r][c];
+            hi[r] = src[8 + r][c];
+        }
+        uint4* d = reinterpret_cast<uint4*>(dst + (int64_t)c * R + r0w);
+        d[0] = __builtin_bit_cast(uint4, lo);
+        d[1] = __builtin_bit_cast(uint4, hi);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_mlp_fwd_bwd(const MlpArgs a)
 {
+    // act: h1 (bf16) as layer 2's A operand, then dz2 (bf16) as the dgrad A
+    // operand; gp1: gelu'(z1) kept from the forward pass for the backward
+    // one, so no first-layer pre-activations stay in registers.
     __shared__ __align__(16) bf16_t act[4][16][kActLd];
+    __shared__ __align__(16) bf16_t dz1s[4][16][kActLd];
+    __shared__ float gp1[4][16][kH + 4];
     __shared__ float part[4][kPart];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int i16 = lane & 15, kg = lane >> 4;
     const int64_t r0w = (int64_t)blockIdx.x * 64 + wid * 16;
     auto row_of = [&](int64_t r) { return a.idx ? a.idx[r] : a.row0 + r; };
     const float* P = a.P;
+    constexpr float kRs2 = 0.70710678118654752f, kRs2pi = 0.39894228040143268f;
 
     // ---- layer 1: A = normalised features (row i16, features 8kg..8kg+7)
     const int64_t ra = r0w + i16;
@@ -103,33 +119,35 @@ __global__ __launch_bounds__(256) void k_mlp_fwd_bwd(const MlpArgs a)
         for (int e = 0; e < 8; ++e) {
             const float xn = aok ? (x[e] - a.mean[8 * kg + e]) * a.inv_std[8 * kg + e] : 0.0f;
             u[e] = to_bf16(xn);
-            if (a.backward && aok) a.XT[(int64_t)(8 * kg + e) * a.R + ra] = u[e];
+            if (a.backward) act[wid][i16][8 * kg + e] = u[e];
         }
         u16x8 v;
 #pragma unroll
         for (int e = 0; e < 8; ++e) v[e] = u[e];
         a1 = __builtin_bit_cast(bf16x8, v);
     }
-    f32x4 z1[8];
-#pragma unroll
+    if (a.backward) {   // backward launches cover whole 64-row blocks
+        __syncthreads();
+        store_transposed(act[wid], kF, a.XT, a.R, r0w, lane);
+        __syncthreads();
+    }
+    // z1 -> h1 = GELU(z1) into LDS (bf16) and h1^T; gelu'(z1) into LDS
     for (int n = 0; n < 8; ++n) {
         const bf16x8 b = load_bf16x8(a.W1T + (16 * n + i16) * kF + 8 * kg);
-        z1[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        const f32x4 z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
         const float bias = P[ob1 + 16 * n + i16];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) z1[n][v] += bias;
-    }
-    // h1 -> LDS (A operand of layer 2) and, for the weight gradient, h1^T
-#pragma unroll
-    for (int n = 0; n < 8; ++n)
-#pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const bf16_t hb = to_bf16(gelu_f(z1[n][v]));
+            const float zz = z[v] + bias;
+            const float e = erff(zz * kRs2);
+            const bf16_t hb = to_bf16(0.5f * zz * (1.0f + e));
             act[wid][4 * kg + v][16 * n + i16] = hb;
-            const int64_t rd = r0w + 4 * kg + v;
-            if (a.backward && rd < a.R) a.h1T[(int64_t)(16 * n + i16) * a.R + rd] = hb;
+            if (a.backward)
+                gp1[wid][4 * kg + v][16 * n + i16] = 0.5f * (1.0f + e) + zz * expf(-0.5f * zz * zz) * kRs2pi;
         }
+    }
     __syncthreads();
+    if (a.backward) store_transposed(act[wid], kH, a.h1T, a.R, r0w, lane);
 
     // ---- layer 2
     f32x4 z2[8];
@@ -145,15 +163,17 @@ __global__ __launch_bounds__(256) void k_mlp_fwd_bwd(const MlpArgs a)
         const float bias = P[ob2 + 16 * n + i16];
 #pragma unroll
         for (int v = 0; v < 4; ++v) z2[n][v] = acc[v] + bias;
+        // one column block at a time: hoisting every block's weight loads
+        // measured 1.4x slower (register pressure, two waves per SIMD)
+        __builtin_amdgcn_sched_barrier(0);
     }
 
     // ---- layer 3 (fp32): out_v for rows r0w + 4kg + v
     float out[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
     for (int n = 0; n < 8; ++n) {
         const float w3 = P[ow3 + 16 * n + i16];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) out[v] += gelu_f(z2[n][v]) * w3;
+        for (int v = 0; v < 4; ++v) out[v] += 0.5f * z2[n][v] * (1.0f + erff(z2[n][v] * kRs2)) * w3;
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -186,34 +206,27 @@ __global__ __launch_bounds__(256) void k_mlp_fwd_bwd(const MlpArgs a)
         db3 += dv;
     }
 
-    // ---- layer 3 backward, layer 2 bias/delta
+    // ---- layer 3 backward and layer 2 deltas, written straight to LDS (bf16)
     float dw3p[8], db2p[8];
-    f32x4 dz2[8];
+    __syncthreads();  // every wave is done reading h1 from LDS
 #pragma unroll
     for (int n = 0; n < 8; ++n) {
         const float w3 = P[ow3 + 16 * n + i16];
         float s3 = 0.f, s2 = 0.f;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            s3 += gelu_f(z2[n][v]) * dout[v];
-            const float d = dout[v] * w3 * gelu_prime_f(z2[n][v]);
-            dz2[n][v] = d;
+            const float zz = z2[n][v];
+            const float e = erff(zz * kRs2);
+            s3 += 0.5f * zz * (1.0f + e) * dout[v];
+            const float d = dout[v] * w3 * (0.5f * (1.0f + e) + zz * expf(-0.5f * zz * zz) * kRs2pi);
             s2 += d;
+            act[wid][4 * kg + v][16 * n + i16] = to_bf16(d);
         }
         dw3p[n] = s3;
         db2p[n] = s2;
     }
-    __syncthreads();  // every wave is done reading h1 from LDS
-#pragma unroll
-    for (int n = 0; n < 8; ++n)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const bf16_t db = to_bf16(dz2[n][v]);
-            act[wid][4 * kg + v][16 * n + i16] = db;
-            const int64_t rd = r0w + 4 * kg + v;
-            if (rd < a.R) a.dz2T[(int64_t)(16 * n + i16) * a.R + rd] = db;
-        }
     __syncthreads();
+    store_transposed(act[wid], kH, a.dz2T, a.R, r0w, lane);
 
     // ---- dgrad of layer 2: dh1 = dz2 W2^T, then through GELU
     float db1p[8];
@@ -229,13 +242,16 @@ __global__ __launch_bounds__(256) void k_mlp_fwd_bwd(const MlpArgs a)
         float s1 = 0.f;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const float d = acc[v] * gelu_prime_f(z1[n][v]);
+            const float d = acc[v] * gp1[wid][4 * kg + v][16 * n + i16];
             s1 += d;
-            const int64_t rd = r0w + 4 * kg + v;
-            if (rd < a.R) a.dz1T[(int64_t)(16 * n + i16) * a.R + rd] = to_bf16(d);
+            dz1s[wid][4 * kg + v][16 * n + i16] = to_bf16(d);
         }
         db1p[n] = s1;
+        __builtin_amdgcn_sched_barrier(0);
     }
+
+    __syncthreads();
+    store_transposed(dz1s[wid], kH, a.dz1T, a.R, r0w, lane);
 
     // ---- per-wave sums over its 16 rows (the 4 row groups kg), then per block
 #pragma unroll
