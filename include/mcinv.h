@@ -173,7 +173,7 @@ mcinv_status mcinv_sample_until_trace(mcinv_ctx* ctx, double rel_se, int64_t max
 
 /* Estimates and standard errors in original indexing, caller-allocated.
  * quantity: one of MCINV_REQ_DIAG (n values), MCINV_REQ_BLOCK (rows x cols,
- * row-major), MCINV_REQ_ENTRIES (n_entries), MCINV_REQ_TRACE (1 value).
+ * row-major), MCINV_REQ_ENTRIES (n_entries), MCINV_REQ_TRACE or MCINV_REQ_QTRACE (1 value).
  * est receives 1 double per value for a real C, 2 (re, im) for a complex C;
  * stderr_ receives 1 double per value (sqrt(SE_re^2 + SE_im^2)); either may be
  * NULL.  capacity = number of values the arrays can hold (EINVAL if short).
