@@ -176,3 +176,23 @@ def test_batched_coupled_burn_in_equals_single_path(mats, schedule):
                 s.burn_in(N)
                 assert np.array_equal(b.state(j, 0), s.state(0))
                 assert np.array_equal(b.state(j, 1), s.state(1))
+
+
+def test_batched_full_size_sampled_pairs():
+    """The batched workload in the benchmark's launch configuration (512
+    pedigree matrices, n log-uniform in [1e3, 5e4], 64 pairs, autotuned
+    schedule): sampled pair columns of three matrices against the oracle."""
+    w = gen.WORKLOADS["batched"]
+    big = [gen.round_values(x, np.float32) for x in gen.batched_pedigrees(w["m"], w["lo"], w["hi"], w["seed"])]
+    P, G, seed = w["pairs"], w["groups"], w["noise_seed"]
+    print_case(test="batch_full", matrices=len(big), rows=sum(x.n for x in big))
+    with mc.BatchSampler(big, pairs=P, groups=G, seed=seed) as b:
+        b.autotune(1)
+        b.burn_in(2)
+        k = b.info()["sweeps_done"]
+        pids = np.array([0, 5, 63])
+        for m in (0, 255, 511):
+            ora = oracle.Run(big[m], seed=seed, pairs=P, pair_ids=pids, stream=m)
+            ora.burn_in(k)
+            assert rel_err(b.state(m, 0)[:, pids], ora.z) <= 1e-5
+            assert rel_err(b.state(m, 1)[:, pids], ora.w) <= 1e-5
