@@ -369,6 +369,31 @@ def test_xcd_order_does_not_change_results(dtype, maker):
         assert b.info()["sweeps_done"] == 7 + 4
 
 
+def test_stop_rows_restrict_the_stop_check():
+    """sample_until stops on the listed rows only: their max SE/|est| meets the
+    target while the whole diagonal's need not; the estimates themselves equal
+    those of an unrestricted context after the same number of sweeps."""
+    m = oracle_matrix(gen.pedigree(6000, seed=97), "f32")
+    rows = np.arange(0, 6000, 37)
+    with _sampler(m, "f32", 8, 256, 16) as a, _sampler(m, "f32", 8, 256, 16) as b:
+        a.burn_in(20)
+        b.burn_in(20)
+        a.request(diag=True, trace=False)
+        b.request(diag=True, trace=False)
+        a.set_stop_rows(rows)
+        done, ach = a.sample_until(0.03, 2000, 5)
+        b.sample(done)
+        da, sa = a.diag()
+        db, sb = b.diag()
+    rel = sa / np.abs(da)
+    assert np.max(rel[rows]) <= 0.03 + 1e-12 and abs(np.max(rel[rows]) - ach) < 1e-12
+    assert np.array_equal(da, db) and np.array_equal(sa, sb)
+    with _sampler(m, "f32", 8, 16) as c:
+        with pytest.raises(mc.McinvError) as ei:
+            c.set_stop_rows([6000])
+        assert ei.value.code == mc.MCINV_EINVAL
+
+
 def test_convergence_rate_is_spectral_radius():
     from oracle import theory
     rng = np.random.default_rng(13)
