@@ -509,6 +509,7 @@ int32_t kc_of(int32_t R)
 mcinv_status ensure_step(mcinv_mlp* m, int32_t R)
 {
     if (R <= m->Rcap) return MCINV_OK;
+    m->Rcap = 0;   // until every buffer below is allocated again
     mfree(m->idx);
     mfree(m->XT);
     mfree(m->h1T);
@@ -764,7 +765,10 @@ mcinv_status mcinv_mlp_gradients(mcinv_mlp* m, const int64_t* rows, int32_t nrow
     for (int32_t r = 0; r < nrows; ++r)
         if (rows[r] < 0 || rows[r] >= m->N) return merr(m, MCINV_EINVAL, "row index out of range");
     MHIP(m, hipSetDevice(m->device));
-    if (ensure_step(m, nrows) != MCINV_OK) return MCINV_ENOMEM;
+    {
+        const mcinv_status st = ensure_step(m, nrows);
+        if (st != MCINV_OK) return st;
+    }
     MHIP(m, hipMemcpyAsync(m->idx, rows, sizeof(int64_t) * nrows, hipMemcpyHostToDevice, m->stream));
     mcinv_status s = run_step(m, nrows, false, 0.0f, m->loss);
     if (s != MCINV_OK) return s;
@@ -784,24 +788,25 @@ mcinv_status mcinv_mlp_train(mcinv_mlp* m, int64_t steps, int32_t batch_rows, fl
         return merr(m, MCINV_EINVAL, "batch_rows must be a multiple of 64 in [64, 2^20]");
     if (m->N < 1) return merr(m, MCINV_ESTATE, "no training data");
     MHIP(m, hipSetDevice(m->device));
-    if (ensure_step(m, batch_rows) != MCINV_OK) return MCINV_ENOMEM;
-    float* dloss = nullptr;
-    if (loss_history && steps > 0) MHIP(m, hipMalloc((void**)&dloss, sizeof(float) * steps));
+    {
+        const mcinv_status st = ensure_step(m, batch_rows);
+        if (st != MCINV_OK) return st;
+    }
+    struct LossBuf {  // freed on every return path (hipFree waits for the device)
+        float* p = nullptr;
+        ~LossBuf() { mfree(p); }
+    } dloss;
+    if (loss_history && steps > 0) MHIP(m, hipMalloc((void**)&dloss.p, sizeof(float) * steps));
     for (int64_t s = 0; s < steps; ++s) {
         k_mlp_sample_rows<<<dim3((batch_rows + 255) / 256), dim3(256), 0, m->stream>>>(
             (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), (uint32_t)(m->t + 1), m->N, batch_rows, m->idx);
         MHIP(m, hipGetLastError());
-        const mcinv_status st = run_step(m, batch_rows, true, lr, dloss ? dloss + s : nullptr);
-        if (st != MCINV_OK) {
-            mfree(dloss);
-            return st;
-        }
+        const mcinv_status st = run_step(m, batch_rows, true, lr, dloss.p ? dloss.p + s : nullptr);
+        if (st != MCINV_OK) return st;
     }
-    if (dloss) {
-        MHIP(m, hipMemcpyAsync(loss_history, dloss, sizeof(float) * steps, hipMemcpyDeviceToHost, m->stream));
-    }
+    if (dloss.p)
+        MHIP(m, hipMemcpyAsync(loss_history, dloss.p, sizeof(float) * steps, hipMemcpyDeviceToHost, m->stream));
     MHIP(m, hipStreamSynchronize(m->stream));
-    mfree(dloss);
     return MCINV_OK;
 }
 
