@@ -243,6 +243,38 @@ def dirac_form(pkg, torch, gen):
             "paper_case1": {"burn_in": 18, "sample_cycles": 10832, "chain_pairs": 1}}
 
 
+def qtrace_form(pkg, torch, gen, w, steps=20):
+    """General-Q trace tr(Q C^-1) (eq tr) on the headline pedigree: a random
+    sparse Q with about 5 nonzeros per row; sampling sweeps with diag + trace
+    versus diag + trace + Q trace."""
+    import scipy.sparse as sp
+    P, G, seed = w["pairs"], w["groups"], w["noise_seed"]
+    m = gen.round_values(gen.pedigree(w["n"], seed=w["seed"]), np.float32)
+    rng = np.random.default_rng(7)
+    Q = (sp.random(m.n, m.n, density=4.0 / m.n, random_state=rng, format="csr") + sp.identity(m.n)).tocsr()
+    out = {"workload": f"pedigree n={m.n}, {P} pairs, Q: {Q.nnz} nonzeros"}
+    for name, with_q in (("diag_trace", False), ("diag_trace_qtrace", True)):
+        with pkg.Sampler(m, pairs=P, groups=G, dtype="f32", seed=seed, use_torch_stream=True) as s:
+            s.set_trace_matrix(Q)
+            s.burn_in(5)
+            s.request(diag=True, trace=True, qtrace=with_q)
+            s.sample(3)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.sample(steps)
+            torch.cuda.synchronize()
+            out[name] = {"ms_per_sweep": (time.perf_counter() - t0) * 1e3 / steps}
+            if with_q:
+                est, se = s.qtrace()
+                out[name]["estimate"] = float(np.real(est))
+                out[name]["se"] = float(se)
+    out["qtrace_ms_per_sample"] = out["diag_trace_qtrace"]["ms_per_sweep"] - out["diag_trace"]["ms_per_sweep"]
+    # algorithmic bytes of one Q-trace evaluation: Q's CSR, the gathered z slices and the w rows
+    qbytes = Q.nnz * (8 + 4) + 8 * (m.n + 1) + (Q.nnz + m.n) * P * 4
+    out["qtrace_algorithmic_GBps"] = qbytes / max(out["qtrace_ms_per_sample"], 1e-6) / 1e6
+    return out
+
+
 MLP_FLOP_PER_ROW_STEP = 2 * (32 * 128 + 128 * 128 + 128) + 2 * (2 * 128 + 2 * 128 * 128 + 32 * 128)
 
 
@@ -519,6 +551,9 @@ def main():
         if args.workload == "pedigree":
             forms["hermitian"] = hermitian_form(pkg, torch, gen, w)
             log(f"hermitian single-draw: {forms['hermitian']['speedup_sweep']:.2f}x per sweep")
+        if args.workload == "pedigree":
+            forms["qtrace"] = qtrace_form(pkg, torch, gen, w)
+            log(f"Q trace: {forms['qtrace']['qtrace_ms_per_sample']:.3f} ms per sample")
         if args.workload == "pedigree" and not args.no_dirac:
             forms["dirac"] = dirac_form(pkg, torch, gen)
             log(f"dirac 18^4: {forms['dirac']['seconds']:.2f} s to 1e-5 ({forms['dirac']['sample_sweeps']} sweeps)")
