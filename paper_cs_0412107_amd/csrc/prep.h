@@ -16,6 +16,7 @@
 #include <complex>
 #include <cstdint>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "device_common.h"
@@ -39,6 +40,25 @@ struct Prepared {
     std::vector<cd> a, b;           // per position
     std::vector<cd> diag;           // c_ii per position
 };
+
+// Run f(begin, end) over [0, n) split into contiguous ranges on up to 16
+// host threads (serially for small n).  Every stage below writes disjoint
+// outputs per index, so the result does not depend on the split.
+template <typename F>
+inline void parallel_for(int64_t n, F&& f)
+{
+    constexpr int64_t kGrain = 1 << 14;
+    int64_t T = std::min<int64_t>(16, std::max<unsigned>(1u, std::thread::hardware_concurrency()));
+    T = std::min<int64_t>(T, n / kGrain);
+    if (T <= 1) {
+        f((int64_t)0, n);
+        return;
+    }
+    std::vector<std::thread> th;
+    th.reserve((size_t)T);
+    for (int64_t t = 0; t < T; ++t) th.emplace_back([&f, n, t, T]() { f(n * t / T, n * (t + 1) / T); });
+    for (std::thread& x : th) x.join();
+}
 
 // Returns an empty string on success, else the reason; *singular is set when
 // the failure is a missing or zero diagonal.
@@ -72,53 +92,114 @@ inline std::string prepare_matrix(int64_t n, int64_t nnz, const int64_t* row_ptr
         }
     }
 
-    // Transpose: column i lists (row j, position of c_ji), rows ascending.
+    // Transpose: column i lists (row j, position of c_ji), rows ascending --
+    // a counting sort over row ranges: range t counts its entries per column,
+    // the per-column counts become per-range offsets, then every range writes
+    // its own slots (ranges ascend, so rows come out ascending).
     std::vector<int64_t> tptr(n + 1, 0);
-    for (int64_t e = 0; e < nnz; ++e) tptr[col_idx[e] + 1]++;
-    for (int64_t i = 0; i < n; ++i) tptr[i + 1] += tptr[i];
-    std::vector<int64_t> trow(nnz), tsrc(nnz);
+    std::vector<int32_t> trow(nnz);
+    std::vector<int64_t> tsrc(nnz);
     {
-        std::vector<int64_t> fill(tptr.begin(), tptr.end() - 1);
-        for (int64_t i = 0; i < n; ++i)
-            for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
-                const int64_t slot = fill[col_idx[e]]++;
-                trow[slot] = i;
-                tsrc[slot] = e;
+        const int64_t T = std::max<int64_t>(1, std::min<int64_t>(16, ((int64_t)1 << 25) / n));
+        std::vector<int32_t> cnt((size_t)(T * n), 0);
+        auto range_of = [&](int64_t t, int64_t* i0, int64_t* i1) {
+            *i0 = n * t / T;
+            *i1 = n * (t + 1) / T;
+        };
+        auto per_range = [&](auto&& body) {
+            std::vector<std::thread> th;
+            for (int64_t t = 1; t < T; ++t) th.emplace_back([&body, t]() { body(t); });
+            body(0);
+            for (std::thread& x : th) x.join();
+        };
+        per_range([&](int64_t t) {
+            int64_t i0, i1;
+            range_of(t, &i0, &i1);
+            int32_t* c = cnt.data() + t * n;
+            for (int64_t e = row_ptr[i0]; e < row_ptr[i1]; ++e) c[col_idx[e]]++;
+        });
+        parallel_for(n, [&](int64_t c0, int64_t c1) {
+            for (int64_t c = c0; c < c1; ++c) {
+                int32_t run = 0;
+                for (int64_t t = 0; t < T; ++t) {
+                    const int32_t k = cnt[t * n + c];
+                    cnt[t * n + c] = run;
+                    run += k;
+                }
+                tptr[c + 1] = run;
             }
+        });
+        for (int64_t i = 0; i < n; ++i) tptr[i + 1] += tptr[i];
+        per_range([&](int64_t t) {
+            int64_t i0, i1;
+            range_of(t, &i0, &i1);
+            int32_t* c = cnt.data() + t * n;
+            for (int64_t i = i0; i < i1; ++i)
+                for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+                    const int64_t slot = tptr[col_idx[e]] + c[col_idx[e]]++;
+                    trow[slot] = (int32_t)i;
+                    tsrc[slot] = e;
+                }
+        });
     }
 
-    // Merged off-diagonal pattern per original row.
-    std::vector<int64_t> mptr(n + 1, 0), mcol;
-    std::vector<cd> mu, mv;
-    mcol.reserve(2 * nnz);
-    mu.reserve(2 * nnz);
-    mv.reserve(2 * nnz);
-    for (int64_t i = 0; i < n; ++i) {
+    // Merged off-diagonal pattern per original row: the union of row i and
+    // column i (both ascending).  merge_row visits it in column order;
+    // emit(j, u, v) receives each neighbour j != i with its two coefficients.
+    auto merge_row = [&](int64_t i, auto&& emit) {
         const cd inv = 1.0 / diag[i];
+        const double inv_re = 1.0 / diag[i].real();   // real C: the same products without complex arithmetic
         int64_t e = row_ptr[i], t = tptr[i];
         const int64_t e_end = row_ptr[i + 1], t_end = tptr[i + 1];
         while (e < e_end || t < t_end) {
             const int64_t je = e < e_end ? col_idx[e] : INT64_MAX;
             const int64_t jt = t < t_end ? trow[t] : INT64_MAX;
             const int64_t j = std::min(je, jt);
-            cd u(0.0, 0.0), v(0.0, 0.0);
-            if (je == j) u = inv * val(e++);
-            if (jt == j) v = std::conj(inv) * std::conj(val(tsrc[t++]));
-            if (j == i) continue;
-            mcol.push_back(j);
-            mu.push_back(u);
-            mv.push_back(v);
+            const bool has_e = je == j, has_t = jt == j;
+            if (j != i) {
+                cd u(0.0, 0.0), v(0.0, 0.0);
+                if (complex_values) {
+                    if (has_e) u = inv * val(e);
+                    if (has_t) v = std::conj(inv) * std::conj(val(tsrc[t]));
+                } else {
+                    if (has_e) u = cd(inv_re * vd[e], 0.0);
+                    if (has_t) v = cd(inv_re * vd[tsrc[t]], 0.0);
+                }
+                emit(j, u, v);
+            }
+            e += has_e ? 1 : 0;
+            t += has_t ? 1 : 0;
         }
-        mptr[i + 1] = (int64_t)mcol.size();
-    }
+    };
+    std::vector<int32_t> mcount(n);
+    parallel_for(n, [&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i) {
+            int32_t k = 0;
+            // count only: the coefficients are not needed yet
+            int64_t e = row_ptr[i], t = tptr[i];
+            const int64_t e_end = row_ptr[i + 1], t_end = tptr[i + 1];
+            while (e < e_end || t < t_end) {
+                const int64_t je = e < e_end ? col_idx[e] : INT64_MAX;
+                const int64_t jt = t < t_end ? trow[t] : INT64_MAX;
+                const int64_t j = std::min(je, jt);
+                k += j != i ? 1 : 0;
+                e += je == j ? 1 : 0;
+                t += jt == j ? 1 : 0;
+            }
+            mcount[i] = k;
+        }
+    });
 
-    // Greedy first-fit colouring in natural order.
+    // Greedy first-fit colouring in natural order (neighbours read from row i
+    // and column i directly; a neighbour listed twice only marks twice).
     std::vector<int32_t> color(n, 0);
     std::vector<int64_t> mark(n + 1, -1);
     int32_t ncolors = 0;
     for (int64_t i = 0; i < n; ++i) {
-        for (int64_t e = mptr[i]; e < mptr[i + 1]; ++e)
-            if (mcol[e] < i) mark[color[mcol[e]]] = i;
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
+            if (col_idx[e] < i) mark[color[col_idx[e]]] = i;
+        for (int64_t t = tptr[i]; t < tptr[i + 1]; ++t)
+            if (trow[t] < i) mark[color[trow[t]]] = i;
         int32_t k = 0;
         while (mark[k] == i) ++k;
         color[i] = k;
@@ -140,32 +221,38 @@ inline std::string prepare_matrix(int64_t n, int64_t nnz, const int64_t* row_ptr
     h.n = n;
     h.nnz = nnz;
     h.ncolors = ncolors;
-    h.rows.assign(n, RowRec{});
-    h.a.assign(n, cd());
-    h.b.assign(n, cd());
-    h.diag.assign(n, cd());
-    h.ent.clear();
-    h.ent.reserve(mcol.size());
-    for (int64_t q = 0; q < n; ++q) {
-        const int64_t i = perm[q];
-        h.rows[q].begin = (int64_t)h.ent.size();
-        h.rows[q].count = (int32_t)(mptr[i + 1] - mptr[i]);
-        h.rows[q].orig = (uint32_t)i;
-        const size_t first = h.ent.size();
-        for (int64_t e = mptr[i]; e < mptr[i + 1]; ++e) h.ent.push_back(MergedEntry{pos[mcol[e]], mu[e], mv[e]});
-        std::sort(h.ent.begin() + first, h.ent.end(),
-                  [](const MergedEntry& x, const MergedEntry& y) { return x.col < y.col; });
-        const cd d = diag[i];
-        h.diag[q] = d;
-        if (!complex_values) {
-            const double s = 1.0 / std::sqrt(std::fabs(d.real()));
-            h.a[q] = cd(s, 0.0);
-            h.b[q] = cd(d.real() > 0 ? s : -s, 0.0);
-        } else {
-            h.a[q] = 1.0 / std::sqrt(d);
-            h.b[q] = std::conj(h.a[q]);
+    h.rows.resize(n);
+    h.a.resize(n);
+    h.b.resize(n);
+    h.diag.resize(n);
+    std::vector<int64_t> begin(n + 1, 0);
+    for (int64_t q = 0; q < n; ++q) begin[q + 1] = begin[q] + mcount[perm[q]];
+    h.ent.resize((size_t)begin[n]);
+    // rows in original order (sequential reads of C and its transpose), each
+    // written to its position's slot
+    parallel_for(n, [&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i) {
+            const int64_t q = pos[i];
+            h.rows[q].begin = begin[q];
+            h.rows[q].count = mcount[i];
+            h.rows[q].orig = (uint32_t)i;
+            MergedEntry* out = h.ent.data() + begin[q];
+            int32_t k = 0;
+            merge_row(i, [&](int64_t j, const cd& u, const cd& v) { out[k++] = MergedEntry{pos[j], u, v}; });
+            for (int32_t a = 1; a < k; ++a)   // rows are short: insertion sort by position
+                for (int32_t b = a; b > 0 && out[b - 1].col > out[b].col; --b) std::swap(out[b - 1], out[b]);
+            const cd d = diag[i];
+            h.diag[q] = d;
+            if (!complex_values) {
+                const double sc = 1.0 / std::sqrt(std::fabs(d.real()));
+                h.a[q] = cd(sc, 0.0);
+                h.b[q] = cd(d.real() > 0 ? sc : -sc, 0.0);
+            } else {
+                h.a[q] = 1.0 / std::sqrt(d);
+                h.b[q] = std::conj(h.a[q]);
+            }
         }
-    }
+    });
     h.perm = std::move(perm);
     h.pos = std::move(pos);
     h.color = std::move(color);
