@@ -100,7 +100,8 @@ inline std::string prepare_matrix(int64_t n, int64_t nnz, const int64_t* row_ptr
     std::vector<int32_t> trow(nnz);
     std::vector<int64_t> tsrc(nnz);
     {
-        const int64_t T = std::max<int64_t>(1, std::min<int64_t>(16, ((int64_t)1 << 25) / n));
+        // ranges: one per 16K rows, at most 16, and at most 2^25 / n (count memory)
+        const int64_t T = std::max<int64_t>(1, std::min<int64_t>({16, n >> 14, ((int64_t)1 << 25) / n}));
         std::vector<int32_t> cnt((size_t)(T * n), 0);
         auto range_of = [&](int64_t t, int64_t* i0, int64_t* i1) {
             *i0 = n * t / T;
