@@ -359,7 +359,8 @@ mcinv_status mcinv_batch_read_state(mcinv_batch* b, int64_t m, int32_t which, fl
 /* Time every (schedule, rows per item, items per grab) candidate on
  * sweeps_per_trial burn-in sweeps (plus one warm-up each; the chains advance
  * as in burn-in, and the schedule never changes the chains) and keep the
- * fastest.  Any output pointer may be NULL. */
+ * fastest; a schedule whose first candidate takes over twice the best time so
+ * far is not explored further.  Any output pointer may be NULL. */
 mcinv_status mcinv_batch_autotune(mcinv_batch* b, int32_t sweeps_per_trial, int32_t* schedule,
                                   int32_t* rows_per_item, int32_t* grab, double* ms_per_sweep);
 

@@ -827,10 +827,12 @@ mcinv_status mcinv_batch_autotune(mcinv_batch* b, int32_t sweeps_per_trial, int3
     hipEvent_t e0, e1;
     BHIP(b, hipEventCreate(&e0));
     BHIP(b, hipEventCreate(&e1));
-    for (int32_t sched : {MCINV_SCHEDULE_PHASED, MCINV_SCHEDULE_PERSISTENT})
+    for (int32_t sched : {MCINV_SCHEDULE_PHASED, MCINV_SCHEDULE_PERSISTENT}) {
+    bool first = true, skip = false;
     for (int32_t r : rows_c)
         for (int32_t g : grab_c) {
             if (sched == MCINV_SCHEDULE_PHASED && g != grab_c[0]) continue;  // grab is persistent-only
+            if (skip) continue;
             b->schedule = sched;
             b->rows_per_item = r;
             b->grab = g;
@@ -843,6 +845,9 @@ mcinv_status mcinv_batch_autotune(mcinv_batch* b, int32_t sweeps_per_trial, int3
             float ms = 0.f;
             BHIP(b, hipEventElapsedTime(&ms, e0, e1));
             const double per = ms / sweeps_per_trial;
+            // a schedule whose first candidate is over twice the best so far is not explored further
+            if (first && per > 2.0 * best) skip = true;
+            first = false;
             if (per < best) {
                 best = per;
                 best_r = r;
@@ -850,6 +855,7 @@ mcinv_status mcinv_batch_autotune(mcinv_batch* b, int32_t sweeps_per_trial, int3
                 best_s = sched;
             }
         }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     b->rows_per_item = best_r;
