@@ -158,7 +158,7 @@ class Sampler:
         mcinv_set_stop_rows(self.ctx, rows)
 
     def tune_launch(self, sweeps_per_trial=2):
-        """Pick the faster sweep workgroup order; returns (order, ms natural, ms XCD-contiguous)."""
+        """Pick the fastest sweep workgroup order; returns (order, ms per sweep of orders 0, 1, 2)."""
         from ._binding import mcinv_tune_launch
         return mcinv_tune_launch(self.ctx, sweeps_per_trial)
 

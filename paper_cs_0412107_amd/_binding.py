@@ -134,7 +134,7 @@ SIGNATURES = {
     "mcinv_set_trace_matrix": (_I32, [_P, _I64, _P, _P, _P, _I32]),
     "mcinv_save": (_I32, [_P, ctypes.c_char_p]),
     "mcinv_restore": (_I32, [_P, ctypes.c_char_p]),
-    "mcinv_tune_launch": (_I32, [_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+    "mcinv_tune_launch": (_I32, [_P, _I32, ctypes.POINTER(_I32), _P]),
     "mcinv_check_convergence": (_I32, [_P, _I64, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
     "mcinv_get_info": (_I32, [_P, ctypes.POINTER(mcinv_info)]),
     "mcinv_reset_profile": (_I32, [_P]),
@@ -335,11 +335,9 @@ def mcinv_get_permutation(ctx, n):
 
 def mcinv_tune_launch(ctx, sweeps_per_trial=2):
     o = ctypes.c_int32(0)
-    a = ctypes.c_double(0)
-    b = ctypes.c_double(0)
-    _check(ctx, lib().mcinv_tune_launch(ctx, int(sweeps_per_trial), ctypes.byref(o), ctypes.byref(a),
-                                        ctypes.byref(b)))
-    return o.value, a.value, b.value
+    ms = np.zeros(3, dtype=np.float64)
+    _check(ctx, lib().mcinv_tune_launch(ctx, int(sweeps_per_trial), ctypes.byref(o), _ptr(ms)))
+    return o.value, ms
 
 
 def mcinv_check_convergence(ctx, iters):

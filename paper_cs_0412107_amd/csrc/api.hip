@@ -316,7 +316,7 @@ mcinv_status run_sweeps(mcinv_ctx* c, int64_t nsw, bool sample, V* z, V* w, int6
     a.n = c->n;
     a.flag = flag;
     a.thresh = (typename Real<V>::type)kGuardThreshold;
-    a.xcd_order = c->cfg.xcd_order ? 1 : 0;
+    a.xcd_order = c->cfg.xcd_order;
 
     const bool prof = c->cfg.profile != 0 && use_counters;
     size_t next_ev = 0;
@@ -568,7 +568,7 @@ mcinv_status mcinv_create(const mcinv_config* cfg, mcinv_ctx** out)
     if (cfg->moments == MCINV_MOMENTS_BF16X3 && cfg->sweep_dtype != MCINV_R32)
         return fail(nullptr, MCINV_EINVAL, "bf16x3 block moments need a real fp32 sweep");
     if (cfg->n_pairs < 1 || cfg->n_pairs > (int64_t)1 << 30) return fail(nullptr, MCINV_EINVAL, "n_pairs out of range");
-    if (cfg->xcd_order != 0 && cfg->xcd_order != 1) return fail(nullptr, MCINV_EINVAL, "xcd_order must be 0 or 1");
+    if (cfg->xcd_order < 0 || cfg->xcd_order > 2) return fail(nullptr, MCINV_EINVAL, "xcd_order must be 0, 1 or 2");
     const int64_t P = cfg->n_pairs, G = cfg->n_groups;
     if (G < 1 || P % G != 0) return fail(nullptr, MCINV_EINVAL, "n_groups must divide n_pairs");
     const int64_t gs = P / G;
@@ -798,17 +798,16 @@ mcinv_status mcinv_burn_in(mcinv_ctx* c, int64_t sweeps)
     return check_flag(c);
 }
 
-mcinv_status mcinv_tune_launch(mcinv_ctx* c, int32_t sweeps_per_trial, int32_t* xcd_order, double* ms_natural,
-                               double* ms_xcd)
+mcinv_status mcinv_tune_launch(mcinv_ctx* c, int32_t sweeps_per_trial, int32_t* xcd_order, double* ms_orders)
 {
     MC_TRY(check_ready(c));
     if (sweeps_per_trial < 1) return fail(c, MCINV_EINVAL, "sweeps_per_trial must be >= 1");
     hipEvent_t e0, e1;
     HIP_TRY(c, hipEventCreate(&e0));
     HIP_TRY(c, hipEventCreate(&e1));
-    double ms[2] = {0.0, 0.0};
+    double ms[3] = {0.0, 0.0, 0.0};
     mcinv_status s = MCINV_OK;
-    for (int order = 0; order < 2 && s == MCINV_OK; ++order) {
+    for (int order = 0; order < 3 && s == MCINV_OK; ++order) {
         c->cfg.xcd_order = order;
         if ((s = dispatch_sweeps(c, 1, false)) != MCINV_OK) break;
         if (hipEventRecord(e0, c->stream) != hipSuccess) s = fail(c, MCINV_EDEVICE, "hipEventRecord failed");
@@ -823,10 +822,13 @@ mcinv_status mcinv_tune_launch(mcinv_ctx* c, int32_t sweeps_per_trial, int32_t* 
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (s != MCINV_OK) return s;
-    c->cfg.xcd_order = ms[1] < ms[0] ? 1 : 0;
-    if (xcd_order) *xcd_order = c->cfg.xcd_order;
-    if (ms_natural) *ms_natural = ms[0];
-    if (ms_xcd) *ms_xcd = ms[1];
+    int best = 0;
+    for (int order = 1; order < 3; ++order)
+        if (ms[order] < ms[best]) best = order;
+    c->cfg.xcd_order = best;
+    if (xcd_order) *xcd_order = best;
+    if (ms_orders)
+        for (int order = 0; order < 3; ++order) ms_orders[order] = ms[order];
     return check_flag(c);
 }
 

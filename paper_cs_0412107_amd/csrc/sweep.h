@@ -31,7 +31,8 @@ struct SweepArgs {
     double* tpart;           // per-workgroup trace partials of this launch, or null
     int32_t* flag;           // divergence flag (bit 0)
     typename Real<V>::type thresh;
-    int32_t xcd_order;       // 0: natural workgroup order; 1: contiguous tile ranges per XCD
+    int32_t xcd_order;       // 0: natural workgroup order; 1: contiguous tile ranges per XCD;
+                             // 2: runs of 16 consecutive row blocks per XCD
 };
 
 // Launch over pair tiles [a.tile0, a.tile0 + ntiles).  herm: C is hermitian

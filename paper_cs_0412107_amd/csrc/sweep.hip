@@ -87,7 +87,17 @@ __global__ __launch_bounds__(256) void k_sweep(const SweepArgs<V> a)
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     uint32_t bx = blockIdx.x, by = blockIdx.y;
-    if (a.xcd_order) {
+    if (a.xcd_order == 2) {
+        // XCD x takes runs of 16 consecutive row blocks of a tile: workgroups
+        // k, k + 8, ... (one XCD) sweep neighbouring rows, whose neighbour
+        // slices then share that XCD's L2 (pays off on lattice-like patterns)
+        constexpr uint32_t C = 16;
+        const uint32_t k = blockIdx.x, whole = gridDim.x / (8 * C) * (8 * C);
+        if (k < whole) {
+            const uint32_t r = k % (8 * C);
+            bx = k - r + (r % 8) * C + r / 8;
+        }
+    } else if (a.xcd_order == 1) {
         // XCD-aware order: workgroups are dealt round-robin to the 8 XCDs, so
         // give XCD x one contiguous range of (tile, row block) indices of this
         // launch (each XCD's L2 then holds the neighbour slices of its own
