@@ -321,15 +321,16 @@ mcinv_status mcinv_batch_load_csr(mcinv_batch* b, int64_t m, int64_t n, int64_t 
 /* flags: MCINV_REQ_DIAG and/or MCINV_REQ_BLOCK.  block_dim (1..128): each
  * matrix's block is its last block_dim rows x columns unless set with
  * mcinv_batch_set_block.  expected_samples sets the block time-batch length.
- * Clears the moments and the sample count. */
+ * Clears the moments and the sample counts, and makes every matrix active
+ * again (see mcinv_batch_sample_until_each). */
 mcinv_status mcinv_batch_set_requested(mcinv_batch* b, uint32_t flags, int32_t block_dim, int64_t expected_samples);
 
 /* Block rows and columns of matrix m (block_dim original indices each). */
 mcinv_status mcinv_batch_set_block(mcinv_batch* b, int64_t m, const int64_t* rows, const int64_t* cols);
 
-/* Burn-in / sampling sweeps of every matrix (one persistent launch per call,
- * split only beyond 2^30 work items).  EDIVERGED as mcinv_burn_in; EDEVICE if
- * a dependency wait inside the launch exceeded its bound. */
+/* Burn-in / sampling sweeps of every active matrix (one persistent launch per
+ * call, split only beyond 2^30 work items).  EDIVERGED as mcinv_burn_in;
+ * EDEVICE if a dependency wait inside the launch exceeded its bound. */
 mcinv_status mcinv_batch_burn_in(mcinv_batch* b, int64_t sweeps);
 mcinv_status mcinv_batch_sample(mcinv_batch* b, int64_t sweeps);
 
@@ -346,6 +347,22 @@ mcinv_status mcinv_batch_burn_in_coupled(mcinv_batch* b, double tol, int64_t max
  * diagonal is <= rel_se (or max_sweeps). */
 mcinv_status mcinv_batch_sample_until(mcinv_batch* b, double rel_se, int64_t max_sweeps, int64_t check_every,
                                       int64_t* sweeps_done, double* achieved);
+
+/* Per-matrix stopping rule: sample in chunks of check_every sweeps; after each
+ * chunk, every active matrix whose max over rows of SE/|est| (diagonal) is
+ * <= rel_se stops -- it gets no further sweeps, so its chains, moments and
+ * sample count stay as they were (each matrix ends where mcinv_sample_until
+ * would have ended it alone, given the same burn-in).  Ends when no matrix is
+ * active or after max_sweeps.  *sweeps_done: sweeps of the longest-running
+ * matrix; *achieved: max over all matrices of their last checked value.
+ * Later burn_in / sample calls sweep only the active matrices;
+ * mcinv_batch_set_requested reactivates all.  Outputs may be NULL. */
+mcinv_status mcinv_batch_sample_until_each(mcinv_batch* b, double rel_se, int64_t max_sweeps, int64_t check_every,
+                                           int64_t* sweeps_done, double* achieved);
+
+/* Per matrix: samples accumulated (int64_t[n_matrices]) and whether it is
+ * still active (uint8_t[n_matrices], 1 = active).  Either may be NULL. */
+mcinv_status mcinv_batch_matrix_samples(mcinv_batch* b, int64_t* samples, uint8_t* active);
 
 /* Estimates of matrix m: MCINV_REQ_DIAG (n values, original order) or
  * MCINV_REQ_BLOCK (block_dim^2, row-major); est and stderr_ as

@@ -228,6 +228,16 @@ class BatchSampler:
     def sample_until(self, rel_se, max_sweeps, check_every=10):
         return mcinv_batch_sample_until(self.b, rel_se, max_sweeps, check_every)
 
+    def sample_until_each(self, rel_se, max_sweeps, check_every=10):
+        """Each matrix stops at its own first check that meets rel_se."""
+        from ._binding import mcinv_batch_sample_until_each
+        return mcinv_batch_sample_until_each(self.b, rel_se, max_sweeps, check_every)
+
+    def matrix_samples(self):
+        """(samples per matrix, active flags)."""
+        from ._binding import mcinv_batch_matrix_samples
+        return mcinv_batch_matrix_samples(self.b, len(self.n))
+
     def diag(self, m):
         return mcinv_batch_read_estimates(self.b, m, MCINV_REQ_DIAG, self.n[m])
 

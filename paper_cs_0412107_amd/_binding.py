@@ -149,6 +149,8 @@ SIGNATURES = {
     "mcinv_batch_sample": (_I32, [_P, _I64]),
     "mcinv_batch_burn_in_coupled": (_I32, [_P, _D, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_D)]),
     "mcinv_batch_sample_until": (_I32, [_P, _D, _I64, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_D)]),
+    "mcinv_batch_sample_until_each": (_I32, [_P, _D, _I64, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_D)]),
+    "mcinv_batch_matrix_samples": (_I32, [_P, _P, _P]),
     "mcinv_batch_read_estimates": (_I32, [_P, _I64, _U32, _P, _P, _I64]),
     "mcinv_batch_read_state": (_I32, [_P, _I64, _I32, _P, _I64]),
     "mcinv_batch_autotune": (_I32, [_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32),
@@ -434,6 +436,21 @@ def mcinv_batch_sample_until(b, rel_se, max_sweeps, check_every):
     _bcheck(b, lib().mcinv_batch_sample_until(b, float(rel_se), int(max_sweeps), int(check_every),
                                               ctypes.byref(done), ctypes.byref(ach)))
     return done.value, ach.value
+
+
+def mcinv_batch_sample_until_each(b, rel_se, max_sweeps, check_every):
+    done = ctypes.c_int64(0)
+    ach = ctypes.c_double(0)
+    _bcheck(b, lib().mcinv_batch_sample_until_each(b, float(rel_se), int(max_sweeps), int(check_every),
+                                                   ctypes.byref(done), ctypes.byref(ach)))
+    return done.value, ach.value
+
+
+def mcinv_batch_matrix_samples(b, n_matrices):
+    samples = np.zeros(n_matrices, dtype=np.int64)
+    active = np.zeros(n_matrices, dtype=np.uint8)
+    _bcheck(b, lib().mcinv_batch_matrix_samples(b, _ptr(samples), _ptr(active)))
+    return samples, active.astype(bool)
 
 
 def mcinv_batch_read_estimates(b, m, quantity, count):

@@ -66,6 +66,7 @@ struct mcinv_batch {
     BItem* d_items_burn = nullptr;
     BItem* d_items_sample = nullptr;
     BMat* d_mats_sample = nullptr;
+    size_t cap_items_burn = 0, cap_items_sample = 0, cap_mats_burn = 0, cap_mats_sample = 0;  // allocated lengths
     int64_t ips_burn = 0, ips_sample = 0;
     int32_t schedule = MCINV_SCHEDULE_PHASED;
     // phase boundaries of the item lists (burn, sample) and whether a phase is
@@ -89,8 +90,18 @@ struct mcinv_batch {
     double* d_slot_len = nullptr;
     double* d_est = nullptr;
     double* d_se = nullptr;
-    unsigned long long* d_maxrel = nullptr;
     double last_ms = 0.0;
+
+    // Per-matrix stopping (mcinv_batch_sample_until_each): a matrix that met
+    // the tolerance is left out of the item lists, so its chains and
+    // accumulators stay as they were when it stopped.
+    std::vector<uint8_t> active;
+    std::vector<int64_t> msamples;          // samples accumulated per matrix
+    std::vector<double> mrel;               // per matrix: max se/|est| at its last check
+    int32_t* d_row_mat = nullptr;           // position -> matrix
+    int64_t* d_row0 = nullptr;              // [M + 1] first position of each matrix
+    double* d_rel = nullptr;                // [nrows] se/|est| per position at the last check
+    double* d_mrel = nullptr;               // [M] per-matrix max of d_rel
 
     std::string err;
 };
@@ -144,6 +155,19 @@ mcinv_status bupload(mcinv_batch* b, T** p, const std::vector<T>& h)
     return MCINV_OK;
 }
 
+// Upload into a device array that is reallocated only when it must grow.
+template <typename T>
+mcinv_status bupload_keep(mcinv_batch* b, T** p, size_t* cap, const std::vector<T>& h)
+{
+    if (*p == nullptr || h.size() > *cap) {
+        bfree(*p);
+        BTRY(balloc(b, p, h.size()));
+        *cap = std::max<size_t>(h.size(), 1);
+    }
+    if (!h.empty()) BHIP(b, hipMemcpyAsync(*p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, b->stream));
+    return MCINV_OK;
+}
+
 void drop_graphs(mcinv_batch* b)
 {
     for (auto& kv : b->graphs) {
@@ -155,6 +179,7 @@ void drop_graphs(mcinv_batch* b)
 
 // One sweep's items: colours ascending, matrices ascending, chunks of
 // rows_per_item rows; then (sampling with a block) one block item per matrix.
+// Matrices that have stopped (not active) get no items.
 mcinv_status build_items(mcinv_batch* b)
 {
     for (int pass = 0; pass < 2; ++pass) {
@@ -168,7 +193,7 @@ mcinv_status build_items(mcinv_batch* b)
             b->phase_block[pass].push_back(false);
             for (int64_t m = 0; m < b->M; ++m) {
                 const Prepared& h = b->prep[m];
-                if (c >= h.ncolors) continue;
+                if (c >= h.ncolors || !b->active[m]) continue;
                 const int64_t beg = b->row0[m] + h.color_ptr[c], end = b->row0[m] + h.color_ptr[c + 1];
                 const int32_t prior = per_m[m];
                 for (int64_t r = beg; r < end; r += b->rows_per_item) {
@@ -189,6 +214,7 @@ mcinv_status build_items(mcinv_batch* b)
         }
         if (with_block)
             for (int64_t m = 0; m < b->M; ++m) {
+                if (!b->active[m]) continue;
                 BItem it{};
                 it.m = (int32_t)m;
                 it.kind = 1;
@@ -206,12 +232,12 @@ mcinv_status build_items(mcinv_batch* b)
             mats[m].blk = b->bdim > 0 ? m * b->bdim : -1;
         }
         if (pass == 0) {
-            BTRY(bupload(b, &b->d_items_burn, items));
-            BTRY(bupload(b, &b->d_mats, mats));
+            BTRY(bupload_keep(b, &b->d_items_burn, &b->cap_items_burn, items));
+            BTRY(bupload_keep(b, &b->d_mats, &b->cap_mats_burn, mats));
             b->ips_burn = (int64_t)items.size();
         } else {
-            BTRY(bupload(b, &b->d_items_sample, items));
-            BTRY(bupload(b, &b->d_mats_sample, mats));
+            BTRY(bupload_keep(b, &b->d_items_sample, &b->cap_items_sample, items));
+            BTRY(bupload_keep(b, &b->d_mats_sample, &b->cap_mats_sample, mats));
             b->ips_sample = (int64_t)items.size();
         }
     }
@@ -264,6 +290,18 @@ mcinv_status commit(mcinv_batch* b)
     BTRY(bupload(b, &b->d_ent, ent));
     BTRY(bupload(b, &b->d_sc, sc));
     BTRY(bupload(b, &b->d_orig, orig));
+    std::vector<int32_t> row_mat(b->nrows);
+    for (int64_t m = 0; m < b->M; ++m)
+        for (int64_t q = b->row0[m]; q < b->row0[m + 1]; ++q) row_mat[q] = (int32_t)m;
+    BTRY(bupload(b, &b->d_row_mat, row_mat));
+    BTRY(bupload(b, &b->d_row0, b->row0));
+    BTRY(balloc(b, &b->d_rel, (size_t)b->nrows));
+    BTRY(balloc(b, &b->d_mrel, (size_t)b->M));
+    bfree(b->d_slot_len);
+    BTRY(balloc(b, &b->d_slot_len, (size_t)b->M * std::max(kBlockSlots, kDiagSlotsSmallG)));
+    b->active.assign(b->M, 1);
+    b->msamples.assign(b->M, 0);
+    b->mrel.assign(b->M, INFINITY);
     const size_t sbytes = (size_t)b->nrows * b->P * sizeof(float);
     BHIP(b, hipMalloc((void**)&b->d_z, sbytes));
     BHIP(b, hipMalloc((void**)&b->d_w, sbytes));
@@ -363,7 +401,11 @@ mcinv_status run_sweeps(mcinv_batch* b, int64_t nsweeps, bool sample, bool use_g
         }
         left -= k;
         b->sweeps += k;
-        if (sample) b->samples += k;
+        if (sample) {
+            b->samples += k;
+            for (int64_t m = 0; m < b->M; ++m)
+                if (b->active[m]) b->msamples[m] += k;
+        }
     }
     return MCINV_OK;
 }
@@ -392,12 +434,17 @@ std::vector<double> slot_lengths(int64_t samples, int64_t L, int32_t nslots)
     return len;
 }
 
+// Estimates and SEs of every matrix's diagonal, each over its own samples;
+// with want_max, b->mrel receives each matrix's max se/|est|.
 mcinv_status finalize_diag_all(mcinv_batch* b, bool want_max)
 {
-    const std::vector<double> len = slot_lengths(b->samples, b->batch_len, b->nslots_diag);
+    std::vector<double> len((size_t)b->M * b->nslots_diag);
+    for (int64_t m = 0; m < b->M; ++m) {
+        const std::vector<double> l = slot_lengths(b->msamples[m], b->batch_len, b->nslots_diag);
+        std::copy(l.begin(), l.end(), len.begin() + m * b->nslots_diag);
+    }
     BHIP(b, hipMemcpyAsync(b->d_slot_len, len.data(), sizeof(double) * len.size(), hipMemcpyHostToDevice,
                            b->stream));
-    if (want_max) BHIP(b, hipMemsetAsync(b->d_maxrel, 0, sizeof(unsigned long long), b->stream));
     FinalizeArgs f{};
     f.acc = b->d_diag;
     f.nslots = b->nslots_diag;
@@ -412,8 +459,15 @@ mcinv_status finalize_diag_all(mcinv_batch* b, bool want_max)
     f.mstride = b->G;
     f.est = b->d_est;
     f.se = b->d_se;
-    f.max_rel = want_max ? b->d_maxrel : nullptr;
-    BHIP(b, launch_finalize_flat(f, b->stream));
+    f.val_group = b->d_row_mat;
+    f.slot_len_stride = b->nslots_diag;
+    f.rel_out = want_max ? b->d_rel : nullptr;
+    BHIP(b, launch_finalize_groups(f, b->stream));
+    if (want_max) {
+        BHIP(b, launch_segment_max(b->d_rel, b->d_row0, b->M, b->d_mrel, b->stream));
+        BHIP(b, hipMemcpyAsync(b->mrel.data(), b->d_mrel, sizeof(double) * b->M, hipMemcpyDeviceToHost, b->stream));
+        BHIP(b, hipStreamSynchronize(b->stream));
+    }
     return MCINV_OK;
 }
 
@@ -476,7 +530,6 @@ mcinv_status mcinv_batch_create(const mcinv_batch_config* cfg, int64_t n_matrice
     b->grid = prop.multiProcessorCount * batch_kernel_occupancy();
     if (hipMalloc((void**)&b->d_clock, sizeof(BatchClock)) != hipSuccess ||
         hipMalloc((void**)&b->d_flag, sizeof(int32_t)) != hipSuccess ||
-        hipMalloc((void**)&b->d_maxrel, sizeof(unsigned long long)) != hipSuccess ||
         hipMalloc((void**)&b->d_slot_len, sizeof(double) * std::max(kBlockSlots, kDiagSlotsSmallG)) != hipSuccess)
         return bail("device allocation failed");
     if (hipMemsetAsync(b->d_clock, 0, sizeof(BatchClock), b->stream) != hipSuccess ||
@@ -513,7 +566,10 @@ void mcinv_batch_destroy(mcinv_batch* b)
     bfree(b->d_slot_len);
     bfree(b->d_est);
     bfree(b->d_se);
-    bfree(b->d_maxrel);
+    bfree(b->d_row_mat);
+    bfree(b->d_row0);
+    bfree(b->d_rel);
+    bfree(b->d_mrel);
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
     delete b;
 }
@@ -574,6 +630,10 @@ mcinv_status mcinv_batch_set_requested(mcinv_batch* b, uint32_t flags, int32_t b
     BTRY(balloc(b, &b->d_est, (size_t)cap));
     BTRY(balloc(b, &b->d_se, (size_t)cap));
     b->samples = 0;
+    // every matrix takes part again, from zero samples
+    std::fill(b->active.begin(), b->active.end(), (uint8_t)1);
+    std::fill(b->msamples.begin(), b->msamples.end(), (int64_t)0);
+    std::fill(b->mrel.begin(), b->mrel.end(), (double)INFINITY);
     // the device clock's sample count restarts with the accumulators
     BatchClock clk{};
     BHIP(b, hipMemcpyAsync(&clk, b->d_clock, sizeof(clk), hipMemcpyDeviceToHost, b->stream));
@@ -749,14 +809,57 @@ mcinv_status mcinv_batch_sample_until(mcinv_batch* b, double rel_se, int64_t max
         BTRY(run_sweeps(b, chunk, true));
         done += chunk;
         BTRY(finalize_diag_all(b, true));
-        unsigned long long bits = 0;
-        BHIP(b, hipMemcpyAsync(&bits, b->d_maxrel, sizeof(bits), hipMemcpyDeviceToHost, b->stream));
         BTRY(check_after(b));
-        std::memcpy(&maxrel, &bits, sizeof(double));
+        maxrel = *std::max_element(b->mrel.begin(), b->mrel.end());
         if (maxrel <= rel_se) break;
     }
     if (sweeps_done) *sweeps_done = done;
     if (achieved) *achieved = maxrel;
+    return MCINV_OK;
+}
+
+mcinv_status mcinv_batch_sample_until_each(mcinv_batch* b, double rel_se, int64_t max_sweeps, int64_t check_every,
+                                           int64_t* sweeps_done, double* achieved)
+{
+    BTRY(check_batch(b));
+    if (!b->requested || !(b->flags & MCINV_REQ_DIAG))
+        return bfail(b, MCINV_ESTATE, "sample_until_each needs MCINV_REQ_DIAG requested");
+    if (check_every < 1 || max_sweeps < 0) return bfail(b, MCINV_EINVAL, "bad sweep counts");
+    int64_t done = 0;
+    int64_t left = std::count(b->active.begin(), b->active.end(), (uint8_t)1);
+    // Once a matrix has stopped, the item lists change at every few checks:
+    // the chunks are then launched directly rather than captured and
+    // instantiated as graphs for a single replay.
+    bool graphs = true;
+    while (done < max_sweeps && left > 0) {
+        const int64_t chunk = std::min(check_every, max_sweeps - done);
+        BTRY(run_sweeps(b, chunk, true, graphs));
+        done += chunk;
+        BTRY(finalize_diag_all(b, true));
+        BTRY(check_after(b));
+        bool stopped = false;
+        for (int64_t m = 0; m < b->M; ++m)
+            if (b->active[m] && b->mrel[m] <= rel_se) {
+                b->active[m] = 0;
+                stopped = true;
+                --left;
+            }
+        // the remaining matrices' item lists (and the graphs replaying them)
+        if (stopped) {
+            BTRY(build_items(b));
+            graphs = false;
+        }
+    }
+    if (sweeps_done) *sweeps_done = done;
+    if (achieved) *achieved = *std::max_element(b->mrel.begin(), b->mrel.end());
+    return MCINV_OK;
+}
+
+mcinv_status mcinv_batch_matrix_samples(mcinv_batch* b, int64_t* samples, uint8_t* active)
+{
+    BTRY(check_batch(b));
+    if (samples) std::copy(b->msamples.begin(), b->msamples.end(), samples);
+    if (active) std::copy(b->active.begin(), b->active.end(), active);
     return MCINV_OK;
 }
 
@@ -775,7 +878,7 @@ mcinv_status mcinv_batch_read_estimates(mcinv_batch* b, int64_t m, uint32_t quan
     } else if (quantity == MCINV_REQ_BLOCK) {
         count = (int64_t)b->bdim * b->bdim;
         if (capacity < count) return bfail(b, MCINV_EINVAL, "capacity too small");
-        const std::vector<double> len = slot_lengths(b->samples, b->batch_len, kBlockSlots);
+        const std::vector<double> len = slot_lengths(b->msamples[m], b->batch_len, kBlockSlots);
         BHIP(b, hipMemcpyAsync(b->d_slot_len, len.data(), sizeof(double) * len.size(), hipMemcpyHostToDevice,
                                b->stream));
         FinalizeArgs f{};

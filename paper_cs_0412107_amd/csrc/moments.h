@@ -78,11 +78,18 @@ struct FinalizeArgs {
     int64_t mstride;         // flat only: between consecutive values (0: 1)
     double* est;             // [M][comps] (at out_index)
     double* se;              // [M]
-    unsigned long long* max_rel;  // diag only, may be null: max se/|est| as bits
+    unsigned long long* max_rel;  // diag / flat, may be null: max se/|est| as bits
     const uint8_t* stop_mask;     // diag only, may be null: rows (output index) that max_rel covers
+    const int32_t* val_group;     // groups only, may be null: value -> its own slot lengths at
+    int64_t slot_len_stride;      //   slot_len + val_group[v] * slot_len_stride (one matrix of a batch)
+    double* rel_out;              // groups only, may be null: per value se/|est| (+inf without estimate)
 };
 hipError_t launch_finalize_diag(const FinalizeArgs& f, hipStream_t stream);
 hipError_t launch_finalize_flat(const FinalizeArgs& f, hipStream_t stream);
+// Flat layout [nslots][M][G] (G a power of two <= 64), coalesced.
+hipError_t launch_finalize_groups(const FinalizeArgs& f, hipStream_t stream);
+// out[s] = max of x[begin[s] .. begin[s+1]), one workgroup per segment.
+hipError_t launch_segment_max(const double* x, const int64_t* begin, int64_t nseg, double* out, hipStream_t stream);
 
 // Geyer initial-positive-sequence error of the per-sweep trace series.
 // out[0..1] = mean (re, im), out[2] = gamma_0 (var), out[3] = sigma^2, out[4] = N_eff, out[5] = SE.

@@ -341,11 +341,34 @@ hipError_t launch_reduce_sum(const double* x, int64_t count, int comps, double* 
 // terms and sum S_c:  est = sum S_c / sum n_c,
 // Var = nc/(nc-1) sum_c (S_c - n_c est)^2 / (sum n_c)^2  (per real component).
 
-// Diagonal: one thread per position; groups gather their columns.
-__global__ __launch_bounds__(64) void k_finalize_diag(const FinalizeArgs f)
+// atomicMax of v >= 0 (double bits: non-negative doubles order like their
+// bit patterns) into base[idx] for the lanes with has set.  Called by all 64
+// lanes of a wave; when every such lane targets the same slot, the wave
+// reduces first and issues one atomic (rows of one matrix share a slot, so
+// per-lane atomics would serialise on it).
+__device__ inline void wave_atomic_max(unsigned long long* base, int64_t idx, bool has, double v)
 {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= f.M) return;
+    const int64_t idx0 = __shfl(idx, __builtin_ctzll(__ballot(has) | (1ull << 63)));
+    if (__all(!has || idx == idx0)) {
+        double m = has ? v : -1.0;
+        for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off));
+        if ((threadIdx.x & 63) == 0 && m >= 0.0) atomicMax(base + idx0, (unsigned long long)__double_as_longlong(m));
+    } else if (has) {
+        atomicMax(base + idx, (unsigned long long)__double_as_longlong(v));
+    }
+}
+
+__device__ inline double rel_error(double se, double er, double ei)
+{
+    double rel = se / sqrt(er * er + ei * ei);
+    if (!(rel >= 0.0) || !(rel < __builtin_inf())) rel = __builtin_inf();
+    return rel;
+}
+
+// Diagonal: one thread per position; groups gather their columns.  Returns
+// whether the position counts for max_rel, with its se/|est| in *rel.
+__device__ inline bool finalize_diag_row(const FinalizeArgs& f, int64_t q, double* rel)
+{
     const int64_t ncl = f.nslots * f.G;
     const int64_t cols_per_group = f.G > 1 ? f.gs / f.pairs_per_col : f.A;
     // Sums are formed on the fly per cluster (two passes).
@@ -373,8 +396,8 @@ __global__ __launch_bounds__(64) void k_finalize_diag(const FinalizeArgs f)
         f.est[out * f.comps] = __builtin_nan("");
         if (f.comps == 2) f.est[out * 2 + 1] = __builtin_nan("");
         f.se[out] = __builtin_nan("");
-        if (stop_row) atomicMax(f.max_rel, (unsigned long long)__double_as_longlong(__builtin_inf()));
-        return;
+        *rel = __builtin_inf();
+        return stop_row;
     }
     er /= wsum;
     ei /= wsum;
@@ -402,27 +425,31 @@ __global__ __launch_bounds__(64) void k_finalize_diag(const FinalizeArgs f)
     f.est[out * f.comps] = er;
     if (f.comps == 2) f.est[out * 2 + 1] = ei;
     f.se[out] = se;
-    if (stop_row) {
-        double rel = se / sqrt(er * er + ei * ei);
-        if (!(rel >= 0.0) || !(rel < __builtin_inf())) rel = __builtin_inf();
-        atomicMax(f.max_rel, (unsigned long long)__double_as_longlong(rel));
-    }
+    *rel = rel_error(se, er, ei);
+    return stop_row;
+}
+
+__global__ __launch_bounds__(64) void k_finalize_diag(const FinalizeArgs f)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double rel = 0.0;
+    const bool has = q < f.M && finalize_diag_row(f, q, &rel);
+    if (f.max_rel) wave_atomic_max(f.max_rel, 0, has, rel);
 }
 
 // Flat accumulators: value m of group g in slot b at
 // acc[b * slot_stride + (g * gstride + m * mstride) * comps]; one thread per value.
-__global__ __launch_bounds__(64) void k_finalize_flat(const FinalizeArgs f)
+__device__ inline void finalize_flat_value(const FinalizeArgs& f, int64_t m0, double* rel)
 {
-    const int64_t m0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (m0 >= f.M) return;
     const int64_t gstride = f.gstride > 0 ? f.gstride : f.M;
     const int64_t mstride = f.mstride > 0 ? f.mstride : 1;
     const int64_t ncl = f.nslots * f.G;
     const int64_t m = f.out_index ? f.out_index[m0] : m0;  // output index
+    const double* slot_len = f.slot_len;
     double wsum = 0.0, er = 0.0, ei = 0.0;
     int64_t nc = 0;
     for (int64_t c = 0; c < ncl; ++c) {
-        const double wt = f.slot_len[c / f.G] * (double)f.gs;
+        const double wt = slot_len[c / f.G] * (double)f.gs;
         if (wt <= 0.0) continue;
         const double* v = f.acc + (c / f.G) * f.slot_stride + ((c % f.G) * gstride + m0 * mstride) * f.comps;
         wsum += wt;
@@ -434,14 +461,14 @@ __global__ __launch_bounds__(64) void k_finalize_flat(const FinalizeArgs f)
         f.est[m * f.comps] = __builtin_nan("");
         if (f.comps == 2) f.est[m * 2 + 1] = __builtin_nan("");
         f.se[m] = __builtin_nan("");
-        if (f.max_rel) atomicMax(f.max_rel, (unsigned long long)__double_as_longlong(__builtin_inf()));
+        *rel = __builtin_inf();
         return;
     }
     er /= wsum;
     ei /= wsum;
     double vr = 0.0, vi = 0.0;
     for (int64_t c = 0; c < ncl; ++c) {
-        const double wt = f.slot_len[c / f.G] * (double)f.gs;
+        const double wt = slot_len[c / f.G] * (double)f.gs;
         if (wt <= 0.0) continue;
         const double* v = f.acc + (c / f.G) * f.slot_stride + ((c % f.G) * gstride + m0 * mstride) * f.comps;
         const double dr = v[0] - wt * er;
@@ -456,11 +483,124 @@ __global__ __launch_bounds__(64) void k_finalize_flat(const FinalizeArgs f)
     f.est[m * f.comps] = er;
     if (f.comps == 2) f.est[m * 2 + 1] = ei;
     f.se[m] = se;
-    if (f.max_rel != nullptr) {
-        double rel = se / sqrt(er * er + ei * ei);
-        if (!(rel >= 0.0) || !(rel < __builtin_inf())) rel = __builtin_inf();
-        atomicMax(f.max_rel, (unsigned long long)__double_as_longlong(rel));
+    *rel = rel_error(se, er, ei);
+}
+
+__global__ __launch_bounds__(64) void k_finalize_flat(const FinalizeArgs f)
+{
+    const int64_t m0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool has = m0 < f.M;
+    double rel = 0.0;
+    if (has) finalize_flat_value(f, m0, &rel);
+    if (f.max_rel) wave_atomic_max(f.max_rel, 0, has, rel);
+}
+
+// Flat accumulators laid out [nslots][M][G] with G a power of two <= 64
+// (gstride 1, mstride G): a wave takes 64/G values, lane = (value, group), so
+// every load is coalesced and a value's sums are butterfly reductions over its
+// G lanes.  Same estimator as k_finalize_flat (sums in another order).
+__global__ __launch_bounds__(256) void k_finalize_groups(const FinalizeArgs f)
+{
+    const int G = (int)f.G;
+    const int lg = __builtin_ctz((unsigned)G);
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t v = t >> lg;
+    const int g = (int)(t & (G - 1));
+    const bool ok = v < f.M;
+    const int64_t grp = ok && f.val_group ? f.val_group[v] : 0;
+    const double* slot_len = f.slot_len + grp * f.slot_len_stride;
+    double wsum = 0.0, er = 0.0, ei = 0.0, nc = 0.0;
+    if (ok)
+        for (int64_t b = 0; b < f.nslots; ++b) {
+            const double wt = slot_len[b] * (double)f.gs;
+            if (wt <= 0.0) continue;
+            const double* x = f.acc + b * f.slot_stride + (v * G + g) * f.comps;
+            wsum += wt;
+            er += x[0];
+            if (f.comps == 2) ei += x[1];
+            nc += 1.0;
+        }
+    for (int off = 1; off < G; off <<= 1) {
+        wsum += __shfl_xor(wsum, off);
+        er += __shfl_xor(er, off);
+        ei += __shfl_xor(ei, off);
+        nc += __shfl_xor(nc, off);
     }
+    double vr = 0.0, vi = 0.0;
+    if (ok && wsum > 0.0) {
+        const double mr = er / wsum, mi = ei / wsum;
+        for (int64_t b = 0; b < f.nslots; ++b) {
+            const double wt = slot_len[b] * (double)f.gs;
+            if (wt <= 0.0) continue;
+            const double* x = f.acc + b * f.slot_stride + (v * G + g) * f.comps;
+            const double dr = x[0] - wt * mr;
+            vr += dr * dr;
+            if (f.comps == 2) {
+                const double di = x[1] - wt * mi;
+                vi += di * di;
+            }
+        }
+    }
+    for (int off = 1; off < G; off <<= 1) {
+        vr += __shfl_xor(vr, off);
+        vi += __shfl_xor(vi, off);
+    }
+    const bool has = ok && g == 0;
+    double rel = 0.0;
+    if (has) {
+        const int64_t m = f.out_index ? f.out_index[v] : v;
+        if (wsum <= 0.0) {
+            f.est[m * f.comps] = __builtin_nan("");
+            if (f.comps == 2) f.est[m * 2 + 1] = __builtin_nan("");
+            f.se[m] = __builtin_nan("");
+            rel = __builtin_inf();
+        } else {
+            const double mr = er / wsum, mi = ei / wsum;
+            double se = __builtin_nan("");
+            if (nc >= 2.0) se = sqrt((vr + vi) * (nc / (nc - 1.0))) / wsum;
+            f.est[m * f.comps] = mr;
+            if (f.comps == 2) f.est[m * 2 + 1] = mi;
+            f.se[m] = se;
+            rel = rel_error(se, mr, mi);
+        }
+    }
+    if (has && f.rel_out) f.rel_out[v] = rel;
+}
+
+// out[s] = max of x[begin[s] .. begin[s+1]) (values >= 0, NaN taken as +inf;
+// 0 for an empty segment); one workgroup per segment, no atomics.
+__global__ __launch_bounds__(256) void k_segment_max(const double* x, const int64_t* begin, double* out)
+{
+    __shared__ double lds[256];
+    const int64_t seg = blockIdx.x;
+    double m = 0.0;
+    for (int64_t i = begin[seg] + threadIdx.x; i < begin[seg + 1]; i += 256) {
+        const double v = x[i];
+        m = fmax(m, v <= __builtin_inf() ? v : __builtin_inf());
+    }
+    lds[threadIdx.x] = m;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) lds[threadIdx.x] = fmax(lds[threadIdx.x], lds[threadIdx.x + st]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[seg] = lds[0];
+}
+
+hipError_t launch_segment_max(const double* x, const int64_t* begin, int64_t nseg, double* out, hipStream_t stream)
+{
+    if (nseg <= 0) return hipSuccess;
+    k_segment_max<<<dim3((unsigned)nseg), dim3(256), 0, stream>>>(x, begin, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize_groups(const FinalizeArgs& f, hipStream_t stream)
+{
+    if (f.M <= 0) return hipSuccess;
+    if (f.G < 1 || f.G > 64 || (f.G & (f.G - 1)) != 0) return hipErrorInvalidValue;
+    const int64_t threads = f.M * f.G;
+    k_finalize_groups<<<dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, stream>>>(f);
+    return hipGetLastError();
 }
 
 hipError_t launch_finalize_diag(const FinalizeArgs& f, hipStream_t stream)

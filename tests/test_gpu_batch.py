@@ -136,6 +136,54 @@ def test_autotune_and_sample_until(mats):
             assert np.array_equal(b.state(2, 0), s.state(0))
 
 
+@pytest.mark.parametrize("schedule", [0, 1])
+def test_per_matrix_stop_equals_single_path(mats, schedule):
+    """sample_until_each: every matrix stops at the first check where its own
+    max SE/|est| meets the tolerance, exactly where the single path's
+    sample_until stops it (same burn-in, seed and stream), with bit-identical
+    chains and estimates; stopped matrices are frozen while the rest go on, and
+    a new request makes every matrix active again."""
+    print_case(test="batch_each", schedule=schedule)
+    P, G, seed, rel, burn, bd = 64, 16, 77, 0.04, 20, 16
+    sub = mats[:6]
+    with mc.BatchSampler(sub, pairs=P, groups=G, seed=seed, schedule=schedule) as b:
+        b.burn_in(burn)
+        b.request(diag=True, block_dim=bd, expected_samples=400)
+        done, ach = b.sample_until_each(rel, 2000, 10)
+        samples, active = b.matrix_samples()
+        assert not active.any() and ach <= rel
+        assert done == samples.max() and len(set(samples.tolist())) >= 2, samples
+        for m in range(len(sub)):
+            with mc.Sampler(sub[m], pairs=P, groups=G, dtype="f32", seed=seed, stream_id=m) as s:
+                s.burn_in(burn)
+                s.request(diag=True, trace=False)
+                dj, aj = s.sample_until(rel, 2000, 10)
+                assert dj == samples[m], (m, dj, samples[m])
+                d, se = s.diag()
+                assert np.array_equal(b.state(m, 0), s.state(0))
+                assert np.array_equal(b.state(m, 1), s.state(1))
+            bd_, bse = b.diag(m)
+            np.testing.assert_allclose(bd_, d, rtol=1e-12, atol=0)
+            np.testing.assert_allclose(bse, se, rtol=1e-9)
+        # block moments of the first matrix to stop: its own sample count
+        m = int(np.argmin(samples))
+        n = sub[m].n
+        rows = np.arange(n - bd, n)
+        with mc.Sampler(sub[m], pairs=P, groups=1, dtype="f32", seed=seed, stream_id=m, moments="bf16x3") as s1:
+            s1.burn_in(burn)
+            s1.request(diag=False, trace=False, block_rows=rows, block_cols=rows)
+            s1.sample(int(samples[m]))
+            sb, _ = s1.block()
+        bb, _ = b.block(m)
+        np.testing.assert_allclose(bb, sb, rtol=1e-12, atol=1e-15)
+        # every matrix active again after a new request
+        b.request(diag=True)
+        samples2, active2 = b.matrix_samples()
+        assert active2.all() and not samples2.any()
+        b.sample(2)
+        assert b.matrix_samples()[0].tolist() == [2] * len(sub)
+
+
 def test_batch_errors(mats):
     with pytest.raises(mc.McinvError) as ei:
         mc.mcinv_batch_create(2, n_pairs=48)
