@@ -809,15 +809,17 @@ mcinv_status mcinv_tune_launch(mcinv_ctx* c, int32_t sweeps_per_trial, int32_t* 
     mcinv_status s = MCINV_OK;
     for (int order = 0; order < 3 && s == MCINV_OK; ++order) {
         c->cfg.xcd_order = order;
+        // every sweep draws its own noise (counter = sweep index), as in burn-in
         if ((s = dispatch_sweeps(c, 1, false)) != MCINV_OK) break;
+        c->sweeps += 1;
         if (hipEventRecord(e0, c->stream) != hipSuccess) s = fail(c, MCINV_EDEVICE, "hipEventRecord failed");
         if (s == MCINV_OK) s = dispatch_sweeps(c, sweeps_per_trial, false);
+        if (s == MCINV_OK) c->sweeps += sweeps_per_trial;
         float t = 0.f;
         if (s == MCINV_OK && (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                               hipEventElapsedTime(&t, e0, e1) != hipSuccess))
             s = fail(c, MCINV_EDEVICE, "timing the launch orders failed");
         ms[order] = (double)t / sweeps_per_trial;
-        c->sweeps += 1 + sweeps_per_trial;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

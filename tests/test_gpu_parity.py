@@ -353,23 +353,51 @@ def test_hermitian_mode_rejects_non_hermitian():
         assert ei.value.code == mc.MCINV_EINVAL
 
 
-@pytest.mark.parametrize("dtype,maker", [("f32", lambda: gen.pedigree(5000, seed=95)),
-                                         ("c64", lambda: gen.lattice(8, k=0.12, seed=96))])
-def test_xcd_order_does_not_change_results(dtype, maker):
-    """Workgroup orders only remap which workgroup sweeps which rows."""
+@pytest.mark.parametrize("dtype,maker,P,G", [
+    ("f32", lambda: gen.pedigree(5000, seed=95), 768, 3),
+    ("c64", lambda: gen.lattice(8, k=0.12, seed=96), 768, 3),
+    ("f64", lambda: gen.pedigree(3001, seed=98), 100, 1),     # ragged last tile
+    ("f32", lambda: gen.pedigree(2003, seed=99), 1024, 16),   # groups of 64 pairs
+])
+def test_workgroup_orders_do_not_change_results(dtype, maker, P, G):
+    """Workgroup orders only remap which workgroup sweeps which rows: chains
+    and moments are bit-identical."""
+    print_case(test="launch_orders", dtype=dtype, P=P, G=G)
     m = oracle_matrix(maker(), dtype)
-    with _sampler(m, dtype, 3, 768, 3) as a, _sampler(m, dtype, 3, 768, 3, xcd_order=1) as b, \
-            _sampler(m, dtype, 3, 768, 3, xcd_order=2) as c:
-        for s in (a, b, c):
-            s.burn_in(3)
-            s.request(diag=True, trace=True)
-            s.sample(4)
-        for s in (b, c):
-            assert np.array_equal(a.state(0), s.state(0)) and np.array_equal(a.state(1), s.state(1))
-            assert np.array_equal(a.diag()[0], s.diag()[0])
-        order, ms = b.tune_launch(1)
+    layouts = [dict(xcd_order=1), dict(xcd_order=2)]
+    with _sampler(m, dtype, 3, P, G) as a:
+        a.burn_in(3)
+        a.request(diag=True, trace=True)
+        a.sample(4)
+        d0, se0 = a.diag()
+        t0, _ = a.trace()
+        for kw in layouts:
+            with _sampler(m, dtype, 3, P, G, **kw) as s:
+                s.burn_in(3)
+                s.request(diag=True, trace=True)
+                s.sample(4)
+                assert np.array_equal(a.state(0), s.state(0)) and np.array_equal(a.state(1), s.state(1)), kw
+                d, se = s.diag()
+                assert np.array_equal(d0, d) and np.array_equal(se0, se, equal_nan=True), kw
+                t, _ = s.trace()
+                np.testing.assert_allclose(np.asarray(t), np.asarray(t0), rtol=1e-12)
+
+
+def test_tune_launch_picks_the_fastest_order():
+    """The tuner's sweeps are ordinary burn-in sweeps, each with its own noise."""
+    m = oracle_matrix(gen.lattice(8, k=0.12, seed=96), "c64")
+    with _sampler(m, "c64", 3, 512, 8) as s:
+        order, ms = s.tune_launch(1)
         assert order in (0, 1, 2) and np.all(ms > 0) and ms[order] == ms.min()
-        assert b.info()["sweeps_done"] == 7 + 6
+        assert s.info()["sweeps_done"] == 3 * 2
+        s.request(diag=True, trace=True)
+        s.sample(2)
+        with _sampler(m, "c64", 3, 512, 8) as r:
+            r.burn_in(3 * 2)
+            r.request(diag=True, trace=True)
+            r.sample(2)
+            assert np.array_equal(r.state(0), s.state(0)) and np.array_equal(r.state(1), s.state(1))
+            assert np.array_equal(r.diag()[0], s.diag()[0])
 
 
 def test_stop_rows_restrict_the_stop_check():
