@@ -73,6 +73,8 @@ STATE_CASES = [
     ("lattice4", "c128", 68, [1, 3, 20]),
     ("diag", "f64", 5, [1, 2]),
     ("cdiag", "c128", 5, [1, 2]),
+    ("hub2500", "f32", 260, [1, 4, 15]),   # one merged row of ~2500 entries
+    ("hub2500", "f64", 64, [1, 4]),
 ]
 
 
@@ -87,6 +89,24 @@ def _matrix(name):
         return gen.diag_matrix(np.array([2.0, -3.0, 0.5, 7.0, -0.25]))
     if name == "cdiag":
         return gen.diag_matrix(np.array([2.0, -3.0, 0.5 + 1j, -1 - 2j, 1j]))
+    if name == "hub2500":
+        # row 0 couples to every row, column 0 to half of them, plus two random
+        # entries per row; diagonal 1.5 x the off-diagonal absolute row sum
+        import scipy.sparse as sps
+        rng = np.random.default_rng(21)
+        n = 2500
+        half = np.arange(1, n)[rng.random(n - 1) < 0.5]
+        rows = np.concatenate([np.zeros(n - 1, np.int64), half, np.repeat(np.arange(n), 2)])
+        cols = np.concatenate([np.arange(1, n), np.zeros(half.size, np.int64), rng.integers(0, n, 2 * n)])
+        keep = rows != cols
+        rows, cols = rows[keep], cols[keep]
+        off = sps.coo_matrix((rng.uniform(-1, 1, rows.size), (rows, cols)), shape=(n, n)).tocsr()
+        off.sum_duplicates()
+        d = 1.5 * np.asarray(abs(off).sum(axis=1)).ravel()
+        A = (off + sps.diags(np.where(d > 0, d, 1.0))).tocsr()
+        A.sort_indices()
+        return gen.CSR(n=n, row_ptr=A.indptr.astype(np.int64), col=A.indices.astype(np.int32),
+                       val=np.ascontiguousarray(A.data))
     raise KeyError(name)
 
 
