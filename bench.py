@@ -105,10 +105,28 @@ def time_to_1pct(pkg, torch, m, P, G, seed, dtype, moments, burn_in, rel=0.01, c
     done, ach = s.sample_until(rel, max_sweeps, check)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
-    s.close()
-    return {"seconds": t, "setup_seconds": t_setup, "burn_in": nb, "burn_in_rule": burn_desc,
-            "sample_sweeps": done, "max_rel_se": ach, "form": f"{dtype} sweeps, {moments} blocks",
-            "xcd_order": ORDER_NAMES[xcd_order]}
+    out = {"seconds": t, "setup_seconds": t_setup, "burn_in": nb, "burn_in_rule": burn_desc,
+           "sample_sweeps": done, "max_rel_se": ach, "form": f"{dtype} sweeps, {moments} blocks",
+           "xcd_order": ORDER_NAMES[xcd_order]}
+    if dtype == "f32":
+        # the same chains in fp64 (same matrix values, noise, burn-in and sample
+        # sweeps; the fp64 path is the one tested against the oracle to 1e-12):
+        # how far the fp32 sweeps move the estimates, next to their SE
+        est, se = s.diag()
+        s.close()
+        with pkg.Sampler(m, pairs=P, groups=G, dtype="f64", seed=seed, use_torch_stream=True,
+                         hermitian=hermitian, xcd_order=xcd_order) as r:
+            r.burn_in(nb)
+            r.request(diag=True, trace=False)
+            r.sample(done)
+            ref, _ = r.diag()
+        err = np.abs(np.asarray(est) - np.asarray(ref))
+        out["vs_fp64_same_noise"] = {"max_abs": float(err.max()),
+                                     "max_rel": float((err / np.abs(ref)).max()),
+                                     "max_over_se": float((err / np.asarray(se)).max())}
+    else:
+        s.close()
+    return out
 
 
 def batched_forms(pkg, torch, gen, rel=0.01, check=10):
