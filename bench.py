@@ -466,8 +466,8 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the chain pairs would "
-              "split across GPUs with one fp64 all-reduce of the moment sums, which this "
-              "build does not implement.", file=sys.stderr)
+              "split across GPUs with one fp64 all-reduce of the moment sums, which the "
+              "library does not implement.", file=sys.stderr)
         sys.exit(2)
 
     import torch
