@@ -1,0 +1,115 @@
+"""Statistical checks of the GPU estimator against exact inverses, at working
+sizes: the estimates of eq (1/C) and eq (tr) must be unbiased and their
+reported standard errors calibrated (the check of Sec. 3.1, which compares the
+spread over independent replicates with the reported SEs).  The oracle pins the
+same properties on the CPU at small sizes; here the library's own cluster and
+Geyer SEs are checked on its own runs."""
+
+import numpy as np
+import pytest
+
+import gen
+from gpu_util import oracle_matrix, print_case
+
+pytestmark = pytest.mark.gpu
+
+mc = pytest.importorskip("paper_cs_0412107_amd")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _exact_inverse(m):
+    return np.linalg.inv(gen.to_dense(m))
+
+
+@pytest.mark.parametrize("dtype,noise", [("f32", mc.MCINV_NOISE_NORMAL), ("f32", mc.MCINV_NOISE_RADEMACHER),
+                                         ("f64", mc.MCINV_NOISE_NORMAL)])
+def test_diagonal_zscores_against_exact_inverse(dtype, noise):
+    """Pedigree n = 1500, 2048 pairs in 64 groups, 400 samples: z = (est -
+    exact) / SE over all rows has mean ~0 (rows share chains, so their errors
+    are correlated and the mean scatters by a few hundredths) and standard
+    deviation ~1 (t with 63 degrees of freedom: sd 1.016), and no outlier
+    beyond 5.5.  The trace is checked against its Geyer SE, which needs a
+    long enough series (at 60 samples it ran ~1.6x small over 8 seeds; at
+    600, ~1.1x)."""
+    print_case(test="diag_zscores", dtype=dtype, noise=noise)
+    m = oracle_matrix(gen.pedigree(1500, seed=501), dtype)
+    exact = np.diag(_exact_inverse(m))
+    with mc.Sampler(m, pairs=2048, groups=64, dtype=dtype, seed=0x5EED + noise, noise=noise) as s:
+        s.burn_in_coupled(5e-5, 2000)
+        s.request(diag=True, trace=True)
+        s.sample(400)
+        est, se = s.diag()
+        tr, tr_se = s.trace()
+    est, se = np.asarray(est), np.asarray(se)
+    live = se > 0   # Z2 noise makes rows without off-diagonal entries exact
+    if noise == mc.MCINV_NOISE_RADEMACHER:
+        assert np.allclose(est[~live], exact[~live], rtol=1e-6)
+    z = (est[live] - exact[live]) / se[live]
+    print(f"z: mean {z.mean():.4f} sd {z.std():.4f} max {np.abs(z).max():.2f} over {z.size} rows; "
+          f"trace {(tr - exact.sum()) / tr_se:.2f} SE", flush=True)
+    assert abs(z.mean()) < 0.12, z.mean()
+    assert 0.9 < z.std() < 1.12, z.std()
+    assert np.abs(z).max() < 5.5, np.abs(z).max()
+    # trace against the exact trace, within its Geyer SE
+    assert abs(tr - exact.sum()) < 5 * tr_se, (tr, exact.sum(), tr_se)
+
+
+def test_complex_diagonal_zscores_against_exact_inverse():
+    """Random-phase lattice 6^4 (complex, non-hermitian), 1024 pairs in 32
+    groups: |est - exact|^2 / SE^2 averages ~1 (SE combines the real and
+    imaginary parts)."""
+    print_case(test="diag_zscores_complex")
+    m = oracle_matrix(gen.lattice(6, k=0.12, seed=502), "c64")
+    exact = np.diag(_exact_inverse(m))
+    with mc.Sampler(m, pairs=1024, groups=32, dtype="c64", seed=77) as s:
+        s.burn_in_coupled(5e-5, 2000)
+        s.request(diag=True, trace=True)
+        s.sample(80)
+        est, se = s.diag()
+        tr, tr_se = s.trace()
+    r2 = np.abs(np.asarray(est) - exact) ** 2 / np.asarray(se) ** 2
+    print(f"r2: mean {r2.mean():.4f} max {np.sqrt(r2.max()):.2f}; trace {abs(tr - exact.sum()) / tr_se:.2f} SE",
+          flush=True)
+    assert 0.85 < r2.mean() < 1.15, r2.mean()
+    assert np.sqrt(r2.max()) < 5.5
+    assert abs(tr - exact.sum()) < 5 * tr_se, (tr, exact.sum(), tr_se)
+
+
+def test_se_calibration_over_replicates():
+    """Sec. 3.1's check: 48 independent replicates (seeds) of a small run; the
+    spread of the estimates over the replicates matches the mean reported SE,
+    for a few diagonal entries (chain-group SE) and for the trace (Geyer SE
+    over the per-sweep series with one group)."""
+    print_case(test="se_calibration")
+    m = oracle_matrix(gen.pedigree(400, seed=503), "f32")
+    rows = [0, 57, 199, 399]
+    R = 48
+    d_est, d_se, t_est, t_se = [], [], [], []
+    for r in range(R):
+        with mc.Sampler(m, pairs=64, groups=16, dtype="f32", seed=1000 + r) as s:
+            s.burn_in(60)
+            s.request(diag=True, trace=False)
+            s.sample(100)
+            e, se = s.diag()
+            d_est.append(np.asarray(e)[rows])
+            d_se.append(np.asarray(se)[rows])
+        with mc.Sampler(m, pairs=8, groups=1, dtype="f32", seed=5000 + r) as s:
+            s.burn_in(60)
+            s.request(diag=False, trace=True)
+            s.sample(400)
+            e, se = s.trace()
+            t_est.append(e)
+            t_se.append(se)
+    ratio_d = np.std(d_est, axis=0, ddof=1) / np.mean(d_se, axis=0)
+    ratio_t = np.std(t_est, ddof=1) / np.mean(t_se)
+    print(f"sd / mean SE: diagonal {np.round(ratio_d, 3)}, trace {ratio_t:.3f}", flush=True)
+    # sd of an sd estimate from 48 replicates: ~10%; four entries
+    assert np.all((ratio_d > 0.7) & (ratio_d < 1.35)), ratio_d
+    assert 0.8 < ratio_d.mean() < 1.2, ratio_d
+    assert 0.7 < ratio_t < 1.35, ratio_t
