@@ -168,7 +168,9 @@ mcinv_status mcinv_sample_until(mcinv_ctx* ctx, double rel_se, int64_t max_sweep
 /* Sample in chunks of check_every sweeps until the trace estimate's standard
  * error (Geyer's initial positive sequence on the per-sweep series, Sec. 2.3)
  * relative to |estimate| is <= rel_se, or max_sweeps -- the stopping rule of
- * the paper's numerical tests.  Needs MCINV_REQ_TRACE. */
+ * the paper's numerical tests, which ran long series.  The error is trusted
+ * only once the series holds at least 50 effective samples (S gamma_0 /
+ * sigma^2; a shorter series gives too small an error).  Needs MCINV_REQ_TRACE. */
 mcinv_status mcinv_sample_until_trace(mcinv_ctx* ctx, double rel_se, int64_t max_sweeps, int64_t check_every,
                                       int64_t* sweeps_done, double* achieved);
 

@@ -874,6 +874,7 @@ mcinv_status mcinv_sample_until(mcinv_ctx* c, double rel_se, int64_t max_sweeps,
 mcinv_status mcinv_sample_until_trace(mcinv_ctx* c, double rel_se, int64_t max_sweeps, int64_t check_every,
                                       int64_t* sweeps_done, double* achieved)
 {
+    constexpr double kMinEffectiveSamples = 50.0;
     MC_TRY(check_ready(c));
     if (!c->requested || !(c->flags & (MCINV_REQ_TRACE | MCINV_REQ_QTRACE)))
         return fail(c, MCINV_ESTATE, "sample_until_trace needs MCINV_REQ_TRACE or MCINV_REQ_QTRACE requested");
@@ -895,7 +896,10 @@ mcinv_status mcinv_sample_until_trace(mcinv_ctx* c, double rel_se, int64_t max_s
         const double mag = std::sqrt(g[0] * g[0] + (c->comps == 2 ? g[1] * g[1] : 0.0));
         rel = g[5] / mag;
         if (!(rel >= 0.0)) rel = INFINITY;
-        if (rel <= rel_se) break;
+        // Geyer's SE is trusted only on a series of at least kMinEffectiveSamples
+        // effective samples (N_eff = S gamma_0 / sigma^2): shorter series give
+        // too small an error (the truncated autocovariance sum is short)
+        if (rel <= rel_se && (g[4] >= kMinEffectiveSamples || !(g[3] > 0.0))) break;  // sigma^2 = 0: exact
     }
     if (sweeps_done) *sweeps_done = done;
     if (achieved) *achieved = rel;

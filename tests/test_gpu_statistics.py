@@ -113,3 +113,19 @@ def test_se_calibration_over_replicates():
     assert np.all((ratio_d > 0.7) & (ratio_d < 1.35)), ratio_d
     assert 0.8 < ratio_d.mean() < 1.2, ratio_d
     assert 0.7 < ratio_t < 1.35, ratio_t
+
+
+def test_trace_stop_waits_for_a_long_enough_series():
+    """The Geyer stop accepts a relative SE only on a series of at least 50
+    effective samples: with a loose tolerance that 10 samples already meet,
+    sampling still runs until the series is long enough."""
+    print_case(test="trace_stop_min_series")
+    m = oracle_matrix(gen.pedigree(3000, seed=504), "f32")
+    with mc.Sampler(m, pairs=4096, groups=64, dtype="f32", seed=9) as s:
+        s.burn_in(40)
+        s.request(diag=False, trace=True)
+        s.sample(10)
+        t, tse = s.trace()
+        assert tse / abs(t) < 0.05          # the tolerance is met after 10 samples
+        done, ach = s.sample_until_trace(0.05, 1000, 10)
+        assert ach <= 0.05 and 40 <= done < 1000, done
