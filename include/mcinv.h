@@ -160,8 +160,10 @@ mcinv_status mcinv_sample(mcinv_ctx* ctx, int64_t sweeps);
 
 /* Sample in chunks of check_every sweeps until the largest relative standard
  * error max_i SE_i/|est_i| over the diagonal is <= rel_se, or max_sweeps were
- * run.  Needs MCINV_REQ_DIAG.  *sweeps_done (may be NULL) receives the count,
- * *achieved (may be NULL) the last max relative SE. */
+ * run.  With n_groups < 16 the error clusters are time batches, and the stop
+ * waits until a batch spans at least 16 sweeps (more than 512 samples) so that
+ * batches are close to independent.  Needs MCINV_REQ_DIAG.  *sweeps_done (may
+ * be NULL) receives the count, *achieved (may be NULL) the last max relative SE. */
 mcinv_status mcinv_sample_until(mcinv_ctx* ctx, double rel_se, int64_t max_sweeps,
                                 int64_t check_every, int64_t* sweeps_done, double* achieved);
 

@@ -847,6 +847,7 @@ mcinv_status mcinv_sample(mcinv_ctx* c, int64_t sweeps)
 mcinv_status mcinv_sample_until(mcinv_ctx* c, double rel_se, int64_t max_sweeps, int64_t check_every,
                                 int64_t* sweeps_done, double* achieved)
 {
+    constexpr int64_t kMinBatchLen = 16;
     MC_TRY(check_ready(c));
     if (!c->requested || !(c->flags & MCINV_REQ_DIAG))
         return fail(c, MCINV_ESTATE, "sample_until needs MCINV_REQ_DIAG requested");
@@ -864,7 +865,10 @@ mcinv_status mcinv_sample_until(mcinv_ctx* c, double rel_se, int64_t max_sweeps,
         HIP_TRY(c, hipStreamSynchronize(c->stream));
         std::memcpy(&maxrel, &bits, sizeof(double));
         MC_TRY(check_flag(c));
-        if (maxrel <= rel_se) break;
+        // with fewer than 16 groups the SE clusters include time batches, which
+        // must be long against the chains' autocorrelation to be independent
+        const bool batches_ok = c->nslots == 1 || c->batch_len >= kMinBatchLen;
+        if (maxrel <= rel_se && batches_ok) break;
     }
     if (sweeps_done) *sweeps_done = done;
     if (achieved) *achieved = maxrel;

@@ -129,3 +129,16 @@ def test_trace_stop_waits_for_a_long_enough_series():
         assert tse / abs(t) < 0.05          # the tolerance is met after 10 samples
         done, ach = s.sample_until_trace(0.05, 1000, 10)
         assert ach <= 0.05 and 40 <= done < 1000, done
+
+
+def test_diag_stop_with_time_batches_waits_for_long_batches():
+    """With fewer than 16 chain groups the SE clusters are time batches; the
+    stop accepts them only once a batch spans 16 sweeps (more than 512
+    samples), even when a loose tolerance is met much earlier."""
+    print_case(test="diag_stop_time_batches")
+    m = oracle_matrix(gen.pedigree(300, seed=505), "f32")
+    with mc.Sampler(m, pairs=8, groups=1, dtype="f32", seed=10) as s:
+        s.burn_in(40)
+        s.request(diag=True, trace=False)
+        done, ach = s.sample_until(0.5, 5000, 10)
+        assert 512 < done <= 520 and ach <= 0.5, (done, ach)
