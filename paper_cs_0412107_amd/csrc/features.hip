@@ -8,7 +8,9 @@
 // output.  fp64 arithmetic, one thread per row, fp32 output.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -108,8 +110,7 @@ __device__ inline void stats(double v, double& s1, double& s2, double& mx, doubl
 }
 
 __global__ __launch_bounds__(256) void k_features_pass2(int64_t n, const int64_t* beg, const int32_t* cnt,
-                                                        const FEnt* ent, double* F, const int64_t* out_row,
-                                                        float* out)
+                                                        const FEnt* ent, double* F, float* out)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -158,7 +159,7 @@ __global__ __launch_bounds__(256) void k_features_pass2(int64_t n, const int64_t
         for (int k = 11; k <= 23; ++k) o[k] = 0.0;
     }
     o[30] = r2 / 8.0;
-    float* dst = out + out_row[i] * kNF;
+    float* dst = out + i * kNF;
     for (int k = 0; k < kNF; ++k) dst[k] = (float)o[k];
 }
 
@@ -173,34 +174,56 @@ extern "C" mcinv_status mcinv_features(int32_t device, int64_t n, int64_t nnz, c
         set_context_free_error("mcinv_features: null output");
         return MCINV_EINVAL;
     }
-    Prepared h;
+    std::vector<cd> diag;
     bool singular = false;
-    const std::string why = prepare_matrix(n, nnz, row_ptr, col_idx, values, false, h, &singular);
+    const std::string why = validate_csr(n, nnz, row_ptr, col_idx, values, false, diag, &singular);
     if (!why.empty()) {
         set_context_free_error("mcinv_features: " + why);
         return singular ? MCINV_ESINGULAR : MCINV_EINVAL;
     }
-    std::vector<int64_t> beg(n);
-    std::vector<int32_t> cnt(n);
-    std::vector<FEnt> ent(h.ent.size());
-    std::vector<double> d(n);
-    for (int64_t q = 0; q < n; ++q) {
-        beg[q] = h.rows[q].begin;
-        cnt[q] = h.rows[q].count;
-        d[q] = h.diag[q].real();
-        for (int64_t t = h.rows[q].begin; t < h.rows[q].begin + h.rows[q].count; ++t) {
-            // the merged entry stores u = c_ij / c_ii and v = c_ji / c_ii (real C)
-            ent[t].col = (int32_t)h.ent[t].col;
-            ent[t].pad = 0;
-            ent[t].cij = h.ent[t].u.real() * d[q];
-            ent[t].cji = h.ent[t].v.real() * d[q];
+    // Each row's neighbours: the union of row i and column i of C in natural
+    // order (no colouring is needed here), with c_ij and c_ji.
+    std::vector<int64_t> tptr, tsrc;
+    std::vector<int32_t> trow;
+    transpose_csr(n, nnz, row_ptr, col_idx, tptr, trow, tsrc);
+    auto merge_row = [&](int64_t i, auto&& emit) {
+        int64_t e = row_ptr[i], t = tptr[i];
+        const int64_t e_end = row_ptr[i + 1], t_end = tptr[i + 1];
+        while (e < e_end || t < t_end) {
+            const int64_t je = e < e_end ? col_idx[e] : INT64_MAX;
+            const int64_t jt = t < t_end ? trow[t] : INT64_MAX;
+            const int64_t j = std::min(je, jt);
+            const bool has_e = je == j, has_t = jt == j;
+            if (j != i) emit(j, has_e ? values[e] : 0.0, has_t ? values[tsrc[t]] : 0.0);
+            e += has_e ? 1 : 0;
+            t += has_t ? 1 : 0;
         }
-    }
+    };
+    std::vector<int32_t> cnt(n);
+    parallel_for(n, [&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i) {
+            int32_t k = 0;
+            merge_row(i, [&](int64_t, double, double) { ++k; });
+            cnt[i] = k;
+        }
+    });
+    std::vector<int64_t> beg(n + 1, 0);
+    for (int64_t i = 0; i < n; ++i) beg[i + 1] = beg[i] + cnt[i];
+    const int64_t nent = beg[n];
+    std::unique_ptr<FEnt[]> ent(new FEnt[(size_t)std::max<int64_t>(nent, 1)]);   // filled below, not zeroed
+    std::vector<double> d(n);
+    parallel_for(n, [&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i) {
+            FEnt* out_e = ent.get() + beg[i];
+            merge_row(i, [&](int64_t j, double cij, double cji) { *out_e++ = FEnt{(int32_t)j, 0, cij, cji}; });
+            d[i] = diag[i].real();
+        }
+    });
     if (hipSetDevice(device) != hipSuccess) {
         set_context_free_error("mcinv_features: no such device");
         return MCINV_EDEVICE;
     }
-    int64_t *d_beg = nullptr, *d_row = nullptr;
+    int64_t* d_beg = nullptr;
     int32_t* d_cnt = nullptr;
     FEnt* d_ent = nullptr;
     double *d_d = nullptr, *d_F = nullptr;
@@ -210,17 +233,15 @@ extern "C" mcinv_status mcinv_features(int32_t device, int64_t n, int64_t nnz, c
         if (e == hipSuccess) e = hipMalloc(p, bytes > 0 ? bytes : 1);
     };
     alloc((void**)&d_beg, sizeof(int64_t) * n);
-    alloc((void**)&d_row, sizeof(int64_t) * n);
     alloc((void**)&d_cnt, sizeof(int32_t) * n);
-    alloc((void**)&d_ent, sizeof(FEnt) * ent.size());
+    alloc((void**)&d_ent, sizeof(FEnt) * (size_t)nent);
     alloc((void**)&d_d, sizeof(double) * n);
     alloc((void**)&d_F, sizeof(double) * n * kNF);
     alloc((void**)&d_out, sizeof(float) * n * kNF);
     if (e == hipSuccess) e = hipMemcpy(d_beg, beg.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(d_row, h.perm.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d_cnt, cnt.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice);
-    if (e == hipSuccess && !ent.empty())
-        e = hipMemcpy(d_ent, ent.data(), sizeof(FEnt) * ent.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && nent > 0)
+        e = hipMemcpy(d_ent, ent.get(), sizeof(FEnt) * (size_t)nent, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d_d, d.data(), sizeof(double) * n, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(d_F, 0, sizeof(double) * n * kNF);
     const unsigned blocks = (unsigned)((n + 255) / 256);
@@ -229,12 +250,11 @@ extern "C" mcinv_status mcinv_features(int32_t device, int64_t n, int64_t nnz, c
         e = hipGetLastError();
     }
     if (e == hipSuccess) {
-        k_features_pass2<<<blocks, 256>>>(n, d_beg, d_cnt, d_ent, d_F, d_row, d_out);
+        k_features_pass2<<<blocks, 256>>>(n, d_beg, d_cnt, d_ent, d_F, d_out);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipMemcpy(out, d_out, sizeof(float) * n * kNF, hipMemcpyDeviceToHost);
     (void)hipFree(d_beg);
-    (void)hipFree(d_row);
     (void)hipFree(d_cnt);
     (void)hipFree(d_ent);
     (void)hipFree(d_d);

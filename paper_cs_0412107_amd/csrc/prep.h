@@ -60,89 +60,119 @@ inline void parallel_for(int64_t n, F&& f)
     for (std::thread& x : th) x.join();
 }
 
+// Validation of a CSR matrix: sorted, duplicate-free, in-range columns and a
+// nonzero diagonal in every row, which is returned in diag.  Rows are checked
+// in parallel ranges; the reported failure is the lowest row's pattern error,
+// else the lowest row without a diagonal.  Returns an empty string on success, else the
+// reason; *singular is set when the failure is a missing or zero diagonal.
+inline std::string validate_csr(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
+                                const double* vd, bool complex_values, std::vector<cd>& diag, bool* singular)
+{
+    *singular = false;
+    if (n < 1 || n > INT32_MAX || nnz < n || !row_ptr || !col_idx || !vd) return "bad sizes or null arrays";
+    if (row_ptr[0] != 0 || row_ptr[n] != nnz) return "row_ptr[0] must be 0 and row_ptr[n] nnz";
+    for (int64_t i = 0; i < n; ++i)
+        if (row_ptr[i + 1] < row_ptr[i]) return "row_ptr is decreasing";
+    diag.assign(n, cd(0.0, 0.0));
+    // per row: 0 fine, 1 column out of range, 2 columns not increasing, 3 no nonzero diagonal
+    std::vector<int8_t> bad(n, 0);
+    parallel_for(n, [&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i) {
+            bool found = false;
+            for (int64_t e = row_ptr[i]; e < row_ptr[i + 1] && !bad[i]; ++e) {
+                if (col_idx[e] < 0 || col_idx[e] >= n)
+                    bad[i] = 1;
+                else if (e > row_ptr[i] && col_idx[e] <= col_idx[e - 1])
+                    bad[i] = 2;
+                else if (col_idx[e] == i) {
+                    diag[i] = complex_values ? cd(vd[2 * e], vd[2 * e + 1]) : cd(vd[e], 0.0);
+                    found = true;
+                }
+            }
+            if (!bad[i] && (!found || diag[i] == cd(0.0, 0.0))) bad[i] = 3;
+        }
+    });
+    for (int64_t i = 0; i < n; ++i) {   // pattern errors first, then a missing diagonal
+        if (bad[i] == 1) return "column index out of range";
+        if (bad[i] == 2) return "columns must be strictly increasing within a row";
+    }
+    for (int64_t i = 0; i < n; ++i)
+        if (bad[i] == 3) {
+            *singular = true;
+            return "row " + std::to_string(i) + " has no nonzero diagonal entry";
+        }
+    return "";
+}
+
+// Transpose of the pattern: column i lists (row j, position of c_ji in the
+// CSR arrays), rows ascending -- a counting sort over row ranges: range t
+// counts its entries per column, the per-column counts become per-range
+// offsets, then every range writes its own slots (ranges ascend, so rows come
+// out ascending).
+inline void transpose_csr(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
+                          std::vector<int64_t>& tptr, std::vector<int32_t>& trow, std::vector<int64_t>& tsrc)
+{
+    tptr.assign(n + 1, 0);
+    trow.resize(nnz);
+    tsrc.resize(nnz);
+    // ranges: one per 16K rows, at most 16, and at most 2^25 / n (count memory)
+    const int64_t T = std::max<int64_t>(1, std::min<int64_t>({16, n >> 14, ((int64_t)1 << 25) / n}));
+    std::vector<int32_t> cnt((size_t)(T * n), 0);
+    auto range_of = [&](int64_t t, int64_t* i0, int64_t* i1) {
+        *i0 = n * t / T;
+        *i1 = n * (t + 1) / T;
+    };
+    auto per_range = [&](auto&& body) {
+        std::vector<std::thread> th;
+        for (int64_t t = 1; t < T; ++t) th.emplace_back([&body, t]() { body(t); });
+        body(0);
+        for (std::thread& x : th) x.join();
+    };
+    per_range([&](int64_t t) {
+        int64_t i0, i1;
+        range_of(t, &i0, &i1);
+        int32_t* c = cnt.data() + t * n;
+        for (int64_t e = row_ptr[i0]; e < row_ptr[i1]; ++e) c[col_idx[e]]++;
+    });
+    parallel_for(n, [&](int64_t c0, int64_t c1) {
+        for (int64_t c = c0; c < c1; ++c) {
+            int32_t run = 0;
+            for (int64_t t = 0; t < T; ++t) {
+                const int32_t k = cnt[t * n + c];
+                cnt[t * n + c] = run;
+                run += k;
+            }
+            tptr[c + 1] = run;
+        }
+    });
+    for (int64_t i = 0; i < n; ++i) tptr[i + 1] += tptr[i];
+    per_range([&](int64_t t) {
+        int64_t i0, i1;
+        range_of(t, &i0, &i1);
+        int32_t* c = cnt.data() + t * n;
+        for (int64_t i = i0; i < i1; ++i)
+            for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+                const int64_t slot = tptr[col_idx[e]] + c[col_idx[e]]++;
+                trow[slot] = (int32_t)i;
+                tsrc[slot] = e;
+            }
+    });
+}
+
 // Returns an empty string on success, else the reason; *singular is set when
 // the failure is a missing or zero diagonal.
 inline std::string prepare_matrix(int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
                                   const double* vd, bool complex_values, Prepared& h, bool* singular)
 {
-    *singular = false;
-    if (n < 1 || n > INT32_MAX || nnz < n || !row_ptr || !col_idx || !vd) return "bad sizes or null arrays";
-    if (row_ptr[0] != 0 || row_ptr[n] != nnz) return "row_ptr[0] must be 0 and row_ptr[n] nnz";
-    for (int64_t i = 0; i < n; ++i) {
-        if (row_ptr[i + 1] < row_ptr[i]) return "row_ptr is decreasing";
-        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
-            if (col_idx[e] < 0 || col_idx[e] >= n) return "column index out of range";
-            if (e > row_ptr[i] && col_idx[e] <= col_idx[e - 1])
-                return "columns must be strictly increasing within a row";
-        }
-    }
+    std::vector<cd> diag;
+    const std::string why = validate_csr(n, nnz, row_ptr, col_idx, vd, complex_values, diag, singular);
+    if (!why.empty()) return why;
     auto val = [&](int64_t e) { return complex_values ? cd(vd[2 * e], vd[2 * e + 1]) : cd(vd[e], 0.0); };
 
-    std::vector<cd> diag(n);
-    for (int64_t i = 0; i < n; ++i) {
-        bool found = false;
-        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
-            if (col_idx[e] == i) {
-                diag[i] = val(e);
-                found = true;
-            }
-        if (!found || diag[i] == cd(0.0, 0.0)) {
-            *singular = true;
-            return "row " + std::to_string(i) + " has no nonzero diagonal entry";
-        }
-    }
-
-    // Transpose: column i lists (row j, position of c_ji), rows ascending --
-    // a counting sort over row ranges: range t counts its entries per column,
-    // the per-column counts become per-range offsets, then every range writes
-    // its own slots (ranges ascend, so rows come out ascending).
-    std::vector<int64_t> tptr(n + 1, 0);
-    std::vector<int32_t> trow(nnz);
-    std::vector<int64_t> tsrc(nnz);
-    {
-        // ranges: one per 16K rows, at most 16, and at most 2^25 / n (count memory)
-        const int64_t T = std::max<int64_t>(1, std::min<int64_t>({16, n >> 14, ((int64_t)1 << 25) / n}));
-        std::vector<int32_t> cnt((size_t)(T * n), 0);
-        auto range_of = [&](int64_t t, int64_t* i0, int64_t* i1) {
-            *i0 = n * t / T;
-            *i1 = n * (t + 1) / T;
-        };
-        auto per_range = [&](auto&& body) {
-            std::vector<std::thread> th;
-            for (int64_t t = 1; t < T; ++t) th.emplace_back([&body, t]() { body(t); });
-            body(0);
-            for (std::thread& x : th) x.join();
-        };
-        per_range([&](int64_t t) {
-            int64_t i0, i1;
-            range_of(t, &i0, &i1);
-            int32_t* c = cnt.data() + t * n;
-            for (int64_t e = row_ptr[i0]; e < row_ptr[i1]; ++e) c[col_idx[e]]++;
-        });
-        parallel_for(n, [&](int64_t c0, int64_t c1) {
-            for (int64_t c = c0; c < c1; ++c) {
-                int32_t run = 0;
-                for (int64_t t = 0; t < T; ++t) {
-                    const int32_t k = cnt[t * n + c];
-                    cnt[t * n + c] = run;
-                    run += k;
-                }
-                tptr[c + 1] = run;
-            }
-        });
-        for (int64_t i = 0; i < n; ++i) tptr[i + 1] += tptr[i];
-        per_range([&](int64_t t) {
-            int64_t i0, i1;
-            range_of(t, &i0, &i1);
-            int32_t* c = cnt.data() + t * n;
-            for (int64_t i = i0; i < i1; ++i)
-                for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
-                    const int64_t slot = tptr[col_idx[e]] + c[col_idx[e]]++;
-                    trow[slot] = (int32_t)i;
-                    tsrc[slot] = e;
-                }
-        });
-    }
+    std::vector<int64_t> tptr;
+    std::vector<int32_t> trow;
+    std::vector<int64_t> tsrc;
+    transpose_csr(n, nnz, row_ptr, col_idx, tptr, trow, tsrc);
 
     // Merged off-diagonal pattern per original row: the union of row i and
     // column i (both ascending).  merge_row visits it in column order;
