@@ -370,7 +370,9 @@ def surrogate_form(pkg, torch, gen, n_train, n_val, rel_label=0.005, rel=0.01, s
     t_train = time.perf_counter() - t0
     pv = net.predict(Xv).astype(np.float64)
     rv = (pv - yv) / yv
-    gate = sur.Gate(Xv, pv, yv, sev, feature_a=1, feature_b=5, bins=8, min_rows=200, tol=rel)
+    # a bin is trusted when a one-sided 95% upper bound of its error meets the
+    # tolerance (few validation rows need a smaller observed error)
+    gate = sur.Gate(Xv, pv, yv, sev, feature_a=1, feature_b=5, bins=8, min_rows=20, tol=rel, ucb_z=1.645)
     log(f"surrogate: trained {steps} steps x {batch} rows in {t_train:.2f} s; held-out matrix ...")
 
     m = make(qs[-1], w["eval_n"])
@@ -396,6 +398,12 @@ def surrogate_form(pkg, torch, gen, n_train, n_val, rel_label=0.005, rel=0.01, s
     net.close()
     gate_tab = gate.table()
     gate.close()
+    # rows in bins with fewer than 200 validation rows (which a fixed 200-row
+    # floor would send to the sampler): their difference from the plain run
+    Xh = sur.features(m)
+    hb = np.searchsorted(gate_tab["edges_a"], Xh[:, 1].astype(np.float64), side="right") * 8 + \
+        np.searchsorted(gate_tab["edges_b"], Xh[:, 5].astype(np.float64), side="right")
+    sparse = acc & (gate_tab["count"][hb] < 200)
     return {
         "workload": f"{n_train} train + {n_val} validation pedigree matrices (n={w['train_n']}, random "
                     f"dominance 1.2-2.0, lambda 0-0.5, founders 2-20%), held-out n={m.n}",
@@ -425,7 +433,11 @@ def surrogate_form(pkg, torch, gen, n_train, n_val, rel_label=0.005, rel=0.01, s
                      "accepted_rms_rel_diff_vs_plain": float(np.sqrt(np.mean(r[acc] ** 2))) if acc.any() else None,
                      "accepted_model_err_est": float(np.sqrt(max(np.mean(r[acc] ** 2) - np.mean(s_rel[acc] ** 2),
                                                                  0.0))) if acc.any() else None,
-                     "plain_pairs": P},
+                     "plain_pairs": P,
+                     "sparse_bin_rows": {
+                         "rows": int(sparse.sum()),
+                         "rms_rel_diff_vs_plain": float(np.sqrt(np.mean(r[sparse] ** 2))) if sparse.any() else None,
+                         "plain_rms_rel_se": float(np.sqrt(np.mean(s_rel[sparse] ** 2))) if sparse.any() else None}},
     }
 
 

@@ -472,14 +472,21 @@ const char* mcinv_mlp_last_error(const mcinv_mlp* m);
  * quantile edges: the sorted values at floor(k N / bins), k = 1..bins-1, and a
  * value's bin is the number of edges <= it.  A bin's validated relative error
  * is sqrt(max(sum r^2 - sum s^2, 0) / count), r = (pred - y)/y, s = se/y (the
- * observed spread less what the label noise explains); the bin needs the
- * sampler when it holds fewer than min_rows rows or that error exceeds tol.
- * Host code, float64. */
+ * observed spread less what the label noise explains).  With ucb_z > 0 the
+ * error compared with tol is instead an upper confidence bound for it,
+ * sqrt(max(sum r^2 - sum s^2, 0) / q), where q is the lower quantile of a
+ * chi-square with count degrees of freedom at standard normal quantile -ucb_z
+ * (Wilson-Hilferty: q = k (1 - 2/(9k) - ucb_z sqrt(2/(9k)))^3, k = count;
+ * ucb_z = 1.645: one-sided 95%), so a bin with few rows needs a smaller
+ * observed error.  The bin needs the sampler when it holds fewer than
+ * min_rows rows or that error exceeds tol.  Host code, float64. */
 typedef struct {
     int32_t feature_a, feature_b;  /* binning features, 0..31                    */
     int32_t bins;                  /* bins per feature, 1..256                    */
     int32_t min_rows;              /* fewer validation rows in a bin: sampler     */
     double  tol;                   /* largest accepted relative error (e.g. 0.01) */
+    double  ucb_z;                 /* 0: point estimate; > 0: upper bound at that
+                                      normal quantile (see above)                 */
 } mcinv_gate_config;
 typedef struct mcinv_gate mcinv_gate;
 
@@ -490,7 +497,8 @@ mcinv_status mcinv_gate_fit(const mcinv_gate_config* cfg, int64_t N, const float
 /* fallback[i] = 1 when row i's bin needs the sampler (or a binning feature is NaN). */
 mcinv_status mcinv_gate_apply(const mcinv_gate* g, int64_t N, const float* X, uint8_t* fallback);
 /* edges_a, edges_b [bins-1]; bin_err, bin_count, bin_fallback [bins * bins],
- * bin (a, b) at a * bins + b (err is +inf for an empty bin).  Any may be NULL. */
+ * bin (a, b) at a * bins + b.  bin_err is the value compared with tol (the
+ * upper bound when ucb_z > 0; +inf for an empty bin).  Any may be NULL. */
 mcinv_status mcinv_gate_read(const mcinv_gate* g, double* edges_a, double* edges_b, double* bin_err,
                              int64_t* bin_count, uint8_t* bin_fallback);
 void mcinv_gate_destroy(mcinv_gate* g);

@@ -276,10 +276,21 @@ def gate_bin(edges, x):
     return np.searchsorted(edges, np.asarray(x, dtype=np.float64), side="right")
 
 
-def gate_fit(X, pred, y, y_se, fa, fb, bins, min_rows, tol):
+def chi2_lower_quantile(k, z):
+    """Wilson and Hilferty's (1931) normal approximation of the chi-square
+    distribution with k degrees of freedom: (X / k)^(1/3) is close to normal
+    with mean 1 - 2/(9k) and variance 2/(9k), so the quantile at standard
+    normal value -z is k (1 - 2/(9k) - z sqrt(2/(9k)))^3 (floored at 1e-3)."""
+    c = 2.0 / (9.0 * k)
+    return max(k * (1.0 - c - z * np.sqrt(c)) ** 3, 1e-3)
+
+
+def gate_fit(X, pred, y, y_se, fa, fb, bins, min_rows, tol, ucb_z=0.0):
     """Validated relative error per (feature a, feature b) bin: sqrt(max(sum r^2 - sum s^2, 0) / count)
     with r = (pred - y) / y and s = y_se / y (the label noise is removed from the observed spread);
-    a bin needs the sampler when it has fewer than min_rows rows or its error exceeds tol."""
+    with ucb_z > 0 the count is replaced by the chi-square lower quantile above, which turns the
+    error into an upper confidence bound; a bin needs the sampler when it has fewer than min_rows
+    rows or that error exceeds tol."""
     X = np.asarray(X, dtype=np.float32)
     ea = gate_edges(X[:, fa], bins)
     eb = gate_edges(X[:, fb], bins)
@@ -294,8 +305,10 @@ def gate_fit(X, pred, y, y_se, fa, fb, bins, min_rows, tol):
         r2[b[i]] += r[i] * r[i]
         s2[b[i]] += s[i] * s[i]
     err = np.full(bins * bins, np.inf)
-    ok = cnt > 0
-    err[ok] = np.sqrt(np.maximum(r2[ok] - s2[ok], 0.0) / cnt[ok])
+    for b in range(bins * bins):
+        if cnt[b] > 0:
+            q = chi2_lower_quantile(float(cnt[b]), ucb_z) if ucb_z > 0 else float(cnt[b])
+            err[b] = np.sqrt(max(r2[b] - s2[b], 0.0) / q)
     fallback = (cnt < min_rows) | ~(err <= tol)
     return {"edges_a": ea, "edges_b": eb, "err": err, "count": cnt, "fallback": fallback,
             "fa": fa, "fb": fb, "bins": bins}

@@ -104,7 +104,7 @@ class mcinv_batch_info(ctypes.Structure):
 
 class mcinv_gate_config(ctypes.Structure):
     _fields_ = [("feature_a", ctypes.c_int32), ("feature_b", ctypes.c_int32), ("bins", ctypes.c_int32),
-                ("min_rows", ctypes.c_int32), ("tol", ctypes.c_double)]
+                ("min_rows", ctypes.c_int32), ("tol", ctypes.c_double), ("ucb_z", ctypes.c_double)]
 
 
 _lib = None
@@ -596,7 +596,7 @@ def _gcheck(status):
     return status
 
 
-def mcinv_gate_fit(X, pred, y, y_se, feature_a, feature_b, bins, min_rows, tol):
+def mcinv_gate_fit(X, pred, y, y_se, feature_a, feature_b, bins, min_rows, tol, ucb_z=0.0):
     X = _f32(X)
     N = X.size // MCINV_N_FEATURES
     pr = np.ascontiguousarray(pred, dtype=np.float64)
@@ -604,7 +604,7 @@ def mcinv_gate_fit(X, pred, y, y_se, feature_a, feature_b, bins, min_rows, tol):
     se = np.ascontiguousarray(y_se, dtype=np.float64)
     if pr.size != N or yy.size != N or se.size != N:
         raise ValueError("pred, y and y_se need one value per row of X")
-    cfg = mcinv_gate_config(int(feature_a), int(feature_b), int(bins), int(min_rows), float(tol))
+    cfg = mcinv_gate_config(int(feature_a), int(feature_b), int(bins), int(min_rows), float(tol), float(ucb_z))
     h = ctypes.c_void_p()
     _gcheck(lib().mcinv_gate_fit(ctypes.byref(cfg), int(N), _ptr(X), _ptr(pr), _ptr(yy), _ptr(se),
                                  ctypes.byref(h)))

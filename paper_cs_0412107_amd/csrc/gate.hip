@@ -6,7 +6,11 @@
 // values at floor(k N / bins), k = 1..bins-1; bin = number of edges <= x).  A
 // bin's validated relative error is sqrt(max(sum r^2 - sum s^2, 0) / count)
 // with r = (pred - y) / y and s = se / y: the observed spread less the part
-// the label noise explains.  A bin needs the sampler when it holds fewer than
+// the label noise explains.  With ucb_z > 0 the error is replaced by an upper
+// confidence bound: the bin's rows give a chi-square with count degrees of
+// freedom for (sum of squared errors) / (true mean square), so dividing by
+// that distribution's lower quantile (Wilson-Hilferty approximation) bounds
+// the true error from above.  A bin needs the sampler when it holds fewer than
 // min_rows rows or its error exceeds tol.  Host code, float64, rows summed in
 // order.
 #include <algorithm>
@@ -38,6 +42,16 @@ std::vector<double> quantile_edges(const float* X, int64_t N, int32_t f, int32_t
     return e;
 }
 
+// Lower quantile of a chi-square with k degrees of freedom at the standard
+// normal quantile -z (Wilson and Hilferty, 1931); floored at a small positive
+// value for tiny k, where the cube can turn negative.
+double chi2_lower(double k, double z)
+{
+    const double c = 2.0 / (9.0 * k);
+    const double t = 1.0 - c - z * std::sqrt(c);
+    return std::max(k * t * t * t, 1e-3);
+}
+
 int64_t bin_of(const std::vector<double>& edges, double x)
 {
     return std::upper_bound(edges.begin(), edges.end(), x) - edges.begin();
@@ -60,7 +74,7 @@ mcinv_status mcinv_gate_fit(const mcinv_gate_config* cfg, int64_t N, const float
     *out = nullptr;
     if (cfg->feature_a < 0 || cfg->feature_a >= MCINV_N_FEATURES || cfg->feature_b < 0 ||
         cfg->feature_b >= MCINV_N_FEATURES || cfg->bins < 1 || cfg->bins > 256 || cfg->min_rows < 0 ||
-        !(cfg->tol >= 0.0)) {
+        !(cfg->tol >= 0.0) || !(cfg->ucb_z >= 0.0) || !(cfg->ucb_z < 10.0)) {
         set_err("mcinv_gate_fit: bad configuration");
         return MCINV_EINVAL;
     }
@@ -89,7 +103,11 @@ mcinv_status mcinv_gate_fit(const mcinv_gate_config* cfg, int64_t N, const float
     g->err.assign((size_t)B * B, INFINITY);
     g->fallback.assign((size_t)B * B, 1);
     for (size_t b = 0; b < g->err.size(); ++b) {
-        if (g->count[b] > 0) g->err[b] = std::sqrt(std::max(r2[b] - s2[b], 0.0) / (double)g->count[b]);
+        if (g->count[b] > 0) {
+            const double k = (double)g->count[b];
+            const double q = cfg->ucb_z > 0.0 ? chi2_lower(k, cfg->ucb_z) : k;
+            g->err[b] = std::sqrt(std::max(r2[b] - s2[b], 0.0) / q);
+        }
         g->fallback[b] = (g->count[b] < cfg->min_rows || !(g->err[b] <= cfg->tol)) ? 1 : 0;
     }
     *out = g;

@@ -99,9 +99,9 @@ class Network:
 class Gate:
     """Per-bin validated error over two features (``mcinv_gate``)."""
 
-    def __init__(self, X, pred, y, y_se, feature_a=1, feature_b=5, bins=8, min_rows=50, tol=0.01):
+    def __init__(self, X, pred, y, y_se, feature_a=1, feature_b=5, bins=8, min_rows=50, tol=0.01, ucb_z=0.0):
         self.bins = bins
-        self.h = B.mcinv_gate_fit(X, pred, y, y_se, feature_a, feature_b, bins, min_rows, tol)
+        self.h = B.mcinv_gate_fit(X, pred, y, y_se, feature_a, feature_b, bins, min_rows, tol, ucb_z)
 
     def close(self):
         if self.h:

@@ -206,6 +206,43 @@ def test_gate_hand_example():
     assert g3["err"][2] == 0.0  # noise larger than the spread
 
 
+def test_chi2_lower_quantile_matches_scipy_and_covers():
+    """The gate's confidence bound: Wilson-Hilferty against scipy's chi-square
+    quantiles, and the bound covers the true RMS error ~95% of the time."""
+    from scipy import stats
+    z = 1.645
+    for k in (20, 50, 200, 2000, 100000):
+        exact = stats.chi2.ppf(stats.norm.cdf(-z), k)
+        assert abs(S.chi2_lower_quantile(k, z) - exact) <= 0.01 * exact, k
+    for k in (5, 10):
+        exact = stats.chi2.ppf(stats.norm.cdf(-z), k)
+        assert abs(S.chi2_lower_quantile(k, z) - exact) <= 0.05 * exact, k
+    rng = np.random.default_rng(3)
+    sigma, k, reps = 0.004, 30, 4000
+    r = rng.normal(0.0, sigma, (reps, k))
+    ucb = np.sqrt((r ** 2).sum(axis=1) / S.chi2_lower_quantile(k, z))
+    cover = np.mean(ucb >= sigma)
+    assert 0.93 < cover < 0.97, cover
+    # in the gate: a small bin needs a smaller observed error than a large one.
+    # Features 0 and 1 are ranks 0..209 split at 105; swapping rows 100-104 with
+    # 105-109 in feature 1 leaves 100 rows in bins (0,0) and (1,1), 5 in (0,1), (1,0)
+    X = np.zeros((210, 32), dtype=np.float32)
+    X[:, 0] = np.arange(210)
+    b = np.arange(210)
+    b[100:105], b[105:110] = np.arange(105, 110), np.arange(100, 105)
+    X[:, 1] = b
+    y = np.ones(210)
+    pred = 1 + np.where(np.arange(210) % 2 == 0, 0.008, -0.008)
+    g0 = S.gate_fit(X, pred, y, np.zeros(210), 0, 1, 2, 1, 0.01)
+    g = S.gate_fit(X, pred, y, np.zeros(210), 0, 1, 2, 1, 0.01, ucb_z=z)
+    assert g0["count"].tolist() == [100, 5, 5, 100]
+    np.testing.assert_allclose(g0["err"], 0.008, rtol=1e-12)
+    # 100 rows: 0.008 sqrt(100 / q(100)) ~ 0.0091 <= 0.01; 5 rows: ~0.0168 > 0.01
+    assert g["err"][0] < 0.01 < g["err"][1] and g["err"][3] < 0.01 < g["err"][2]
+    assert g["fallback"].tolist() == [False, True, True, False]
+    assert not g0["fallback"].any()
+
+
 def test_gate_library_matches_oracle():
     mc = pytest.importorskip("paper_cs_0412107_amd")
     try:
@@ -219,9 +256,10 @@ def test_gate_library_matches_oracle():
     y = 1 + 0.2 * rng.random(N)
     pred = y * (1 + 0.01 * rng.standard_normal(N) * (1 + np.abs(X[:, 1])))
     se = 0.003 * y
-    for bins, min_rows, tol in ((8, 20, 0.012), (1, 1, 0.02), (16, 30, 0.01)):
-        ref = S.gate_fit(X, pred, y, se, 1, 5, bins, min_rows, tol)
-        h = mc.mcinv_gate_fit(X, pred, y, se, 1, 5, bins, min_rows, tol)
+    for bins, min_rows, tol, z in ((8, 20, 0.012, 0.0), (1, 1, 0.02, 0.0), (16, 30, 0.01, 0.0),
+                                   (8, 5, 0.012, 1.645), (16, 2, 0.01, 2.33)):
+        ref = S.gate_fit(X, pred, y, se, 1, 5, bins, min_rows, tol, ucb_z=z)
+        h = mc.mcinv_gate_fit(X, pred, y, se, 1, 5, bins, min_rows, tol, ucb_z=z)
         try:
             got = mc.mcinv_gate_read(h, bins)
             assert np.array_equal(got["edges_a"], ref["edges_a"])
