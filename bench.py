@@ -635,7 +635,15 @@ def main():
 
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
-        result["cpu_baseline"] = cpu_baseline(m, seed, P, G, args.cpu_budget)
+        cb = cpu_baseline(m, seed, P, G, args.cpu_budget)
+        ttt = result.get("time_to_1pct")
+        if ttt is not None:
+            # the same sweeps (burn-in + samples) the GPU needed, at the oracle's rate for all P pairs
+            sweeps = ttt["burn_in"] + ttt["sample_sweeps"]
+            cb["time_to_1pct_s_extrapolated"] = sweeps * 2.0 * m.nnz * P / cb["value"]
+            cb["time_to_1pct_note"] = (f"{sweeps} sweeps of {P} pairs (the GPU run's coupled burn-in and "
+                                       f"samples) at the measured oracle rate")
+        result["cpu_baseline"] = cb
     print(json.dumps(result), flush=True)
 
 

@@ -510,14 +510,18 @@ __global__ __launch_bounds__(256) void k_finalize_groups(const FinalizeArgs f)
     const int64_t grp = ok && f.val_group ? f.val_group[v] : 0;
     const double* slot_len = f.slot_len + grp * f.slot_len_stride;
     double wsum = 0.0, er = 0.0, ei = 0.0, nc = 0.0;
+    double x0r = 0.0, x0i = 0.0, w0 = 0.0;   // the only slot's cluster when there is one (no second read)
     if (ok)
         for (int64_t b = 0; b < f.nslots; ++b) {
             const double wt = slot_len[b] * (double)f.gs;
             if (wt <= 0.0) continue;
             const double* x = f.acc + b * f.slot_stride + (v * G + g) * f.comps;
+            x0r = x[0];
+            if (f.comps == 2) x0i = x[1];
+            w0 = wt;
             wsum += wt;
-            er += x[0];
-            if (f.comps == 2) ei += x[1];
+            er += x0r;
+            ei += x0i;
             nc += 1.0;
         }
     for (int off = 1; off < G; off <<= 1) {
@@ -529,15 +533,21 @@ __global__ __launch_bounds__(256) void k_finalize_groups(const FinalizeArgs f)
     double vr = 0.0, vi = 0.0;
     if (ok && wsum > 0.0) {
         const double mr = er / wsum, mi = ei / wsum;
-        for (int64_t b = 0; b < f.nslots; ++b) {
-            const double wt = slot_len[b] * (double)f.gs;
-            if (wt <= 0.0) continue;
-            const double* x = f.acc + b * f.slot_stride + (v * G + g) * f.comps;
-            const double dr = x[0] - wt * mr;
-            vr += dr * dr;
-            if (f.comps == 2) {
-                const double di = x[1] - wt * mi;
-                vi += di * di;
+        if (f.nslots == 1) {
+            const double dr = x0r - w0 * mr, di = x0i - w0 * mi;
+            vr = dr * dr;
+            vi = f.comps == 2 ? di * di : 0.0;
+        } else {
+            for (int64_t b = 0; b < f.nslots; ++b) {
+                const double wt = slot_len[b] * (double)f.gs;
+                if (wt <= 0.0) continue;
+                const double* x = f.acc + b * f.slot_stride + (v * G + g) * f.comps;
+                const double dr = x[0] - wt * mr;
+                vr += dr * dr;
+                if (f.comps == 2) {
+                    const double di = x[1] - wt * mi;
+                    vi += di * di;
+                }
             }
         }
     }
