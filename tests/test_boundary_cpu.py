@@ -61,3 +61,67 @@ def test_bad_config_rejected_before_device():
     with pytest.raises(pkg.McinvError) as ei:
         pkg.mcinv_create(n_pairs=8, n_groups=3)
     assert ei.value.code == pkg.MCINV_EINVAL
+
+
+def _csr(n, rows):
+    """CSR arrays from per-row (column, value) lists, kept in the given order."""
+    import numpy as np
+    rp = [0]
+    col, val = [], []
+    for r in rows:
+        col += [c for c, _ in r]
+        val += [v for _, v in r]
+        rp.append(len(col))
+    return (n, len(col), np.array(rp, dtype=np.int64), np.array(col, dtype=np.int32),
+            np.array(val, dtype=np.float64))
+
+
+@pytest.mark.parametrize("case,code,text", [
+    ("unsorted", "EINVAL", "strictly increasing"),
+    ("duplicate", "EINVAL", "strictly increasing"),
+    ("range", "EINVAL", "out of range"),
+    ("no_diag", "ESINGULAR", "row 2 has no nonzero diagonal"),
+    ("zero_diag", "ESINGULAR", "row 1 has no nonzero diagonal"),
+    ("both", "EINVAL", "out of range"),          # a pattern error outranks a missing diagonal
+    ("row_ptr", "EINVAL", "row_ptr is decreasing"),
+])
+def test_csr_validation_on_the_host(case, code, text):
+    """The host preparation's CSR checks (run before any device call, here
+    through mcinv_features): the error code and the reported row."""
+    import paper_cs_0412107_amd as pkg
+    good = [[(0, 4.0), (1, 1.0)], [(0, 1.0), (1, 4.0), (3, 1.0)], [(1, 1.0), (2, 4.0)], [(2, 1.0), (3, 4.0)]]
+    rows = [list(r) for r in good]
+    if case == "unsorted":
+        rows[1] = [(1, 4.0), (0, 1.0), (3, 1.0)]
+    elif case == "duplicate":
+        rows[3] = [(3, 4.0), (3, 1.0)]
+    elif case == "range":
+        rows[2] = [(1, 1.0), (2, 4.0), (7, 1.0)]
+    elif case == "no_diag":
+        rows[2] = [(1, 1.0)]
+    elif case == "zero_diag":
+        rows[1] = [(0, 1.0), (1, 0.0), (3, 1.0)]
+    elif case == "both":
+        rows[1] = [(0, 1.0), (3, 1.0)]               # row 1 lacks its diagonal ...
+        rows[3] = [(3, 4.0), (9, 1.0)]               # ... and row 3 has a column out of range
+    n, nnz, rp, col, val = _csr(4, rows)
+    if case == "row_ptr":
+        rp = rp.copy()
+        rp[2], rp[3] = rp[3], rp[2]
+    with pytest.raises(pkg.McinvError) as ei:
+        pkg.mcinv_features(0, n, nnz, rp, col, val)
+    assert ei.value.code == getattr(pkg, "MCINV_" + code), (ei.value.code, str(ei.value))
+    assert text in str(ei.value), str(ei.value)
+
+
+def test_valid_csr_passes_the_host_checks():
+    import torch
+    import paper_cs_0412107_amd as pkg
+    good = [[(0, 4.0), (1, 1.0)], [(0, 1.0), (1, 4.0), (3, 1.0)], [(1, 1.0), (2, 4.0)], [(2, 1.0), (3, 4.0)]]
+    n, nnz, rp, col, val = _csr(4, good)
+    if torch.cuda.is_available():
+        assert pkg.mcinv_features(0, n, nnz, rp, col, val).shape == (4, 32)
+    else:
+        with pytest.raises(pkg.McinvError) as ei:   # validated, then no device
+            pkg.mcinv_features(0, n, nnz, rp, col, val)
+        assert ei.value.code == pkg.MCINV_EDEVICE
