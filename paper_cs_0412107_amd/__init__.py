@@ -34,7 +34,13 @@ def torch_stream():
 
 
 class Sampler:
-    """One context: a matrix, its chain pairs and the requested moments."""
+    """One context: a matrix, its chain pairs and the requested moments.
+
+    ``matrix``: CSR with ``n``, ``row_ptr``, ``col``, ``val`` (float64 or
+    complex128 values); ``pairs`` independent (z, w) chain pairs in ``groups``
+    error groups; ``dtype`` the sweep precision ("f32", "f64", "c64", "c128");
+    ``moments="bf16x3"`` puts dense blocks on the matrix cores (fp32 sweeps).
+    All row indices are the matrix's own.  Usable as a context manager."""
 
     def __init__(self, matrix, pairs, groups=1, dtype="f32", seed=0, noise=MCINV_NOISE_NORMAL,
                  moments="fp64", device=0, stream_id=0, use_torch_stream=False, profile=False, pass_tiles=0,
@@ -81,11 +87,14 @@ class Sampler:
         mcinv_set_trace_matrix(self.ctx, self.n, rp, ci, v)
 
     def qtrace(self):
+        """(estimate, SE) of tr(Q C^-1) for the Q of ``set_trace_matrix``."""
         from ._binding import MCINV_REQ_QTRACE
         est, se = mcinv_read_estimates(self.ctx, MCINV_REQ_QTRACE, 1, self.is_complex)
         return est[0], se[0]
 
     def request(self, diag=True, trace=True, block_rows=None, block_cols=None, entries=None, qtrace=False):
+        """Choose the moments to accumulate (clears earlier ones): the diagonal,
+        the trace, the dense block rows x cols, entries [(i, j), ...], tr(Q C^-1)."""
         from ._binding import MCINV_REQ_QTRACE
         flags = (MCINV_REQ_DIAG if diag else 0) | (MCINV_REQ_TRACE if trace else 0) | \
             (MCINV_REQ_QTRACE if qtrace else 0)
@@ -102,6 +111,7 @@ class Sampler:
         mcinv_set_requested(self.ctx, flags, block_rows, block_cols, ei, ej)
 
     def burn_in(self, sweeps):
+        """Sweeps whose samples are discarded."""
         mcinv_burn_in(self.ctx, sweeps)
 
     def burn_in_coupled(self, tol=5e-5, max_sweeps=10000):
@@ -110,36 +120,45 @@ class Sampler:
         return mcinv_burn_in_coupled(self.ctx, tol, max_sweeps)
 
     def sample(self, sweeps):
+        """Sampling sweeps: one sample per pair each."""
         mcinv_sample(self.ctx, sweeps)
 
     def sample_until(self, rel_se, max_sweeps, check_every=10):
+        """Sample until max_i SE_i / |est_i| <= rel_se on the diagonal; returns (sweeps, achieved)."""
         return mcinv_sample_until(self.ctx, rel_se, max_sweeps, check_every)
 
     def sample_until_trace(self, rel_se, max_sweeps, check_every=20):
+        """Sample until the trace's Geyer SE / |estimate| <= rel_se; returns (sweeps, achieved)."""
         from ._binding import mcinv_sample_until_trace
         return mcinv_sample_until_trace(self.ctx, rel_se, max_sweeps, check_every)
 
     def diag(self):
+        """(estimates, SEs) of (C^-1)_ii."""
         return mcinv_read_estimates(self.ctx, MCINV_REQ_DIAG, self.n, self.is_complex)
 
     def block(self):
+        """(estimates, SEs) of the requested block, rows x cols."""
         est, se = mcinv_read_estimates(self.ctx, MCINV_REQ_BLOCK, self.nI * self.nJ, self.is_complex)
         return est.reshape(self.nI, self.nJ), se.reshape(self.nI, self.nJ)
 
     def entries(self):
+        """(estimates, SEs) of the requested entries."""
         return mcinv_read_estimates(self.ctx, MCINV_REQ_ENTRIES, self.ne, self.is_complex)
 
     def trace(self):
+        """(estimate, Geyer SE) of tr(C^-1)."""
         est, se = mcinv_read_estimates(self.ctx, MCINV_REQ_TRACE, 1, self.is_complex)
         return est[0], se[0]
 
     def state(self, which):
+        """Chain state z (which=0) or w (1), [n][pairs], original row order."""
         return mcinv_read_state(self.ctx, which, self.n, self.P, self.dtype)
 
     def set_state(self, which, values):
         mcinv_write_state(self.ctx, which, values, self.dtype)
 
     def permutation(self):
+        """(position order, colour of each row) of the multicolour sweep."""
         return mcinv_get_permutation(self.ctx, self.n)
 
     def save(self, path):
@@ -163,6 +182,7 @@ class Sampler:
         return mcinv_tune_launch(self.ctx, sweeps_per_trial)
 
     def check_convergence(self, iters=200):
+        """Contraction rates of the noiseless iteration (eq 12): estimates of sp(T), sp(S)."""
         return mcinv_check_convergence(self.ctx, iters)
 
     def info(self):
