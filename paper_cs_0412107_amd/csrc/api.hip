@@ -246,7 +246,11 @@ mcinv_status upload_matrix(mcinv_ctx* c, const Prepared& h)
 }
 
 // ------------------------------------------------------------ the sweeps --
-int64_t qtrace_partials(const mcinv_ctx* c) { return (c->n + 3) / 4 * c->ntiles; }
+int64_t qtrace_partials(const mcinv_ctx* c)
+{
+    const int64_t rows_per_block = 4 * kQRowsPerWave;
+    return (c->n + rows_per_block - 1) / rows_per_block * c->ntiles;
+}
 
 mcinv_status grow_series(mcinv_ctx* c, int64_t need, double** series, int64_t* series_cap)
 {

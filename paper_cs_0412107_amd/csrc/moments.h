@@ -47,6 +47,8 @@ struct QTraceArgs {
     const V* qval;
     double* part;
 };
+// Q rows per wave of the Q-trace kernel; partials: ceil(n / (4 kQRowsPerWave)) per 256-pair tile.
+constexpr int kQRowsPerWave = 4;
 template <typename V>
 hipError_t launch_qtrace(const QTraceArgs<V>& a, hipStream_t stream);
 

@@ -157,9 +157,10 @@ template hipError_t launch_entries<Cx<double>>(const Cx<double>*, const Cx<doubl
 
 // ---------------------------------------------------------------- Q trace --
 // Per-sample value of w^dagger Q z summed over the chain pairs (eq tr with a
-// general sparse Q): a wave takes one row q of Q (position order) and 256
-// pairs, forms (Q z)_q in fp64 and multiplies by conj(w_q); one fp64 partial
-// (x2 complex) per workgroup at part[(tile * gridDim.x + row block) * comps].
+// general sparse Q): a wave takes kQRowsPerWave consecutive rows q of Q
+// (position order) and 256 pairs, forms each (Q z)_q in fp64 and multiplies by
+// conj(w_q); one fp64 partial (x2 complex) per workgroup at
+// part[(tile * gridDim.x + row block) * comps].
 template <typename V>
 __global__ __launch_bounds__(256) void k_qtrace(const QTraceArgs<V> a)
 {
@@ -167,10 +168,11 @@ __global__ __launch_bounds__(256) void k_qtrace(const QTraceArgs<V> a)
     constexpr int comps = IsCx<V>::value ? 2 : 1;
     __shared__ double lds[4][2];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int64_t q = (int64_t)blockIdx.x * 4 + wid;
     const int64_t p0 = (int64_t)blockIdx.y * kPairsPerWave + lane * kPairsPerLane;
     W t = vzero<W>();
-    if (q < a.n && p0 < a.ld) {
+    for (int r = 0; r < kQRowsPerWave; ++r) {
+        const int64_t q = ((int64_t)blockIdx.x * 4 + wid) * kQRowsPerWave + r;
+        if (q >= a.n || p0 >= a.ld) break;
         W acc[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[j] = vzero<W>();
@@ -212,7 +214,9 @@ template <typename V>
 hipError_t launch_qtrace(const QTraceArgs<V>& a, hipStream_t stream)
 {
     if (a.n <= 0) return hipSuccess;
-    const dim3 grid((unsigned)((a.n + 3) / 4), (unsigned)((a.ld + kPairsPerWave - 1) / kPairsPerWave));
+    const int64_t rows_per_block = 4 * kQRowsPerWave;
+    const dim3 grid((unsigned)((a.n + rows_per_block - 1) / rows_per_block),
+                    (unsigned)((a.ld + kPairsPerWave - 1) / kPairsPerWave));
     k_qtrace<V><<<grid, dim3(256), 0, stream>>>(a);
     return hipGetLastError();
 }
