@@ -30,14 +30,16 @@ def mats():
     return [gen.round_values(gen.pedigree(int(n), seed=300 + j), np.float32) for j, n in enumerate(SIZES)]
 
 
-@pytest.mark.parametrize("schedule", [0, 1])
-def test_batched_states_equal_single_path(mats, schedule):
-    print_case(test="batch_states", matrices=len(mats), schedule=schedule)
+@pytest.mark.parametrize("schedule,noise", [(0, mc.MCINV_NOISE_NORMAL), (1, mc.MCINV_NOISE_NORMAL),
+                                            (0, mc.MCINV_NOISE_RADEMACHER), (1, mc.MCINV_NOISE_RADEMACHER)])
+def test_batched_states_equal_single_path(mats, schedule, noise):
+    print_case(test="batch_states", matrices=len(mats), schedule=schedule, noise=noise)
     P, G, seed = 64, 16, 0x412107 + 3
-    with mc.BatchSampler(mats, pairs=P, groups=G, seed=seed, rows_per_item=32, grab=2, schedule=schedule) as b:
+    with mc.BatchSampler(mats, pairs=P, groups=G, seed=seed, rows_per_item=32, grab=2, schedule=schedule,
+                         noise=noise) as b:
         b.burn_in(4)
         for m in (0, 3, 4, 9, 11):
-            with mc.Sampler(mats[m], pairs=P, groups=G, dtype="f32", seed=seed, stream_id=m) as s:
+            with mc.Sampler(mats[m], pairs=P, groups=G, dtype="f32", seed=seed, stream_id=m, noise=noise) as s:
                 s.burn_in(4)
                 for which in (0, 1):
                     assert np.array_equal(b.state(m, which), s.state(which)), (m, which)

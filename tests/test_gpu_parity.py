@@ -110,6 +110,23 @@ def _matrix(name):
     raise KeyError(name)
 
 
+@pytest.mark.parametrize("name,dtype,P", [("pedigree2000", "f32", 300), ("lattice4", "c64", 64),
+                                         ("random200", "f64", 6)])
+def test_state_parity_z2_noise(name, dtype, P):
+    """The chains under Z2 (Rademacher) noise against the oracle drawing the
+    same signs."""
+    print_case(test="state_z2", matrix=name, dtype=dtype, P=P)
+    m = _matrix(name)
+    seed = 0x412107 + 19
+    ora = make_oracle(m, dtype, seed, P, noise=oracle.NOISE_RADEMACHER)
+    with _sampler(m, dtype, seed, P, noise=mc.MCINV_NOISE_RADEMACHER) as s:
+        for k in (1, 6):
+            s.burn_in(k)
+            ora.burn_in(k)
+            assert rel_err(s.state(0), ora.z) <= TOL[dtype]
+            assert rel_err(s.state(1), ora.w) <= TOL[dtype]
+
+
 @pytest.mark.parametrize("name,dtype,P,checks", STATE_CASES)
 def test_state_parity(name, dtype, P, checks):
     print_case(test="state", matrix=name, dtype=dtype, P=P)
