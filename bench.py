@@ -52,6 +52,8 @@ def profiled_traffic(workload):
     summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when the
     kernel sources changed since those counters were taken."""
     import hashlib
+    if workload not in PROFILE:
+        return None
     path = os.path.join(ROOT, PROFILE[workload])
     if not os.path.exists(path):
         return None
@@ -468,7 +470,7 @@ def cpu_baseline(m, seed, P, G, budget_s):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--workload", choices=["pedigree", "lattice"], default="pedigree")
+    ap.add_argument("--workload", choices=["pedigree", "lattice", "dirac"], default="pedigree")
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-budget", type=float, default=12.0)
@@ -500,10 +502,14 @@ def main():
         m = gen.round_values(gen.pedigree(w["n"], seed=w["seed"]), np.float32)
         desc = f"pedigree n={m.n} nnz={m.nnz}, {P} chain pairs in {G} groups, fp32 sweeps, " \
                f"diag + {w['block']}x{w['block']} block + trace"
-    else:
+    elif args.workload == "lattice":
         m = gen.round_values(gen.lattice(w["L"], k=w["k"], seed=w["seed"]), np.complex64)
         desc = f"random-phase lattice {w['L']}^4 (n={m.n}, nnz={m.nnz}), {P} chain pairs in {G} groups, " \
                f"complex64 sweeps, diag + trace"
+    else:
+        m = gen.round_values(gen.dirac(w["N"], w["K"]), np.complex64)
+        desc = f"free Wilson-Dirac {w['N']}^4 (n={m.n}, nnz={m.nnz}), K={w['K']}, {P} chain pairs in {G} " \
+               f"groups, complex64 sweeps, diag + trace"
     n = m.n
     s_elem = {"f32": 4, "c64": 8}[dtype]
     blk = np.arange(n - w["block"], n) if "block" in w else None
@@ -512,7 +518,7 @@ def main():
     s = pkg.Sampler(m, pairs=P, groups=G, dtype=dtype, seed=seed, use_torch_stream=True, profile=True,
                     moments="bf16x3" if dtype == "f32" else "fp64")
     info0 = s.info()
-    s.burn_in(w["burn_in"])
+    s.burn_in(w.get("burn_in", 60))
     order, ms_orders = s.tune_launch(2)   # setup: picks the fastest workgroup order
     s.request(diag=True, trace=True, block_rows=blk, block_cols=blk)
     s.sample(args.warmup)
@@ -583,7 +589,8 @@ def main():
             forms["plain_fp64"] = time_to_1pct(pkg, torch, m64, P, G, seed + 1, "f64", "fp64", w["burn_in"],
                                                xcd_order=order64)
         forms["precision"] = time_to_1pct(pkg, torch, m, P, G, seed + 1, dtype,
-                                          "bf16x3" if dtype == "f32" else "fp64", w["burn_in"], xcd_order=order)
+                                          "bf16x3" if dtype == "f32" else "fp64", w.get("burn_in", 60),
+                                          xcd_order=order)
         forms["precision_coupled"] = time_to_1pct(pkg, torch, m, P, G, seed + 1, dtype,
                                                   "bf16x3" if dtype == "f32" else "fp64", "coupled",
                                                   xcd_order=order)
@@ -600,7 +607,7 @@ def main():
                 forms[k]["speedup_vs_plain"] = forms["plain_fp64"]["seconds"] / forms[k]["seconds"]
             forms["precision_coupled"]["speedup_vs_plain_coupled"] = \
                 forms["plain_fp64_coupled"]["seconds"] / forms["precision_coupled"]["seconds"]
-        log(f"time to 1%: {forms['precision']['seconds']:.2f} s (burn-in {w['burn_in']}), "
+        log(f"time to 1%: {forms['precision']['seconds']:.2f} s (burn-in {forms['precision']['burn_in']}), "
             f"{forms['precision_coupled']['seconds']:.3f} s (coupled burn-in, "
             f"{forms['precision_coupled']['burn_in']} sweeps), "
             f"{forms['precision_coupled_z2']['seconds']:.3f} s (Z2 noise, "
