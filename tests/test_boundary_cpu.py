@@ -125,3 +125,11 @@ def test_valid_csr_passes_the_host_checks():
         with pytest.raises(pkg.McinvError) as ei:   # validated, then no device
             pkg.mcinv_features(0, n, nnz, rp, col, val)
         assert ei.value.code == pkg.MCINV_EDEVICE
+
+
+def test_bench_refuses_several_gpus():
+    """The benchmark runs on one GPU; asking for more exits with a message."""
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr, (r.returncode, r.stderr[-300:])
