@@ -434,8 +434,9 @@ std::vector<double> slot_lengths(int64_t samples, int64_t L, int32_t nslots)
     return len;
 }
 
-// Estimates and SEs of every matrix's diagonal, each over its own samples;
-// with want_max, b->mrel receives each matrix's max se/|est|.
+// Estimates and SEs of every matrix's diagonal, each over its own samples
+// (into d_est / d_se); with want_max only each matrix's max se/|est|, into
+// b->mrel.
 mcinv_status finalize_diag_all(mcinv_batch* b, bool want_max)
 {
     std::vector<double> len((size_t)b->M * b->nslots_diag);
@@ -457,8 +458,8 @@ mcinv_status finalize_diag_all(mcinv_batch* b, bool want_max)
     f.out_index = b->d_orig;
     f.gstride = 1;
     f.mstride = b->G;
-    f.est = b->d_est;
-    f.se = b->d_se;
+    f.est = want_max ? nullptr : b->d_est;   // a stop check needs only the per-row ratios
+    f.se = want_max ? nullptr : b->d_se;
     f.val_group = b->d_row_mat;
     f.slot_len_stride = b->nslots_diag;
     f.rel_out = want_max ? b->d_rel : nullptr;

@@ -562,19 +562,24 @@ __global__ __launch_bounds__(256) void k_finalize_groups(const FinalizeArgs f)
     const bool has = ok && g == 0;
     double rel = 0.0;
     if (has) {
+        // est / se may be null (a stop check needs only rel): no scattered writes then
         const int64_t m = f.out_index ? f.out_index[v] : v;
         if (wsum <= 0.0) {
-            f.est[m * f.comps] = __builtin_nan("");
-            if (f.comps == 2) f.est[m * 2 + 1] = __builtin_nan("");
-            f.se[m] = __builtin_nan("");
+            if (f.est) {
+                f.est[m * f.comps] = __builtin_nan("");
+                if (f.comps == 2) f.est[m * 2 + 1] = __builtin_nan("");
+                f.se[m] = __builtin_nan("");
+            }
             rel = __builtin_inf();
         } else {
             const double mr = er / wsum, mi = ei / wsum;
             double se = __builtin_nan("");
             if (nc >= 2.0) se = sqrt((vr + vi) * (nc / (nc - 1.0))) / wsum;
-            f.est[m * f.comps] = mr;
-            if (f.comps == 2) f.est[m * 2 + 1] = mi;
-            f.se[m] = se;
+            if (f.est) {
+                f.est[m * f.comps] = mr;
+                if (f.comps == 2) f.est[m * 2 + 1] = mi;
+                f.se[m] = se;
+            }
             rel = rel_error(se, mr, mi);
         }
     }
