@@ -21,7 +21,8 @@
  *   - Noise scales satisfy a_i conj(b_i) = 1/c_ii: real c_ii: a = 1/sqrt|c_ii|,
  *     b = sign(c_ii) a; complex: a = 1/sqrt(c_ii) (principal), b = conj(a).
  *   - Noise for (row i, sweep k, pair p) is output (p mod 4) of Philox4x32-10
- *     with key (seed lo, seed hi) and counter (i, k, p div 4, stream_id), turned
+ *     with key (seed lo, seed hi) and counter (i, k, p div 4, stream_id), p the
+ *     global pair index (mcinv_config.pair_offset + the context's own), turned
  *     into N(0,1) by Box-Muller on u = ((x >> 9) + 1/2) 2^-23, or into +-1 (Z2
  *     noise: the sign bit), or 0 (the noiseless Gauss-Seidel of eq 12).
  *   - Complex values are interleaved (re, im) pairs of the stated precision.
@@ -109,6 +110,11 @@ typedef struct {
                               w = z at every step and only z is swept -- the
                               single-draw Gauss-Seidel sampler of eq 2, half the
                               state traffic.  w reads return z; w cannot be written */
+    int64_t  pair_offset;  /* global index of this context's first chain pair, a
+                              multiple of 4 (0 for a whole run): pair p draws the
+                              noise of pair pair_offset + p, so contexts that split
+                              one run's pairs between them (one per GPU) reproduce
+                              its chains; their moment sums add up to the run's */
 } mcinv_config;
 
 typedef struct {

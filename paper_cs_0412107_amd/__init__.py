@@ -44,7 +44,7 @@ class Sampler:
 
     def __init__(self, matrix, pairs, groups=1, dtype="f32", seed=0, noise=MCINV_NOISE_NORMAL,
                  moments="fp64", device=0, stream_id=0, use_torch_stream=False, profile=False, pass_tiles=0,
-                 hermitian=False, xcd_order=0):
+                 hermitian=False, xcd_order=0, pair_offset=0):
         self.dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
         self.is_complex = self.dtype in (DTYPES["c64"], DTYPES["c128"])
         mom = MCINV_MOMENTS_BF16X3 if moments == "bf16x3" else MCINV_MOMENTS_FP64
@@ -52,7 +52,7 @@ class Sampler:
         self.ctx = mcinv_create(device=device, sweep_dtype=self.dtype, moments=mom, noise=noise,
                                 n_pairs=pairs, n_groups=groups, stream_id=stream_id, seed=seed,
                                 stream=stream, profile=profile, pass_tiles=pass_tiles, hermitian=hermitian,
-                                xcd_order=xcd_order)
+                                xcd_order=xcd_order, pair_offset=pair_offset)
         self.n = matrix.n
         self.P = pairs
         self.nI = self.nJ = self.ne = 0

@@ -56,6 +56,7 @@ class mcinv_config(ctypes.Structure):
         ("pass_tiles", ctypes.c_int32),
         ("xcd_order", ctypes.c_int32),
         ("hermitian", ctypes.c_int32),
+        ("pair_offset", ctypes.c_int64),
     ]
 
 
@@ -212,10 +213,10 @@ def mcinv_last_error(ctx=None):
 
 def mcinv_create(device=0, sweep_dtype=MCINV_R32, moments=MCINV_MOMENTS_FP64, noise=MCINV_NOISE_NORMAL,
                  n_pairs=1, n_groups=1, stream_id=0, seed=0, stream=None, profile=False, pass_tiles=0,
-                 hermitian=False, xcd_order=0):
+                 hermitian=False, xcd_order=0, pair_offset=0):
     cfg = mcinv_config(device, sweep_dtype, moments, noise, n_pairs, n_groups, stream_id,
                        seed & 0xFFFFFFFFFFFFFFFF, stream, 1 if profile else 0, int(pass_tiles), int(xcd_order),
-                       1 if hermitian else 0)
+                       1 if hermitian else 0, int(pair_offset))
     h = ctypes.c_void_p()
     _check(None, lib().mcinv_create(ctypes.byref(cfg), ctypes.byref(h)))
     return h

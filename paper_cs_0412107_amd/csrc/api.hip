@@ -315,6 +315,7 @@ mcinv_status run_sweeps(mcinv_ctx* c, int64_t nsw, bool sample, V* z, V* w, int6
     a.key0 = (uint32_t)(c->cfg.seed & 0xffffffffu);
     a.key1 = (uint32_t)(c->cfg.seed >> 32);
     a.stream = c->cfg.stream_id;
+    a.pair_block0 = (uint32_t)(c->cfg.pair_offset >> 2);
     a.noise = noise;
     a.lg_shift = (int32_t)c->lg_shift;
     a.n = c->n;
@@ -573,6 +574,8 @@ mcinv_status mcinv_create(const mcinv_config* cfg, mcinv_ctx** out)
         return fail(nullptr, MCINV_EINVAL, "bf16x3 block moments need a real fp32 sweep");
     if (cfg->n_pairs < 1 || cfg->n_pairs > (int64_t)1 << 30) return fail(nullptr, MCINV_EINVAL, "n_pairs out of range");
     if (cfg->xcd_order < 0 || cfg->xcd_order > 2) return fail(nullptr, MCINV_EINVAL, "xcd_order must be 0, 1 or 2");
+    if (cfg->pair_offset < 0 || cfg->pair_offset % 4 != 0 || cfg->pair_offset + cfg->n_pairs > ((int64_t)1 << 34))
+        return fail(nullptr, MCINV_EINVAL, "pair_offset must be a non-negative multiple of 4 (pairs below 2^34)");
     const int64_t P = cfg->n_pairs, G = cfg->n_groups;
     if (G < 1 || P % G != 0) return fail(nullptr, MCINV_EINVAL, "n_groups must divide n_pairs");
     const int64_t gs = P / G;
@@ -1076,7 +1079,7 @@ struct CkptHeader {
     char magic[8];
     int64_t version, n, nnz, n_off, P, ld, G, dtype, hermitian, noise, stream_id;
     uint64_t seed, fingerprint;
-    int64_t flags, nI, nJ, ne, sweeps, samples, batch_len, nslots, q_nnz, requested;
+    int64_t flags, nI, nJ, ne, sweeps, samples, batch_len, nslots, q_nnz, requested, pair_offset;
 };
 
 }  // extern "C"
@@ -1126,7 +1129,7 @@ static mcinv_status save_body(mcinv_ctx* c, FILE* f)
 {
     CkptHeader hd{};
     std::memcpy(hd.magic, "MCINVCK1", 8);
-    hd.version = 1;
+    hd.version = 2;
     hd.n = c->n;
     hd.nnz = c->nnz;
     hd.n_off = c->n_off;
@@ -1138,6 +1141,7 @@ static mcinv_status save_body(mcinv_ctx* c, FILE* f)
     hd.noise = c->cfg.noise;
     hd.stream_id = c->cfg.stream_id;
     hd.seed = c->cfg.seed;
+    hd.pair_offset = c->cfg.pair_offset;
     hd.fingerprint = fingerprint(c);
     hd.flags = c->flags;
     hd.nI = c->nI;
@@ -1176,13 +1180,13 @@ static mcinv_status save_body(mcinv_ctx* c, FILE* f)
 static mcinv_status restore_body(mcinv_ctx* c, FILE* f)
 {
     CkptHeader hd{};
-    if (!read_all(f, &hd, sizeof(hd)) || std::memcmp(hd.magic, "MCINVCK1", 8) != 0 || hd.version != 1)
+    if (!read_all(f, &hd, sizeof(hd)) || std::memcmp(hd.magic, "MCINVCK1", 8) != 0 || hd.version != 2)
         return fail(c, MCINV_EINVAL, "not an mcinv checkpoint");
     if (hd.n != c->n || hd.nnz != c->nnz || hd.n_off != c->n_off || hd.fingerprint != fingerprint(c))
         return fail(c, MCINV_EINVAL, "checkpoint was taken on a different matrix");
     if (hd.P != c->P || hd.G != c->G || hd.dtype != c->cfg.sweep_dtype || hd.hermitian != (c->cfg.hermitian ? 1 : 0) ||
         hd.noise != c->cfg.noise || hd.stream_id != (int64_t)c->cfg.stream_id || hd.seed != c->cfg.seed ||
-        hd.nslots != c->nslots)
+        hd.nslots != c->nslots || hd.pair_offset != c->cfg.pair_offset)
         return fail(c, MCINV_EINVAL, "checkpoint was taken with a different configuration");
     if ((hd.flags & MCINV_REQ_QTRACE) && c->q_nnz != hd.q_nnz)
         return fail(c, MCINV_ESTATE, "set the same trace matrix Q before restoring");

@@ -25,6 +25,7 @@ struct SweepArgs {
     uint32_t key0, key1;     // Philox key = seed
     uint32_t sweep;          // Philox counter word 1
     uint32_t stream;         // Philox counter word 3
+    uint32_t pair_block0;    // global index of this context's first pair / 4 (Philox counter word 2 offset)
     int32_t noise;           // NoiseKind
     int32_t lg_shift;        // log2(lanes summed into one diagonal column)
     double* diag;            // slot accumulator [tiles][n][64 >> lg_shift] (x2 complex) or null

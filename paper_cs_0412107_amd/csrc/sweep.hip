@@ -153,7 +153,7 @@ __global__ __launch_bounds__(256) void k_sweep(const SweepArgs<V> a)
         }
 
         R phi[4];
-        noise4<R>(a.key0, a.key1, rr.orig, a.sweep, (uint32_t)(p0 >> 2), a.stream, a.noise, phi);
+        noise4<R>(a.key0, a.key1, rr.orig, a.sweep, a.pair_block0 + (uint32_t)(p0 >> 2), a.stream, a.noise, phi);
         const Scales<V> s = a.sc[q];
         Quad<V> zn, wn;
 #pragma unroll

@@ -420,6 +420,36 @@ def test_workgroup_orders_do_not_change_results(dtype, maker, P, G):
                 np.testing.assert_allclose(np.asarray(t), np.asarray(t0), rtol=1e-12)
 
 
+@pytest.mark.parametrize("dtype,maker", [("f32", lambda: gen.pedigree(3000, seed=61)),
+                                         ("c64", lambda: gen.lattice(6, k=0.12, seed=62))])
+def test_pair_split_reproduces_single_run(dtype, maker):
+    """How the pairs would shard over GPUs: two contexts holding pairs
+    [0, 256) and [256, 512) (pair_offset) reproduce one 512-pair run -- the
+    same chains bit for bit, and moments whose average is the run's -- and the
+    second half equals the oracle run on those global pair ids."""
+    print_case(test="pair_split", dtype=dtype)
+    m = oracle_matrix(maker(), dtype)
+    seed, S = 0x412107 + 23, 6
+    runs = []
+    for P, G, off in ((512, 16, 0), (256, 8, 0), (256, 8, 256)):
+        with _sampler(m, dtype, seed, P, G, pair_offset=off) as s:
+            s.burn_in(3)
+            s.request(diag=True, trace=True)
+            s.sample(S)
+            runs.append((s.state(0), s.state(1), s.diag()[0], s.trace()[0]))
+    whole, a, b = runs
+    for k in (0, 1):
+        assert np.array_equal(whole[k][:, :256], a[k]) and np.array_equal(whole[k][:, 256:], b[k])
+    np.testing.assert_allclose((a[2] + b[2]) / 2, whole[2], rtol=1e-12, atol=1e-15)
+    assert abs((a[3] + b[3]) / 2 - whole[3]) <= 1e-12 * abs(whole[3])
+    ora = make_oracle(m, dtype, seed, 256, pair_ids=np.arange(256, 512))
+    ora.burn_in(3 + S)
+    assert rel_err(b[0], ora.z) <= TOL[dtype] and rel_err(b[1], ora.w) <= TOL[dtype]
+    with pytest.raises(mc.McinvError) as ei:
+        _sampler(m, dtype, seed, 8, pair_offset=6)
+    assert ei.value.code == mc.MCINV_EINVAL
+
+
 def test_tune_launch_picks_the_fastest_order():
     """The tuner's sweeps are ordinary burn-in sweeps, each with its own noise."""
     m = oracle_matrix(gen.lattice(8, k=0.12, seed=96), "c64")
