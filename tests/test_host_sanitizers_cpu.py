@@ -1,6 +1,8 @@
-"""The library's host-side matrix preparation built with the address and
-undefined-behaviour sanitizers (host code only; no device code is compiled)
-and run on random, hub-shaped and invalid matrices (tests/host/prep_check.cpp)."""
+"""Host code under the address and undefined-behaviour sanitizers: the
+library's matrix preparation (host code only; no device code is compiled),
+run on random, hub-shaped and invalid matrices (tests/host/prep_check.cpp),
+and the oracle's C part through colouring, sweeps and every moment kind
+(tests/host/oracle_check.c)."""
 
 import os
 import shutil
@@ -25,5 +27,19 @@ def test_host_preparation_under_sanitizers(tmp_path):
     assert r.returncode == 0, r.stderr[-3000:]
     env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
     r = subprocess.run([exe], capture_output=True, text=True, timeout=600, env=env)
+    assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-4000:])
+    assert "0 failures" in r.stdout
+
+
+def test_oracle_under_sanitizers(tmp_path):
+    cc = shutil.which("gcc")
+    if cc is None:
+        pytest.skip("gcc not available")
+    exe = str(tmp_path / "oracle_check")
+    cmd = [cc, "-O1", "-g", "-std=c11", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+           os.path.join(ROOT, "tests", "host", "oracle_check.c"), "-o", exe, "-lm"]
+    r = subprocess.run(cmd, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr[-3000:]
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, (r.stdout[-2000:], r.stderr[-4000:])
     assert "0 failures" in r.stdout
