@@ -60,6 +60,9 @@ typedef int32_t mcinv_status;
 #define MCINV_EDEVICE    -5  /* a HIP runtime error                              */
 #define MCINV_EDIVERGED  -6  /* non-finite or runaway chain state: sp(T) or sp(S)
                                 is not below one (Sec. 2.2)                      */
+#define MCINV_EINTERNAL  -7  /* unexpected host-side failure (e.g. a worker
+                                thread could not start); no exception ever
+                                leaves the library                               */
 
 /* Sweep (state) precision. */
 #define MCINV_R32   0   /* real, float32 state            */
@@ -249,7 +252,8 @@ mcinv_status mcinv_set_trace_matrix(mcinv_ctx* ctx, int64_t nnz, const int64_t* 
  * the caller's responsibility) and, if the checkpoint requested
  * MCINV_REQ_QTRACE, the same Q set.  The restored context continues exactly
  * as the saved one would (same noise counters, same sums).  EINVAL on a
- * mismatch, an unreadable or truncated file. */
+ * mismatch or an unreadable file; a file whose counts or size do not match
+ * its header (damaged, truncated) is rejected before the context changes. */
 mcinv_status mcinv_save(mcinv_ctx* ctx, const char* path);
 mcinv_status mcinv_restore(mcinv_ctx* ctx, const char* path);
 

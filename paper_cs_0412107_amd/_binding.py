@@ -23,6 +23,7 @@ MCINV_ESTATE = -3
 MCINV_ENOMEM = -4
 MCINV_EDEVICE = -5
 MCINV_EDIVERGED = -6
+MCINV_EINTERNAL = -7
 
 MCINV_R32, MCINV_R64, MCINV_C64, MCINV_C128 = 0, 1, 2, 3
 MCINV_NOISE_NORMAL, MCINV_NOISE_RADEMACHER, MCINV_NOISE_NONE = 0, 1, 2

@@ -20,10 +20,12 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <vector>
 
 #include "../../include/mcinv.h"
+#include "boundary.h"
 #include "device_common.h"
 #include "prep.h"
 #include "coupling.h"
@@ -563,7 +565,7 @@ mcinv_status check_ready(mcinv_ctx* c)
 extern "C" {
 
 mcinv_status mcinv_create(const mcinv_config* cfg, mcinv_ctx** out)
-{
+try {
     if (!cfg || !out) return fail(nullptr, MCINV_EINVAL, "null argument");
     *out = nullptr;
     if (elem_size(cfg->sweep_dtype) == 0) return fail(nullptr, MCINV_EINVAL, "unknown sweep dtype");
@@ -589,7 +591,9 @@ mcinv_status mcinv_create(const mcinv_config* cfg, mcinv_ctx** out)
     if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev)
         return fail(nullptr, MCINV_EDEVICE, "no such HIP device");
 
-    mcinv_ctx* c = new mcinv_ctx();
+    // the owner destroys a partly built context on every early return or exception
+    std::unique_ptr<mcinv_ctx, void (*)(mcinv_ctx*)> owner(new mcinv_ctx(), mcinv_destroy);
+    mcinv_ctx* c = owner.get();
     c->cfg = *cfg;
     c->cplx = cfg->sweep_dtype == MCINV_C64 || cfg->sweep_dtype == MCINV_C128;
     c->comps = c->cplx ? 2 : 1;
@@ -611,7 +615,6 @@ mcinv_status mcinv_create(const mcinv_config* cfg, mcinv_ctx** out)
 
     auto bail = [&](mcinv_status s) {
         g_error = c->err;
-        mcinv_destroy(c);
         return s;
     };
     mcinv_status s = set_device(c);
@@ -632,8 +635,10 @@ mcinv_status mcinv_create(const mcinv_config* cfg, mcinv_ctx** out)
         hipMemsetAsync(c->d_counter, 0, sizeof(uint32_t), c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess)
         return bail(fail(c, MCINV_EDEVICE, "initial memset failed"));
-    *out = c;
+    *out = owner.release();
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { fail(nullptr, s_, m_); });
 }
 
 void mcinv_destroy(mcinv_ctx* c)
@@ -655,7 +660,7 @@ void mcinv_destroy(mcinv_ctx* c)
 
 mcinv_status mcinv_load_csr(mcinv_ctx* c, int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
                             const void* values, int32_t value_dtype)
-{
+try {
     if (!c) return fail(nullptr, MCINV_EINVAL, "null context");
     MC_TRY(set_device(c));
     if (value_dtype != MCINV_R64 && value_dtype != MCINV_C128)
@@ -723,12 +728,14 @@ mcinv_status mcinv_load_csr(mcinv_ctx* c, int64_t n, int64_t nnz, const int64_t*
     c->slot_len.assign(c->nslots, 0.0);
     c->loaded = true;
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { fail(c, s_, m_); });
 }
 
 mcinv_status mcinv_set_requested(mcinv_ctx* c, uint32_t flags, const int64_t* block_rows, int64_t n_block_rows,
                                  const int64_t* block_cols, int64_t n_block_cols, const int64_t* entry_i,
                                  const int64_t* entry_j, int64_t n_entries)
-{
+try {
     MC_TRY(check_ready(c));
     if (flags & ~(MCINV_REQ_DIAG | MCINV_REQ_TRACE | MCINV_REQ_BLOCK | MCINV_REQ_ENTRIES | MCINV_REQ_QTRACE))
         return fail(c, MCINV_EINVAL, "unknown request flag");
@@ -794,19 +801,23 @@ mcinv_status mcinv_set_requested(mcinv_ctx* c, uint32_t flags, const int64_t* bl
     c->slot_len.assign(c->nslots, 0.0);
     c->requested = true;
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { fail(c, s_, m_); });
 }
 
 mcinv_status mcinv_burn_in(mcinv_ctx* c, int64_t sweeps)
-{
+try {
     MC_TRY(check_ready(c));
     if (sweeps < 0) return fail(c, MCINV_EINVAL, "negative sweep count");
     MC_TRY(dispatch_sweeps(c, sweeps, false));
     c->sweeps += sweeps;
     return check_flag(c);
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { fail(c, s_, m_); });
 }
 
 mcinv_status mcinv_tune_launch(mcinv_ctx* c, int32_t sweeps_per_trial, int32_t* xcd_order, double* ms_orders)
-{
+try {
     MC_TRY(check_ready(c));
     if (sweeps_per_trial < 1) return fail(c, MCINV_EINVAL, "sweeps_per_trial must be >= 1");
     hipEvent_t e0, e1;
@@ -839,21 +850,25 @@ mcinv_status mcinv_tune_launch(mcinv_ctx* c, int32_t sweeps_per_trial, int32_t* 
     if (ms_orders)
         for (int order = 0; order < 3; ++order) ms_orders[order] = ms[order];
     return check_flag(c);
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { fail(c, s_, m_); });
 }
 
 mcinv_status mcinv_sample(mcinv_ctx* c, int64_t sweeps)
-{
+try {
     MC_TRY(check_ready(c));
     if (!c->requested) return fail(c, MCINV_ESTATE, "call mcinv_set_requested before sampling");
     if (sweeps < 0) return fail(c, MCINV_EINVAL, "negative sweep count");
     MC_TRY(dispatch_sweeps(c, sweeps, true));
     c->sweeps += sweeps;
     return check_flag(c);
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { fail(c, s_, m_); });
 }
 
 mcinv_status mcinv_sample_until(mcinv_ctx* c, double rel_se, int64_t max_sweeps, int64_t check_every,
                                 int64_t* sweeps_done, double* achieved)
-{
+try {
     constexpr int64_t kMinBatchLen = 16;
     MC_TRY(check_ready(c));
     if (!c->requested || !(c->flags & MCINV_REQ_DIAG))
@@ -880,11 +895,13 @@ mcinv_status mcinv_sample_until(mcinv_ctx* c, double rel_se, int64_t max_sweeps,
     if (sweeps_done) *sweeps_done = done;
     if (achieved) *achieved = maxrel;
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { fail(c, s_, m_); });
 }
 
 mcinv_status mcinv_sample_until_trace(mcinv_ctx* c, double rel_se, int64_t max_sweeps, int64_t check_every,
                                       int64_t* sweeps_done, double* achieved)
-{
+try {
     constexpr double kMinEffectiveSamples = 50.0;
     MC_TRY(check_ready(c));
     if (!c->requested || !(c->flags & (MCINV_REQ_TRACE | MCINV_REQ_QTRACE)))
@@ -915,10 +932,12 @@ mcinv_status mcinv_sample_until_trace(mcinv_ctx* c, double rel_se, int64_t max_s
     if (sweeps_done) *sweeps_done = done;
     if (achieved) *achieved = rel;
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { fail(c, s_, m_); });
 }
 
 mcinv_status mcinv_read_estimates(mcinv_ctx* c, uint32_t quantity, double* est, double* stderr_, int64_t capacity)
-{
+try {
     MC_TRY(check_ready(c));
     if (!c->requested || !(c->flags & quantity)) return fail(c, MCINV_ESTATE, "quantity was not requested");
     int64_t M = 0;
@@ -956,10 +975,12 @@ mcinv_status mcinv_read_estimates(mcinv_ctx* c, uint32_t quantity, double* est, 
     if (stderr_) HIP_TRY(c, hipMemcpyAsync(stderr_, c->d_se, sizeof(double) * M, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { fail(c, s_, m_); });
 }
 
 mcinv_status mcinv_read_state(mcinv_ctx* c, int32_t which, void* host, int64_t bytes)
-{
+try {
     MC_TRY(check_ready(c));
     if (which != 0 && which != 1) return fail(c, MCINV_EINVAL, "which must be 0 (z) or 1 (w)");
     if (!host || bytes < c->n * c->P * (int64_t)c->elem) return fail(c, MCINV_EINVAL, "host buffer too small");
@@ -971,10 +992,12 @@ mcinv_status mcinv_read_state(mcinv_ctx* c, int32_t which, void* host, int64_t b
     for (int64_t i = 0; i < c->n; ++i)
         std::memcpy(out + (size_t)i * row_bytes, tmp.data() + (size_t)c->pos[i] * c->ld * c->elem, row_bytes);
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { fail(c, s_, m_); });
 }
 
 mcinv_status mcinv_write_state(mcinv_ctx* c, int32_t which, const void* host, int64_t bytes)
-{
+try {
     MC_TRY(check_ready(c));
     if (which != 0 && which != 1) return fail(c, MCINV_EINVAL, "which must be 0 (z) or 1 (w)");
     if (!host || bytes < c->n * c->P * (int64_t)c->elem) return fail(c, MCINV_EINVAL, "host buffer too small");
@@ -987,6 +1010,8 @@ mcinv_status mcinv_write_state(mcinv_ctx* c, int32_t which, const void* host, in
     HIP_TRY(c, hipMemcpyAsync(which ? c->d_w : c->d_z, tmp.data(), tmp.size(), hipMemcpyHostToDevice, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { fail(c, s_, m_); });
 }
 
 }  // extern "C"
@@ -1013,7 +1038,7 @@ extern "C" {
 
 mcinv_status mcinv_set_trace_matrix(mcinv_ctx* c, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
                                     const void* values, int32_t value_dtype)
-{
+try {
     MC_TRY(check_ready(c));
     if (c->requested && (c->flags & MCINV_REQ_QTRACE))
         return fail(c, MCINV_ESTATE, "Q cannot change while MCINV_REQ_QTRACE is requested");
@@ -1050,10 +1075,12 @@ mcinv_status mcinv_set_trace_matrix(mcinv_ctx* c, int64_t nnz, const int64_t* ro
     }
     c->q_nnz = nnz;
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { fail(c, s_, m_); });
 }
 
 mcinv_status mcinv_set_stop_rows(mcinv_ctx* c, const int64_t* rows, int64_t count)
-{
+try {
     MC_TRY(check_ready(c));
     if (count < 0 || (count > 0 && !rows)) return fail(c, MCINV_EINVAL, "bad stop-row list");
     std::vector<uint8_t> mask;
@@ -1068,6 +1095,8 @@ mcinv_status mcinv_set_stop_rows(mcinv_ctx* c, const int64_t* rows, int64_t coun
     dfree(c->d_stop);
     if (count > 0) MC_TRY(upload(c, &c->d_stop, mask));
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { fail(c, s_, m_); });
 }
 
 // ------------------------------------------------------------ checkpoint --
@@ -1190,6 +1219,35 @@ static mcinv_status restore_body(mcinv_ctx* c, FILE* f)
         return fail(c, MCINV_EINVAL, "checkpoint was taken with a different configuration");
     if ((hd.flags & MCINV_REQ_QTRACE) && c->q_nnz != hd.q_nnz)
         return fail(c, MCINV_ESTATE, "set the same trace matrix Q before restoring");
+    // Counts from the file size host buffers below: each must be non-negative
+    // and its bytes must still be in the file, so a corrupt header fails here
+    // instead of asking for a huge allocation.
+    const long here = std::ftell(f);
+    if (here < 0 || std::fseek(f, 0, SEEK_END) != 0) return fail(c, MCINV_EINVAL, "checkpoint file is not seekable");
+    const long end = std::ftell(f);
+    if (end < here || std::fseek(f, here, SEEK_SET) != 0) return fail(c, MCINV_EINVAL, "checkpoint file is not seekable");
+    const int64_t words_left = (int64_t)(end - here) / 8;
+    if (hd.nI < 0 || hd.nI > c->n || hd.nJ < 0 || hd.nJ > c->n || hd.ne < 0 || hd.ne > words_left ||
+        hd.samples < 0 || hd.samples > hd.sweeps || hd.samples > words_left || hd.batch_len < 0 ||
+        hd.nslots + hd.nI + hd.nJ + 2 * hd.ne > words_left)
+        return fail(c, MCINV_EINVAL, "corrupt or truncated checkpoint (counts do not fit the file)");
+    {
+        // the exact size the header implies, so that a damaged file fails
+        // before anything in the context changes
+        using i128 = __int128;
+        const i128 comps = c->comps, slots = hd.nslots;
+        i128 bytes = 8 * ((i128)hd.nslots + hd.nI + hd.nJ + 2 * (i128)hd.ne);
+        bytes += (i128)c->n * c->ld * c->elem * (c->cfg.hermitian ? 1 : 2);
+        if (hd.requested) {
+            if (hd.flags & MCINV_REQ_DIAG) bytes += 8 * slots * c->diag_slot_stride();
+            if (hd.flags & MCINV_REQ_BLOCK) bytes += 8 * slots * c->G * (i128)hd.nI * hd.nJ * comps;
+            if (hd.flags & MCINV_REQ_ENTRIES) bytes += 8 * slots * c->G * (i128)hd.ne * comps;
+            if (hd.flags & MCINV_REQ_TRACE) bytes += 8 * (i128)hd.samples * comps;
+            if (hd.flags & MCINV_REQ_QTRACE) bytes += 8 * (i128)hd.samples * comps;
+        }
+        if (bytes != (i128)(end - here))
+            return fail(c, MCINV_EINVAL, "corrupt or truncated checkpoint (size does not match its header)");
+    }
     std::vector<double> slot_len((size_t)hd.nslots);
     if (!read_all(f, slot_len.data(), sizeof(double) * slot_len.size()))
         return fail(c, MCINV_EINVAL, "checkpoint file is truncated");
@@ -1240,7 +1298,7 @@ static mcinv_status restore_body(mcinv_ctx* c, FILE* f)
 extern "C" {
 
 mcinv_status mcinv_save(mcinv_ctx* c, const char* path)
-{
+try {
     MC_TRY(check_ready(c));
     if (!path) return fail(c, MCINV_EINVAL, "null path");
     FILE* f = std::fopen(path, "wb");
@@ -1248,10 +1306,12 @@ mcinv_status mcinv_save(mcinv_ctx* c, const char* path)
     const mcinv_status s = save_body(c, f);
     if (std::fclose(f) != 0 && s == MCINV_OK) return fail(c, MCINV_EINVAL, "checkpoint write failed");
     return s;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { fail(c, s_, m_); });
 }
 
 mcinv_status mcinv_restore(mcinv_ctx* c, const char* path)
-{
+try {
     MC_TRY(check_ready(c));
     if (!path) return fail(c, MCINV_EINVAL, "null path");
     FILE* f = std::fopen(path, "rb");
@@ -1259,14 +1319,18 @@ mcinv_status mcinv_restore(mcinv_ctx* c, const char* path)
     const mcinv_status s = restore_body(c, f);
     std::fclose(f);
     return s;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { fail(c, s_, m_); });
 }
 
 mcinv_status mcinv_get_permutation(mcinv_ctx* c, int64_t* perm, int32_t* color_of_row)
-{
+try {
     MC_TRY(check_ready(c));
     if (perm) std::memcpy(perm, c->perm.data(), sizeof(int64_t) * c->n);
     if (color_of_row) std::memcpy(color_of_row, c->color.data(), sizeof(int32_t) * c->n);
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { fail(c, s_, m_); });
 }
 
 // The difference of two coupled paths (same noise, starts 0 and x*_i = i,
@@ -1351,7 +1415,7 @@ extern "C" {
 
 mcinv_status mcinv_burn_in_coupled(mcinv_ctx* c, double tol, int64_t max_sweeps, int64_t* sweeps_done,
                                    double* diff_z, double* diff_w)
-{
+try {
     MC_TRY(check_ready(c));
     if (!(tol > 0.0) || max_sweeps < 0) return fail(c, MCINV_EINVAL, "tol must be > 0 and max_sweeps >= 0");
     // one difference value per row (ld = 1): x*_i - 0 with x*_i = i, 1-based
@@ -1400,10 +1464,12 @@ mcinv_status mcinv_burn_in_coupled(mcinv_ctx* c, double tol, int64_t max_sweeps,
     if (diff_z) *diff_z = dzm;
     if (diff_w) *diff_w = dwm;
     return check_flag(c);
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { fail(c, s_, m_); });
 }
 
 mcinv_status mcinv_check_convergence(mcinv_ctx* c, int64_t iters, double* rho_T, double* rho_S)
-{
+try {
     MC_TRY(check_ready(c));
     if (iters < 2) return fail(c, MCINV_EINVAL, "iters must be >= 2");
     const int64_t ld = 4;
@@ -1464,10 +1530,12 @@ mcinv_status mcinv_check_convergence(mcinv_ctx* c, int64_t iters, double* rho_T,
     if (rho_T) *rho_T = rate(z1, z2);
     if (rho_S) *rho_S = rate(w1, w2);
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { fail(c, s_, m_); });
 }
 
 mcinv_status mcinv_get_info(mcinv_ctx* c, mcinv_info* out)
-{
+try {
     if (!c || !out) return fail(c, MCINV_EINVAL, "null argument");
     std::memset(out, 0, sizeof(*out));
     out->n = c->n;
@@ -1486,20 +1554,24 @@ mcinv_status mcinv_get_info(mcinv_ctx* c, mcinv_info* out)
     out->moment_kernel_ms = c->moment_ms;
     out->moment_kernel_launches = c->moment_launches;
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { fail(c, s_, m_); });
 }
 
 mcinv_status mcinv_reset_profile(mcinv_ctx* c)
-{
+try {
     if (!c) return fail(nullptr, MCINV_EINVAL, "null context");
     c->sweep_ms = c->moment_ms = 0.0;
     c->sweep_launches = c->moment_launches = 0;
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { fail(c, s_, m_); });
 }
 
 mcinv_status mcinv_noise_values(int32_t device, uint64_t seed, uint32_t stream_id, int32_t noise, int32_t dtype,
                                 int64_t count, const int64_t* row, const int64_t* sweep, const int64_t* pair,
                                 double* out)
-{
+try {
     if (count < 0 || (count > 0 && (!row || !sweep || !pair || !out)))
         return fail(nullptr, MCINV_EINVAL, "bad arguments");
     if (dtype != MCINV_R32 && dtype != MCINV_R64) return fail(nullptr, MCINV_EINVAL, "dtype must be R32 or R64");
@@ -1524,6 +1596,8 @@ mcinv_status mcinv_noise_values(int32_t device, uint64_t seed, uint32_t stream_i
     (void)hipFree(dout);
     if (e != hipSuccess) return fail(nullptr, MCINV_EDEVICE, std::string("noise kernel: ") + hipGetErrorString(e));
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { fail(nullptr, s_, m_); });
 }
 
 const char* mcinv_last_error(const mcinv_ctx* c)

@@ -15,11 +15,13 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <string>
 #include <utility>
 #include <vector>
 
 #include "../../include/mcinv.h"
+#include "boundary.h"
 #include "batch.h"
 #include "device_common.h"
 #include "prep.h"
@@ -484,7 +486,7 @@ mcinv_status check_batch(mcinv_batch* b)
 extern "C" {
 
 mcinv_status mcinv_batch_create(const mcinv_batch_config* cfg, int64_t n_matrices, mcinv_batch** out)
-{
+try {
     if (!cfg || !out) return bfail(nullptr, MCINV_EINVAL, "null argument");
     *out = nullptr;
     const int32_t P = (int32_t)cfg->n_pairs;
@@ -501,7 +503,9 @@ mcinv_status mcinv_batch_create(const mcinv_batch_config* cfg, int64_t n_matrice
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || cfg->device < 0 || cfg->device >= ndev)
         return bfail(nullptr, MCINV_EDEVICE, "no such HIP device");
-    mcinv_batch* b = new mcinv_batch();
+    // the owner destroys a partly built context on every early return or exception
+    std::unique_ptr<mcinv_batch, void (*)(mcinv_batch*)> owner(new mcinv_batch(), mcinv_batch_destroy);
+    mcinv_batch* b = owner.get();
     b->cfg = *cfg;
     b->M = n_matrices;
     b->P = P;
@@ -516,7 +520,6 @@ mcinv_status mcinv_batch_create(const mcinv_batch_config* cfg, int64_t n_matrice
     if (cfg->grab > 0) b->grab = cfg->grab;
     auto bail = [&](const char* msg) {
         g_berror = msg;
-        mcinv_batch_destroy(b);
         return MCINV_EDEVICE;
     };
     if (hipSetDevice(cfg->device) != hipSuccess) return bail("hipSetDevice failed");
@@ -537,8 +540,10 @@ mcinv_status mcinv_batch_create(const mcinv_batch_config* cfg, int64_t n_matrice
         hipMemsetAsync(b->d_flag, 0, sizeof(int32_t), b->stream) != hipSuccess ||
         hipStreamSynchronize(b->stream) != hipSuccess)
         return bail("initial memset failed");
-    *out = b;
+    *out = owner.release();
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { bfail(nullptr, s_, m_); });
 }
 
 void mcinv_batch_destroy(mcinv_batch* b)
@@ -577,7 +582,7 @@ void mcinv_batch_destroy(mcinv_batch* b)
 
 mcinv_status mcinv_batch_load_csr(mcinv_batch* b, int64_t m, int64_t n, int64_t nnz, const int64_t* row_ptr,
                                   const int32_t* col_idx, const double* values)
-{
+try {
     if (!b) return bfail(nullptr, MCINV_EINVAL, "null batch");
     if (b->committed) return bfail(b, MCINV_ESTATE, "the batch is already committed (first sweep ran)");
     if (m < 0 || m >= b->M) return bfail(b, MCINV_EINVAL, "matrix index out of range");
@@ -587,10 +592,12 @@ mcinv_status mcinv_batch_load_csr(mcinv_batch* b, int64_t m, int64_t n, int64_t 
         return bfail(b, singular ? MCINV_ESINGULAR : MCINV_EINVAL, "matrix " + std::to_string(m) + ": " + why);
     b->loaded[m] = true;
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { bfail(b, s_, m_); });
 }
 
 mcinv_status mcinv_batch_set_requested(mcinv_batch* b, uint32_t flags, int32_t block_dim, int64_t expected_samples)
-{
+try {
     BTRY(check_batch(b));
     if (flags & ~(MCINV_REQ_DIAG | MCINV_REQ_BLOCK))
         return bfail(b, MCINV_EINVAL, "the batched form estimates the diagonal and a block");
@@ -645,10 +652,12 @@ mcinv_status mcinv_batch_set_requested(mcinv_batch* b, uint32_t flags, int32_t b
     BHIP(b, hipStreamSynchronize(b->stream));
     b->requested = true;
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { bfail(b, s_, m_); });
 }
 
 mcinv_status mcinv_batch_set_block(mcinv_batch* b, int64_t m, const int64_t* rows, const int64_t* cols)
-{
+try {
     BTRY(check_batch(b));
     if (!b->requested || b->bdim == 0) return bfail(b, MCINV_ESTATE, "request MCINV_REQ_BLOCK first");
     if (m < 0 || m >= b->M || !rows || !cols) return bfail(b, MCINV_EINVAL, "bad arguments");
@@ -665,10 +674,12 @@ mcinv_status mcinv_batch_set_block(mcinv_batch* b, int64_t m, const int64_t* row
                            hipMemcpyHostToDevice, b->stream));
     BHIP(b, hipStreamSynchronize(b->stream));
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { bfail(b, s_, m_); });
 }
 
 mcinv_status mcinv_batch_burn_in(mcinv_batch* b, int64_t sweeps)
-{
+try {
     BTRY(check_batch(b));
     if (sweeps < 0) return bfail(b, MCINV_EINVAL, "negative sweep count");
     hipEvent_t e0, e1;
@@ -684,11 +695,13 @@ mcinv_status mcinv_batch_burn_in(mcinv_batch* b, int64_t sweeps)
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { bfail(b, s_, m_); });
 }
 
 mcinv_status mcinv_batch_burn_in_coupled(mcinv_batch* b, double tol, int64_t max_sweeps, int64_t* sweeps_done,
                                          double* max_diff)
-{
+try {
     BTRY(check_batch(b));
     if (!(tol > 0.0) || max_sweeps < 0) return bfail(b, MCINV_EINVAL, "tol must be > 0 and max_sweeps >= 0");
     // Difference chains of every matrix (eq 12: noiseless Gauss-Seidel from
@@ -774,10 +787,12 @@ mcinv_status mcinv_batch_burn_in_coupled(mcinv_batch* b, double tol, int64_t max
     if (sweeps_done) *sweeps_done = N;
     if (max_diff) *max_diff = worst;
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { bfail(b, s_, m_); });
 }
 
 mcinv_status mcinv_batch_sample(mcinv_batch* b, int64_t sweeps)
-{
+try {
     BTRY(check_batch(b));
     if (!b->requested) return bfail(b, MCINV_ESTATE, "call mcinv_batch_set_requested before sampling");
     if (sweeps < 0) return bfail(b, MCINV_EINVAL, "negative sweep count");
@@ -794,11 +809,13 @@ mcinv_status mcinv_batch_sample(mcinv_batch* b, int64_t sweeps)
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { bfail(b, s_, m_); });
 }
 
 mcinv_status mcinv_batch_sample_until(mcinv_batch* b, double rel_se, int64_t max_sweeps, int64_t check_every,
                                       int64_t* sweeps_done, double* achieved)
-{
+try {
     BTRY(check_batch(b));
     if (!b->requested || !(b->flags & MCINV_REQ_DIAG))
         return bfail(b, MCINV_ESTATE, "sample_until needs MCINV_REQ_DIAG requested");
@@ -817,11 +834,13 @@ mcinv_status mcinv_batch_sample_until(mcinv_batch* b, double rel_se, int64_t max
     if (sweeps_done) *sweeps_done = done;
     if (achieved) *achieved = maxrel;
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { bfail(b, s_, m_); });
 }
 
 mcinv_status mcinv_batch_sample_until_each(mcinv_batch* b, double rel_se, int64_t max_sweeps, int64_t check_every,
                                            int64_t* sweeps_done, double* achieved)
-{
+try {
     BTRY(check_batch(b));
     if (!b->requested || !(b->flags & MCINV_REQ_DIAG))
         return bfail(b, MCINV_ESTATE, "sample_until_each needs MCINV_REQ_DIAG requested");
@@ -854,19 +873,23 @@ mcinv_status mcinv_batch_sample_until_each(mcinv_batch* b, double rel_se, int64_
     if (sweeps_done) *sweeps_done = done;
     if (achieved) *achieved = *std::max_element(b->mrel.begin(), b->mrel.end());
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { bfail(b, s_, m_); });
 }
 
 mcinv_status mcinv_batch_matrix_samples(mcinv_batch* b, int64_t* samples, uint8_t* active)
-{
+try {
     BTRY(check_batch(b));
     if (samples) std::copy(b->msamples.begin(), b->msamples.end(), samples);
     if (active) std::copy(b->active.begin(), b->active.end(), active);
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { bfail(b, s_, m_); });
 }
 
 mcinv_status mcinv_batch_read_estimates(mcinv_batch* b, int64_t m, uint32_t quantity, double* est, double* stderr_,
                                         int64_t capacity)
-{
+try {
     BTRY(check_batch(b));
     if (m < 0 || m >= b->M) return bfail(b, MCINV_EINVAL, "matrix index out of range");
     if (!b->requested || !(b->flags & quantity)) return bfail(b, MCINV_ESTATE, "quantity was not requested");
@@ -902,10 +925,12 @@ mcinv_status mcinv_batch_read_estimates(mcinv_batch* b, int64_t m, uint32_t quan
         BHIP(b, hipMemcpyAsync(stderr_, b->d_se + offset, sizeof(double) * count, hipMemcpyDeviceToHost, b->stream));
     BHIP(b, hipStreamSynchronize(b->stream));
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { bfail(b, s_, m_); });
 }
 
 mcinv_status mcinv_batch_read_state(mcinv_batch* b, int64_t m, int32_t which, float* host, int64_t bytes)
-{
+try {
     BTRY(check_batch(b));
     if (m < 0 || m >= b->M || (which != 0 && which != 1) || !host) return bfail(b, MCINV_EINVAL, "bad arguments");
     const int64_t n = b->prep[m].n;
@@ -917,11 +942,13 @@ mcinv_status mcinv_batch_read_state(mcinv_batch* b, int64_t m, int32_t which, fl
     for (int64_t i = 0; i < n; ++i)
         std::memcpy(host + i * b->P, tmp.data() + b->prep[m].pos[i] * b->P, sizeof(float) * b->P);
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { bfail(b, s_, m_); });
 }
 
 mcinv_status mcinv_batch_autotune(mcinv_batch* b, int32_t sweeps_per_trial, int32_t* schedule,
                                   int32_t* rows_per_item, int32_t* grab, double* ms_per_sweep)
-{
+try {
     BTRY(check_batch(b));
     if (sweeps_per_trial < 1) return bfail(b, MCINV_EINVAL, "sweeps_per_trial must be >= 1");
     const int32_t rows_c[] = {16, 32, 64, 128, 256, 512, 1024};
@@ -971,10 +998,12 @@ mcinv_status mcinv_batch_autotune(mcinv_batch* b, int32_t sweeps_per_trial, int3
     if (grab) *grab = best_g;
     if (ms_per_sweep) *ms_per_sweep = best;
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { bfail(b, s_, m_); });
 }
 
 mcinv_status mcinv_batch_get_info(mcinv_batch* b, mcinv_batch_info* out)
-{
+try {
     if (!b || !out) return bfail(b, MCINV_EINVAL, "null argument");
     std::memset(out, 0, sizeof(*out));
     out->n_matrices = b->M;
@@ -992,6 +1021,8 @@ mcinv_status mcinv_batch_get_info(mcinv_batch* b, mcinv_batch_info* out)
     out->samples_done = b->samples;
     out->last_call_ms = b->last_ms;
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { bfail(b, s_, m_); });
 }
 
 const char* mcinv_batch_last_error(const mcinv_batch* b)

@@ -15,6 +15,7 @@
 #include <vector>
 
 #include "../../include/mcinv.h"
+#include "boundary.h"
 #include "prep.h"
 
 namespace mcinv {
@@ -169,7 +170,7 @@ using namespace mcinv;
 
 extern "C" mcinv_status mcinv_features(int32_t device, int64_t n, int64_t nnz, const int64_t* row_ptr,
                                        const int32_t* col_idx, const double* values, float* out)
-{
+try {
     if (!out) {
         set_context_free_error("mcinv_features: null output");
         return MCINV_EINVAL;
@@ -265,4 +266,6 @@ extern "C" mcinv_status mcinv_features(int32_t device, int64_t n, int64_t nnz, c
         return e == hipErrorOutOfMemory ? MCINV_ENOMEM : MCINV_EDEVICE;
     }
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status, const std::string& m_) { set_context_free_error(m_); });
 }

@@ -16,10 +16,12 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <vector>
 
 #include "../../include/mcinv.h"
+#include "boundary.h"
 
 struct mcinv_gate {
     mcinv_gate_config cfg{};
@@ -66,7 +68,7 @@ extern "C" {
 
 mcinv_status mcinv_gate_fit(const mcinv_gate_config* cfg, int64_t N, const float* X, const double* pred,
                             const double* y, const double* y_se, mcinv_gate** out)
-{
+try {
     if (!cfg || !X || !pred || !y || !y_se || !out || N < 1) {
         set_err("mcinv_gate_fit: null argument or no rows");
         return MCINV_EINVAL;
@@ -85,7 +87,8 @@ mcinv_status mcinv_gate_fit(const mcinv_gate_config* cfg, int64_t N, const float
                     std::to_string(i));
             return MCINV_EINVAL;
         }
-    mcinv_gate* g = new mcinv_gate();
+    std::unique_ptr<mcinv_gate> owner(new mcinv_gate());
+    mcinv_gate* g = owner.get();
     g->cfg = *cfg;
     const int32_t B = cfg->bins;
     g->ea = quantile_edges(X, N, cfg->feature_a, B);
@@ -110,12 +113,14 @@ mcinv_status mcinv_gate_fit(const mcinv_gate_config* cfg, int64_t N, const float
         }
         g->fallback[b] = (g->count[b] < cfg->min_rows || !(g->err[b] <= cfg->tol)) ? 1 : 0;
     }
-    *out = g;
+    *out = owner.release();
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status, const std::string& m_) { set_err(m_); });
 }
 
 mcinv_status mcinv_gate_apply(const mcinv_gate* g, int64_t N, const float* X, uint8_t* fallback)
-{
+try {
     if (!g || (N > 0 && (!X || !fallback)) || N < 0) {
         set_err("mcinv_gate_apply: bad arguments");
         return MCINV_EINVAL;
@@ -131,11 +136,13 @@ mcinv_status mcinv_gate_apply(const mcinv_gate* g, int64_t N, const float* X, ui
         fallback[i] = g->fallback[(size_t)(bin_of(g->ea, xa) * B + bin_of(g->eb, xb))];
     }
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status, const std::string& m_) { set_err(m_); });
 }
 
 mcinv_status mcinv_gate_read(const mcinv_gate* g, double* edges_a, double* edges_b, double* bin_err,
                              int64_t* bin_count, uint8_t* bin_fallback)
-{
+try {
     if (!g) {
         set_err("mcinv_gate_read: null gate");
         return MCINV_EINVAL;
@@ -146,6 +153,8 @@ mcinv_status mcinv_gate_read(const mcinv_gate* g, double* edges_a, double* edges
     if (bin_count) std::memcpy(bin_count, g->count.data(), sizeof(int64_t) * g->count.size());
     if (bin_fallback) std::memcpy(bin_fallback, g->fallback.data(), g->fallback.size());
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status, const std::string& m_) { set_err(m_); });
 }
 
 void mcinv_gate_destroy(mcinv_gate* g) { delete g; }

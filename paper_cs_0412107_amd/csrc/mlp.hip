@@ -24,10 +24,12 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <vector>
 
 #include "../../include/mcinv.h"
+#include "boundary.h"
 #include "device_common.h"
 #include "mfma_tile.h"
 
@@ -599,14 +601,15 @@ mcinv_status run_step(mcinv_mlp* m, int32_t R, bool apply, float lr, float* loss
 extern "C" {
 
 mcinv_status mcinv_mlp_create(int32_t device, mcinv_mlp** out)
-{
+try {
     if (!out) return merr(nullptr, MCINV_EINVAL, "null argument");
     *out = nullptr;
     if (hipSetDevice(device) != hipSuccess) return merr(nullptr, MCINV_EDEVICE, "no such device");
-    mcinv_mlp* m = new mcinv_mlp();
+    // the owner destroys a partly built network on every early return or exception
+    std::unique_ptr<mcinv_mlp, void (*)(mcinv_mlp*)> owner(new mcinv_mlp(), mcinv_mlp_destroy);
+    mcinv_mlp* m = owner.get();
     m->device = device;
     auto fail_alloc = [&]() {
-        mcinv_mlp_destroy(m);
         return merr(nullptr, MCINV_ENOMEM, "device allocation failed");
     };
     if (hipStreamCreate(&m->stream) != hipSuccess) return fail_alloc();
@@ -629,8 +632,10 @@ mcinv_status mcinv_mlp_create(int32_t device, mcinv_mlp** out)
         hipMemcpy(m->mean, zero.data(), sizeof(float) * kF, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(m->inv_std, one.data(), sizeof(float) * kF, hipMemcpyHostToDevice) != hipSuccess)
         return fail_alloc();
-    *out = m;
+    *out = owner.release();
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { merr(nullptr, s_, m_); });
 }
 
 void mcinv_mlp_destroy(mcinv_mlp* m)
@@ -664,7 +669,7 @@ void mcinv_mlp_destroy(mcinv_mlp* m)
 }
 
 mcinv_status mcinv_mlp_set_params(mcinv_mlp* m, const float* params)
-{
+try {
     if (!m || !params) return merr(m, MCINV_EINVAL, "null argument");
     MHIP(m, hipSetDevice(m->device));
     MHIP(m, hipMemcpyAsync(m->P, params, sizeof(float) * kParams, hipMemcpyHostToDevice, m->stream));
@@ -675,29 +680,35 @@ mcinv_status mcinv_mlp_set_params(mcinv_mlp* m, const float* params)
     MHIP(m, hipStreamSynchronize(m->stream));
     m->t = 0;
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { merr(m, s_, m_); });
 }
 
 mcinv_status mcinv_mlp_get_params(mcinv_mlp* m, float* params)
-{
+try {
     if (!m || !params) return merr(m, MCINV_EINVAL, "null argument");
     MHIP(m, hipSetDevice(m->device));
     MHIP(m, hipMemcpyAsync(params, m->P, sizeof(float) * kParams, hipMemcpyDeviceToHost, m->stream));
     MHIP(m, hipStreamSynchronize(m->stream));
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { merr(m, s_, m_); });
 }
 
 mcinv_status mcinv_mlp_set_normalization(mcinv_mlp* m, const float* mean, const float* inv_std)
-{
+try {
     if (!m || !mean || !inv_std) return merr(m, MCINV_EINVAL, "null argument");
     MHIP(m, hipSetDevice(m->device));
     MHIP(m, hipMemcpyAsync(m->mean, mean, sizeof(float) * kF, hipMemcpyHostToDevice, m->stream));
     MHIP(m, hipMemcpyAsync(m->inv_std, inv_std, sizeof(float) * kF, hipMemcpyHostToDevice, m->stream));
     MHIP(m, hipStreamSynchronize(m->stream));
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { merr(m, s_, m_); });
 }
 
 mcinv_status mcinv_mlp_set_data(mcinv_mlp* m, const float* X, const float* y, const float* w, int64_t N)
-{
+try {
     if (!m || !X || !y || !w || N < 1) return merr(m, MCINV_EINVAL, "bad arguments");
     MHIP(m, hipSetDevice(m->device));
     mfree(m->X);
@@ -712,10 +723,12 @@ mcinv_status mcinv_mlp_set_data(mcinv_mlp* m, const float* X, const float* y, co
     MHIP(m, hipStreamSynchronize(m->stream));
     m->N = N;
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { merr(m, s_, m_); });
 }
 
 mcinv_status mcinv_mlp_fit_normalization(mcinv_mlp* m, float* mean_out, float* inv_std_out)
-{
+try {
     if (!m) return merr(m, MCINV_EINVAL, "null argument");
     if (m->N < 1) return merr(m, MCINV_ESTATE, "no training data");
     MHIP(m, hipSetDevice(m->device));
@@ -739,10 +752,12 @@ mcinv_status mcinv_mlp_fit_normalization(mcinv_mlp* m, float* mean_out, float* i
     if (mean_out) std::memcpy(mean_out, mean, sizeof(mean));
     if (inv_std_out) std::memcpy(inv_std_out, inv, sizeof(inv));
     return mcinv_mlp_set_normalization(m, mean, inv);
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { merr(m, s_, m_); });
 }
 
 mcinv_status mcinv_mlp_label_weights(int64_t N, const double* y_se, double eps, float* w)
-{
+try {
     if (N < 1 || !y_se || !w || !(eps > 0.0)) return merr(nullptr, MCINV_EINVAL, "bad arguments");
     std::vector<double> raw(N);
     double s = 0.0;
@@ -755,10 +770,12 @@ mcinv_status mcinv_mlp_label_weights(int64_t N, const double* y_se, double eps, 
     const double scale = (double)N / s;
     for (int64_t i = 0; i < N; ++i) w[i] = (float)(raw[i] * scale);
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { merr(nullptr, s_, m_); });
 }
 
 mcinv_status mcinv_mlp_gradients(mcinv_mlp* m, const int64_t* rows, int32_t nrows, float* grads, float* loss)
-{
+try {
     if (!m || !rows || !grads) return merr(m, MCINV_EINVAL, "null argument");
     if (nrows < 64 || nrows % 64 != 0) return merr(m, MCINV_EINVAL, "nrows must be a positive multiple of 64");
     if (m->N < 1) return merr(m, MCINV_ESTATE, "no training data");
@@ -778,11 +795,13 @@ mcinv_status mcinv_mlp_gradients(mcinv_mlp* m, const int64_t* rows, int32_t nrow
     MHIP(m, hipStreamSynchronize(m->stream));
     if (loss) *loss = l;
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { merr(m, s_, m_); });
 }
 
 mcinv_status mcinv_mlp_train(mcinv_mlp* m, int64_t steps, int32_t batch_rows, float lr, uint64_t seed,
                              float* loss_history)
-{
+try {
     if (!m || steps < 0) return merr(m, MCINV_EINVAL, "bad arguments");
     if (batch_rows < 64 || batch_rows % 64 != 0 || batch_rows > (1 << 20))
         return merr(m, MCINV_EINVAL, "batch_rows must be a multiple of 64 in [64, 2^20]");
@@ -808,10 +827,12 @@ mcinv_status mcinv_mlp_train(mcinv_mlp* m, int64_t steps, int32_t batch_rows, fl
         MHIP(m, hipMemcpyAsync(loss_history, dloss.p, sizeof(float) * steps, hipMemcpyDeviceToHost, m->stream));
     MHIP(m, hipStreamSynchronize(m->stream));
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { merr(m, s_, m_); });
 }
 
 mcinv_status mcinv_mlp_predict(mcinv_mlp* m, const float* X, int64_t N, float* out)
-{
+try {
     if (!m || !X || !out || N < 0) return merr(m, MCINV_EINVAL, "bad arguments");
     if (N == 0) return MCINV_OK;
     MHIP(m, hipSetDevice(m->device));
@@ -840,6 +861,8 @@ mcinv_status mcinv_mlp_predict(mcinv_mlp* m, const float* X, int64_t N, float* o
     mfree(dout);
     if (e != hipSuccess) return merr(m, MCINV_EDEVICE, std::string("predict: ") + hipGetErrorString(e));
     return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { merr(m, s_, m_); });
 }
 
 const char* mcinv_mlp_last_error(const mcinv_mlp* m)

@@ -43,6 +43,42 @@ def test_binding_covers_header():
     assert sorted(_binding.SIGNATURES) == _declared()
 
 
+def test_binding_constants_match_header():
+    from paper_cs_0412107_amd import _binding
+    text = open(HEADER).read()
+    defs = re.findall(r"#define (MCINV_\w+)\s+\(?(-?\d+)u?\)?", text)
+    assert len(defs) > 20
+    for name, value in defs:
+        assert getattr(_binding, name) == int(value), name
+
+
+def test_every_entry_point_catches_exceptions():
+    """No C++ exception may leave the library: each exported function that
+    returns a status is a function-try-block whose handler converts the
+    exception into a status."""
+    csrc = os.path.join(ROOT, "paper_cs_0412107_amd", "csrc")
+    found = {}
+    for fn in sorted(os.listdir(csrc)):
+        if not fn.endswith(".hip"):
+            continue
+        lines = open(os.path.join(csrc, fn)).read().split("\n")
+        for i, line in enumerate(lines):
+            m = re.match(r'^(?:extern "C" )?mcinv_status (mcinv_\w+)\(', line)
+            if not m:
+                continue
+            j = i
+            while lines[j] not in ("{", "try {"):
+                j += 1
+            k = j
+            while lines[k] != "}":
+                k += 1
+            found[m.group(1)] = (lines[j] == "try {" and lines[k - 2] == "} catch (...) {"
+                                 and "exception_status" in lines[k - 1])
+    status_fns = [n for n in _declared() if re.search(r"mcinv_status\s+" + n + r"\s*\(", open(HEADER).read())]
+    assert sorted(found) == sorted(status_fns)
+    assert all(found.values()), [n for n, ok in found.items() if not ok]
+
+
 def test_create_without_gpu_fails_cleanly():
     import torch
     if torch.cuda.is_available():

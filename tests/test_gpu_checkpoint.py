@@ -109,3 +109,52 @@ def test_restore_rejects_mismatch(tmp_path):
             b.restore(os.path.join(str(tmp_path), "missing.bin"))
         b.restore(path)
         assert b.info()["sweeps_done"] == 2
+
+
+def test_restore_rejects_corrupt_counts(tmp_path):
+    """Counts read from a checkpoint header (index lists, samples) are checked
+    against the bytes left in the file before they size any buffer: a damaged
+    header is EINVAL, not a huge allocation, and the context stays usable."""
+    import struct
+    print_case(test="checkpoint_corrupt_counts")
+    m = oracle_matrix(gen.pedigree(600, seed=95), "f32")
+    rows = np.array([1, 2, 3])
+    path = str(tmp_path / "ck.bin")
+    # header: 8 magic bytes, then 64-bit fields in declaration order
+    fields = ["version", "n", "nnz", "n_off", "P", "ld", "G", "dtype", "hermitian", "noise", "stream_id", "seed",
+              "fingerprint", "flags", "nI", "nJ", "ne", "sweeps", "samples", "batch_len", "nslots", "q_nnz",
+              "requested", "pair_offset"]
+    off = {f: 8 + 8 * i for i, f in enumerate(fields)}
+    with mc.Sampler(m, pairs=64, groups=16, dtype="f32", seed=3) as a:
+        a.burn_in(2)
+        a.request(diag=True, trace=True, block_rows=rows, block_cols=rows, entries=[(0, 1)])
+        a.sample(5)
+        a.save(path)
+        ref = a.diag()
+    data = open(path, "rb").read()
+    assert struct.unpack_from("<q", data, off["nI"])[0] == 3
+    assert struct.unpack_from("<q", data, off["samples"])[0] == 5
+    bad = str(tmp_path / "bad.bin")
+    with mc.Sampler(m, pairs=64, groups=16, dtype="f32", seed=3) as b:
+        for field, value in (("nI", 1 << 40), ("nJ", -1), ("ne", 1 << 40), ("ne", -2), ("samples", 1 << 40),
+                             ("samples", -5), ("samples", 99)):
+            d = bytearray(data)
+            struct.pack_into("<q", d, off[field], value)
+            open(bad, "wb").write(bytes(d))
+            with pytest.raises(mc.McinvError) as ei:
+                b.restore(bad)
+            assert ei.value.code == mc.MCINV_EINVAL, (field, value)
+        for cut in (len(data) - 8, len(data) - 1):     # truncated, and one byte short
+            open(bad, "wb").write(data[:cut])
+            with pytest.raises(mc.McinvError) as ei:
+                b.restore(bad)
+            assert ei.value.code == mc.MCINV_EINVAL
+        open(bad, "wb").write(data + b"\0" * 8)          # trailing bytes
+        with pytest.raises(mc.McinvError) as ei:
+            b.restore(bad)
+        assert ei.value.code == mc.MCINV_EINVAL
+        assert b.info()["sweeps_done"] == 0              # none of the failed restores changed the context
+        b.restore(path)
+        got = b.diag()
+    for x, y in zip(got, ref):
+        assert np.array_equal(np.asarray(x), np.asarray(y))
