@@ -28,6 +28,9 @@
 #ifndef MCINV_GATHER_U16
 #define MCINV_GATHER_U16 1       // 16-byte state (complex128)
 #endif
+#ifndef MCINV_GATHER_HERM_U4
+#define MCINV_GATHER_HERM_U4 4   // single-draw mode, 4-byte state: one load per neighbour, so twice the chunk
+#endif
 
 namespace mcinv {
 
@@ -125,7 +128,9 @@ __global__ __launch_bounds__(256) void k_sweep(const SweepArgs<V> a)
         // Gather in chunks of U neighbours: all 2U state loads of a chunk are
         // issued before the first multiply (memory-level parallelism per wave).
         // A chunk's unused slots reload entry 0 with zero coefficients.
-        constexpr int U = sizeof(V) >= 16 ? MCINV_GATHER_U16 : (sizeof(V) >= 8 ? MCINV_GATHER_U8 : MCINV_GATHER_U4);
+        constexpr int U = (HERM && sizeof(V) == 4)
+                              ? MCINV_GATHER_HERM_U4
+                              : (sizeof(V) >= 16 ? MCINV_GATHER_U16 : (sizeof(V) >= 8 ? MCINV_GATHER_U8 : MCINV_GATHER_U4));
         if (active) {
             const Entry<V>* e = a.ent + rr.begin;
             const int cnt = rr.count;
