@@ -214,10 +214,13 @@ mcinv_status mcinv_get_permutation(mcinv_ctx* ctx, int64_t* perm, int32_t* color
  * difference of two such paths is the noiseless Gauss-Seidel iteration on
  * C d = 0 (z) and C^dagger d = 0 (w), identical for every chain pair, so the
  * library runs that one iteration (in the sweep precision), checks it after
- * every sweep, and then advances the chains by the same number N of noisy
- * sweeps: the chains end exactly as after mcinv_burn_in(ctx, N).  Stops at
- * max_sweeps if the tolerance is not reached (*diff_z / *diff_w tell).
- * EDIVERGED when the difference becomes non-finite.  Outputs may be NULL. */
+ * every sweep, and advances the chains by the same number N of noisy sweeps:
+ * the chains end exactly as after mcinv_burn_in(ctx, N).  The iteration runs
+ * on a stream of the library's own, ahead of the chains; chain sweep k is
+ * issued on the context's stream once the difference shows N >= k, so the two
+ * overlap.  Stops at max_sweeps if the tolerance is not reached (*diff_z /
+ * *diff_w tell).  EDIVERGED when the difference becomes non-finite (the chain
+ * sweeps issued until then have run).  Outputs may be NULL. */
 mcinv_status mcinv_burn_in_coupled(mcinv_ctx* ctx, double tol, int64_t max_sweeps, int64_t* sweeps_done,
                                    double* diff_z, double* diff_w);
 

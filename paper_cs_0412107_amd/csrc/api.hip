@@ -52,6 +52,7 @@ struct mcinv_ctx {
     mcinv_config cfg{};
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    hipStream_t side = nullptr;   // the coupled burn-in's difference iteration (created on first use)
     bool cplx = false;
     size_t elem = 0;
     int comps = 1;
@@ -654,6 +655,7 @@ void mcinv_destroy(mcinv_ctx* c)
     dfree(c->d_geyer);
     dfree(c->d_slot_len);
     for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+    if (c->side) (void)hipStreamDestroy(c->side);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -1378,13 +1380,13 @@ static mcinv_status noiseless_sweeps(mcinv_ctx* c, int64_t k, void* zc, void* wc
     }
 }
 
-static mcinv_status max_abs(mcinv_ctx* c, const void* x, int64_t ld, unsigned long long* out)
+static mcinv_status max_abs(mcinv_ctx* c, const void* x, int64_t ld, unsigned long long* out, hipStream_t st)
 {
     switch (c->cfg.sweep_dtype) {
-    case MCINV_R32: HIP_TRY(c, launch_max_abs<float>((const float*)x, c->n, ld, out, c->stream)); break;
-    case MCINV_R64: HIP_TRY(c, launch_max_abs<double>((const double*)x, c->n, ld, out, c->stream)); break;
-    case MCINV_C64: HIP_TRY(c, launch_max_abs<Cx<float>>((const Cx<float>*)x, c->n, ld, out, c->stream)); break;
-    default: HIP_TRY(c, launch_max_abs<Cx<double>>((const Cx<double>*)x, c->n, ld, out, c->stream)); break;
+    case MCINV_R32: HIP_TRY(c, launch_max_abs<float>((const float*)x, c->n, ld, out, st)); break;
+    case MCINV_R64: HIP_TRY(c, launch_max_abs<double>((const double*)x, c->n, ld, out, st)); break;
+    case MCINV_C64: HIP_TRY(c, launch_max_abs<Cx<float>>((const Cx<float>*)x, c->n, ld, out, st)); break;
+    default: HIP_TRY(c, launch_max_abs<Cx<double>>((const Cx<double>*)x, c->n, ld, out, st)); break;
     }
     return MCINV_OK;
 }
@@ -1392,22 +1394,21 @@ static mcinv_status max_abs(mcinv_ctx* c, const void* x, int64_t ld, unsigned lo
 }  // extern "C"
 
 template <typename V>
-static mcinv_status coupling_sweep(mcinv_ctx* c, void* dz, void* dw)
+static mcinv_status coupling_sweep(mcinv_ctx* c, void* dz, void* dw, hipStream_t st)
 {
     for (int32_t col = 0; col < c->ncolors; ++col)
         HIP_TRY(c, launch_coupling_sweep<V>(c->d_rows, (const Entry<V>*)c->d_ent, c->color_ptr[col],
-                                            c->color_ptr[col + 1], c->cfg.hermitian != 0, (V*)dz, (V*)dw,
-                                            c->stream));
+                                            c->color_ptr[col + 1], c->cfg.hermitian != 0, (V*)dz, (V*)dw, st));
     return MCINV_OK;
 }
 
-static mcinv_status coupling_sweep_any(mcinv_ctx* c, void* dz, void* dw)
+static mcinv_status coupling_sweep_any(mcinv_ctx* c, void* dz, void* dw, hipStream_t st)
 {
     switch (c->cfg.sweep_dtype) {
-    case MCINV_R32: return coupling_sweep<float>(c, dz, dw);
-    case MCINV_R64: return coupling_sweep<double>(c, dz, dw);
-    case MCINV_C64: return coupling_sweep<Cx<float>>(c, dz, dw);
-    default: return coupling_sweep<Cx<double>>(c, dz, dw);
+    case MCINV_R32: return coupling_sweep<float>(c, dz, dw, st);
+    case MCINV_R64: return coupling_sweep<double>(c, dz, dw, st);
+    case MCINV_C64: return coupling_sweep<Cx<float>>(c, dz, dw, st);
+    default: return coupling_sweep<Cx<double>>(c, dz, dw, st);
     }
 }
 
@@ -1426,18 +1427,32 @@ try {
     if (s == MCINV_OK && hipMalloc((void**)&dmax, 2 * sizeof(unsigned long long)) != hipSuccess)
         s = fail(c, MCINV_ENOMEM, "device allocation failed");
     void* dw_eff = c->cfg.hermitian ? dz : dw;  // C^dagger = C: the w difference is the z difference
-    int64_t N = max_sweeps;
+    if (s == MCINV_OK && !c->side && hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) {
+        c->side = nullptr;
+        s = fail(c, MCINV_EDEVICE, "hipStreamCreateWithFlags failed");
+    }
+    // The difference iteration runs on the side stream, ahead of the chains:
+    // chain sweep k is issued on the context's stream once the difference
+    // after k - 1 steps is still above tol (so that N >= k), and runs while the
+    // next difference steps are checked.  The difference touches only the
+    // matrix and its own buffers, so the two streams share nothing that either
+    // writes; every chain sweep issued here is one of the N.
+    int64_t N = 0;
     double dzm = INFINITY, dwm = INFINITY;
     for (int64_t k = 1; k <= max_sweeps && s == MCINV_OK; ++k) {
-        if ((s = coupling_sweep_any(c, dz, dw)) != MCINV_OK) break;
-        if (hipMemsetAsync(dmax, 0, 2 * sizeof(unsigned long long), c->stream) != hipSuccess) {
+        if ((s = dispatch_sweeps(c, 1, false)) != MCINV_OK) break;
+        c->sweeps += 1;
+        N = k;
+        if ((s = coupling_sweep_any(c, dz, dw, c->side)) != MCINV_OK) break;
+        if (hipMemsetAsync(dmax, 0, 2 * sizeof(unsigned long long), c->side) != hipSuccess) {
             s = fail(c, MCINV_EDEVICE, "hipMemsetAsync failed");
             break;
         }
-        if ((s = max_abs(c, dz, 1, dmax)) != MCINV_OK || (s = max_abs(c, dw_eff, 1, dmax + 1)) != MCINV_OK) break;
+        if ((s = max_abs(c, dz, 1, dmax, c->side)) != MCINV_OK || (s = max_abs(c, dw_eff, 1, dmax + 1, c->side)) != MCINV_OK)
+            break;
         unsigned long long bits[2] = {0, 0};
-        if (hipMemcpyAsync(bits, dmax, sizeof(bits), hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
-            hipStreamSynchronize(c->stream) != hipSuccess) {
+        if (hipMemcpyAsync(bits, dmax, sizeof(bits), hipMemcpyDeviceToHost, c->side) != hipSuccess ||
+            hipStreamSynchronize(c->side) != hipSuccess) {
             s = fail(c, MCINV_EDEVICE, "copying the coupling difference failed");
             break;
         }
@@ -1448,18 +1463,14 @@ try {
                                          "contract (sp(T) or sp(S) >= 1)");
             break;
         }
-        if (dzm < tol && dwm < tol) {
-            N = k;
-            break;
-        }
+        if (dzm < tol && dwm < tol) break;
     }
+    if (c->side) (void)hipStreamSynchronize(c->side);
     (void)hipFree(dz);
     (void)hipFree(dw);
     (void)hipFree(fl);
     (void)hipFree(dmax);
     if (s != MCINV_OK) return s;
-    MC_TRY(dispatch_sweeps(c, N, false));
-    c->sweeps += N;
     if (sweeps_done) *sweeps_done = N;
     if (diff_z) *diff_z = dzm;
     if (diff_w) *diff_w = dwm;
