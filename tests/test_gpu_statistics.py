@@ -142,3 +142,43 @@ def test_diag_stop_with_time_batches_waits_for_long_batches():
         s.request(diag=True, trace=False)
         done, ach = s.sample_until(0.5, 5000, 10)
         assert 512 < done <= 520 and ach <= 0.5, (done, ach)
+
+
+def test_standard_errors_are_nan_until_two_clusters():
+    """The read contract of the estimates: with no sample yet every estimate
+    and error is NaN; with one cluster (one group, one time batch) the
+    estimates are finite and the errors NaN, as is the trace error of a
+    one-sample series; a second cluster makes every error finite.  With 16
+    chain groups the groups are the clusters, so one sample suffices."""
+    print_case(test="nan_until_two_clusters")
+    m = oracle_matrix(gen.pedigree(300, seed=506), "f32")
+    req = dict(diag=True, trace=True, block_rows=np.array([0, 5]), block_cols=np.array([5, 9]),
+               entries=[(1, 2), (7, 7)])
+    with mc.Sampler(m, pairs=8, groups=1, dtype="f32", seed=11) as s:
+        s.burn_in(20)
+        s.request(**req)
+        d, dse = map(np.asarray, s.diag())
+        assert np.all(np.isnan(d)) and np.all(np.isnan(dse))
+        s.sample(1)
+        assert s.info()["n_batches"] == 1
+        parts = [s.diag(), s.block(), s.entries()]
+        for est, se in parts:
+            assert np.all(np.isfinite(np.asarray(est))) and np.all(np.isnan(np.asarray(se)))
+        t, tse = s.trace()
+        assert np.isfinite(t) and np.isnan(tse)
+        for _ in range(4096):
+            if s.info()["n_batches"] >= 2:
+                break
+            s.sample(1)
+        assert s.info()["n_batches"] >= 2
+        for est, se in [s.diag(), s.block(), s.entries()]:
+            assert np.all(np.isfinite(np.asarray(est))) and np.all(np.isfinite(np.asarray(se)))
+        s.sample(8)   # a Geyer error on a series of a few samples
+        for est, se in [s.diag(), s.block(), s.entries(), s.trace()]:
+            assert np.all(np.isfinite(np.asarray(est))) and np.all(np.isfinite(np.asarray(se)))
+    with mc.Sampler(m, pairs=64, groups=16, dtype="f32", seed=12) as s:
+        s.burn_in(20)
+        s.request(**req)
+        s.sample(1)
+        for est, se in [s.diag(), s.block(), s.entries()]:
+            assert np.all(np.isfinite(np.asarray(est))) and np.all(np.isfinite(np.asarray(se)))
