@@ -327,6 +327,7 @@ mcinv_status run_sweeps(mcinv_ctx* c, int64_t nsw, bool sample, V* z, V* w, int6
     a.xcd_order = c->cfg.xcd_order;
 
     const bool prof = c->cfg.profile != 0 && use_counters;
+    int64_t launches_per_sweep = 0;   // sweep-kernel launches between one timed sweep's events
     size_t next_ev = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> sweep_ev, mom_ev;
 
@@ -354,6 +355,7 @@ mcinv_status run_sweeps(mcinv_ctx* c, int64_t nsw, bool sample, V* z, V* w, int6
         int32_t cs = c->ncolors;
         while (cs > 0 && (c->color_ptr[cs] - c->color_ptr[cs - 1]) * pt < kSmallLaunchRows) --cs;
         if (pt >= T) cs = c->ncolors;
+        launches_per_sweep = (T + pt - 1) / pt * cs + (c->ncolors - cs);
         for (int64_t t0 = 0; t0 < T; t0 += pt) {
             for (int32_t col = 0; col < cs; ++col) {
                 a.row_begin = c->color_ptr[col];
@@ -441,7 +443,7 @@ mcinv_status run_sweeps(mcinv_ctx* c, int64_t nsw, bool sample, V* z, V* w, int6
             float ms = 0.f;
             HIP_TRY(c, hipEventElapsedTime(&ms, pr.first, pr.second));
             c->sweep_ms += ms;
-            c->sweep_launches += c->ncolors;
+            c->sweep_launches += launches_per_sweep;
         }
         for (auto& pr : mom_ev) {
             float ms = 0.f;

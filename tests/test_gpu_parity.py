@@ -420,6 +420,46 @@ def test_workgroup_orders_do_not_change_results(dtype, maker, P, G):
                 np.testing.assert_allclose(np.asarray(t), np.asarray(t0), rtol=1e-12)
 
 
+@pytest.mark.parametrize("dtype,P", [("f32", 1024), ("f64", 1000), ("c64", 768)])
+def test_tile_passes_do_not_change_results(dtype, P):
+    """Sweeping the pair tiles in passes (all colours of a few tiles before the
+    next tiles) only reorders independent work: chains and diagonal moments
+    are bit-identical to one launch per colour.  With profiling on, the
+    reported launch count is the number of sweep launches actually issued
+    (colours too small to fill a launch per pass run once over all tiles)."""
+    print_case(test="tile_passes", dtype=dtype, P=P)
+    m = oracle_matrix(gen.pedigree(40000, seed=97), dtype)
+    S = 3
+    with _sampler(m, dtype, 5, P, 1, profile=True) as a:
+        a.burn_in(2)
+        a.request(diag=True, trace=True)
+        a.reset_profile()
+        a.sample(S)
+        d0, se0 = a.diag()
+        t0, _ = a.trace()
+        z0, w0 = a.state(0), a.state(1)
+        _, colour = a.permutation()
+        assert a.info()["sweep_kernel_launches"] == S * a.info()["n_colors"]
+    sizes = np.bincount(np.asarray(colour))
+    T = (P + 255) // 256
+    for pt in (1, 2, 3):
+        with _sampler(m, dtype, 5, P, 1, profile=True, pass_tiles=pt) as s:
+            s.burn_in(2)
+            s.request(diag=True, trace=True)
+            s.reset_profile()
+            s.sample(S)
+            assert np.array_equal(z0, s.state(0)) and np.array_equal(w0, s.state(1)), pt
+            d, se = s.diag()
+            assert np.array_equal(d0, d) and np.array_equal(se0, se, equal_nan=True), pt
+            t, _ = s.trace()
+            np.testing.assert_allclose(np.asarray(t), np.asarray(t0), rtol=1e-12)
+            cs = len(sizes)
+            while cs > 0 and sizes[cs - 1] * pt < 4096:
+                cs -= 1
+            expected = ((T + pt - 1) // pt) * cs + (len(sizes) - cs) if pt < T else len(sizes)
+            assert s.info()["sweep_kernel_launches"] == S * expected, (pt, cs, sizes)
+
+
 @pytest.mark.parametrize("dtype,maker", [("f32", lambda: gen.pedigree(3000, seed=61)),
                                          ("c64", lambda: gen.lattice(6, k=0.12, seed=62))])
 def test_pair_split_reproduces_single_run(dtype, maker):
