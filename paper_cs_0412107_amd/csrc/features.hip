@@ -7,6 +7,7 @@
 // over each row's merged neighbours (row i or column i of C) from pass 1's
 // output.  fp64 arithmetic, one thread per row, fp32 output.
 #include <hip/hip_runtime.h>
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include <algorithm>
 #include <cmath>
@@ -43,6 +44,79 @@ __device__ inline double lookup_cji(const FEnt* e, int32_t cnt, int32_t k)
             hi = mid - 1;
     }
     return 0.0;
+}
+
+// The merged neighbour lists are built on the device.  The transpose of C
+// comes from one radix sort of the keys j * n + i (entry c_ij), which orders
+// the entries by column, then by row, and carries c_ij along: column i's
+// entries are then the keys in [i * n, (i + 1) * n), rows ascending.
+
+// key of every entry and the entry count of every column (thread per row)
+__global__ __launch_bounds__(256) void k_ft_keys(int64_t n, const int64_t* rp, const int32_t* col, uint64_t* key,
+                                                 int32_t* ccount)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+        const int32_t j = col[e];
+        key[e] = (uint64_t)j * (uint64_t)n + (uint64_t)i;
+        atomicAdd(ccount + j, 1);
+    }
+}
+
+// out[k] = in[0] + ... + in[k-1] for k = 0..n (one workgroup: a chunk per
+// thread, the chunk sums scanned in LDS)
+__global__ __launch_bounds__(1024) void k_ft_scan(int64_t n, const int32_t* in, int64_t* out)
+{
+    __shared__ int64_t part[1024];
+    const int64_t per = (n + 1023) / 1024;
+    const int64_t b = (int64_t)threadIdx.x * per, e = b + per < n ? b + per : n;
+    int64_t s = 0;
+    for (int64_t k = b; k < e; ++k) s += in[k];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const int64_t v = (int)threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    int64_t run = part[threadIdx.x] - s;
+    for (int64_t k = b; k < e; ++k) {
+        out[k] = run;
+        run += in[k];
+    }
+    if (threadIdx.x == 1023) out[n] = part[1023];
+}
+
+// Row i's merged list: the union of row i (col, val) and column i (the sorted
+// keys tkey[tp[i] .. tp[i+1]) with values tval), ascending, without i itself.
+// Counting pass (out == nullptr) writes cnt[i]; the writing pass fills
+// out + beg[i].
+__global__ __launch_bounds__(256) void k_ft_merge(int64_t n, const int64_t* rp, const int32_t* col,
+                                                  const double* val, const int64_t* tp, const uint64_t* tkey,
+                                                  const double* tval, const int64_t* beg, FEnt* out, int32_t* cnt)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t base = (uint64_t)i * (uint64_t)n;
+    int64_t e = rp[i], t = tp[i];
+    const int64_t e_end = rp[i + 1], t_end = tp[i + 1];
+    FEnt* o = out ? out + beg[i] : nullptr;
+    int32_t k = 0;
+    while (e < e_end || t < t_end) {
+        const int64_t je = e < e_end ? (int64_t)col[e] : INT64_MAX;
+        const int64_t jt = t < t_end ? (int64_t)(tkey[t] - base) : INT64_MAX;
+        const int64_t j = je < jt ? je : jt;
+        const bool has_e = je == j, has_t = jt == j;
+        if (j != i) {
+            if (o) o[k] = FEnt{(int32_t)j, 0, has_e ? val[e] : 0.0, has_t ? tval[t] : 0.0};
+            ++k;
+        }
+        e += has_e ? 1 : 0;
+        t += has_t ? 1 : 0;
+    }
+    if (!o) cnt[i] = k;
 }
 
 __global__ __launch_bounds__(256) void k_features_pass1(int64_t n, const int64_t* beg, const int32_t* cnt,
@@ -182,70 +256,81 @@ try {
         set_context_free_error("mcinv_features: " + why);
         return singular ? MCINV_ESINGULAR : MCINV_EINVAL;
     }
-    // Each row's neighbours: the union of row i and column i of C in natural
-    // order (no colouring is needed here), with c_ij and c_ji.
-    std::vector<int64_t> tptr, tsrc;
-    std::vector<int32_t> trow;
-    transpose_csr(n, nnz, row_ptr, col_idx, tptr, trow, tsrc);
-    auto merge_row = [&](int64_t i, auto&& emit) {
-        int64_t e = row_ptr[i], t = tptr[i];
-        const int64_t e_end = row_ptr[i + 1], t_end = tptr[i + 1];
-        while (e < e_end || t < t_end) {
-            const int64_t je = e < e_end ? col_idx[e] : INT64_MAX;
-            const int64_t jt = t < t_end ? trow[t] : INT64_MAX;
-            const int64_t j = std::min(je, jt);
-            const bool has_e = je == j, has_t = jt == j;
-            if (j != i) emit(j, has_e ? values[e] : 0.0, has_t ? values[tsrc[t]] : 0.0);
-            e += has_e ? 1 : 0;
-            t += has_t ? 1 : 0;
-        }
-    };
-    std::vector<int32_t> cnt(n);
-    parallel_for(n, [&](int64_t i0, int64_t i1) {
-        for (int64_t i = i0; i < i1; ++i) {
-            int32_t k = 0;
-            merge_row(i, [&](int64_t, double, double) { ++k; });
-            cnt[i] = k;
-        }
-    });
-    std::vector<int64_t> beg(n + 1, 0);
-    for (int64_t i = 0; i < n; ++i) beg[i + 1] = beg[i] + cnt[i];
-    const int64_t nent = beg[n];
-    std::unique_ptr<FEnt[]> ent(new FEnt[(size_t)std::max<int64_t>(nent, 1)]);   // filled below, not zeroed
     std::vector<double> d(n);
-    parallel_for(n, [&](int64_t i0, int64_t i1) {
-        for (int64_t i = i0; i < i1; ++i) {
-            FEnt* out_e = ent.get() + beg[i];
-            merge_row(i, [&](int64_t j, double cij, double cji) { *out_e++ = FEnt{(int32_t)j, 0, cij, cji}; });
-            d[i] = diag[i].real();
-        }
-    });
+    for (int64_t i = 0; i < n; ++i) d[i] = diag[i].real();
     if (hipSetDevice(device) != hipSuccess) {
         set_context_free_error("mcinv_features: no such device");
         return MCINV_EDEVICE;
     }
-    int64_t* d_beg = nullptr;
-    int32_t* d_cnt = nullptr;
-    FEnt* d_ent = nullptr;
-    double *d_d = nullptr, *d_F = nullptr;
-    float* d_out = nullptr;
+    // device buffers, all released at the end whatever happens
+    std::vector<void*> owned;
     hipError_t e = hipSuccess;
     auto alloc = [&](void** p, size_t bytes) {
-        if (e == hipSuccess) e = hipMalloc(p, bytes > 0 ? bytes : 1);
+        *p = nullptr;
+        if (e == hipSuccess) e = hipMalloc(p, std::max<size_t>(bytes, 1));
+        if (e == hipSuccess) owned.push_back(*p);
     };
-    alloc((void**)&d_beg, sizeof(int64_t) * n);
-    alloc((void**)&d_cnt, sizeof(int32_t) * n);
-    alloc((void**)&d_ent, sizeof(FEnt) * (size_t)nent);
-    alloc((void**)&d_d, sizeof(double) * n);
-    alloc((void**)&d_F, sizeof(double) * n * kNF);
-    alloc((void**)&d_out, sizeof(float) * n * kNF);
-    if (e == hipSuccess) e = hipMemcpy(d_beg, beg.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(d_cnt, cnt.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice);
-    if (e == hipSuccess && nent > 0)
-        e = hipMemcpy(d_ent, ent.get(), sizeof(FEnt) * (size_t)nent, hipMemcpyHostToDevice);
+    int64_t *d_rp = nullptr, *d_tp = nullptr, *d_beg = nullptr;
+    int32_t *d_col = nullptr, *d_ccount = nullptr, *d_cnt = nullptr;
+    double *d_val = nullptr, *d_tval = nullptr, *d_d = nullptr, *d_F = nullptr;
+    uint64_t *d_key = nullptr, *d_tkey = nullptr;
+    FEnt* d_ent = nullptr;
+    float* d_out = nullptr;
+    void* d_tmp = nullptr;
+    alloc((void**)&d_rp, sizeof(int64_t) * ((size_t)n + 1));
+    alloc((void**)&d_col, sizeof(int32_t) * (size_t)nnz);
+    alloc((void**)&d_val, sizeof(double) * (size_t)nnz);
+    alloc((void**)&d_key, sizeof(uint64_t) * (size_t)nnz);
+    alloc((void**)&d_tkey, sizeof(uint64_t) * (size_t)nnz);
+    alloc((void**)&d_tval, sizeof(double) * (size_t)nnz);
+    alloc((void**)&d_ccount, sizeof(int32_t) * (size_t)n);
+    alloc((void**)&d_tp, sizeof(int64_t) * ((size_t)n + 1));
+    alloc((void**)&d_cnt, sizeof(int32_t) * (size_t)n);
+    alloc((void**)&d_beg, sizeof(int64_t) * ((size_t)n + 1));
+    alloc((void**)&d_d, sizeof(double) * (size_t)n);
+    if (e == hipSuccess) e = hipMemcpy(d_rp, row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess && nnz > 0) e = hipMemcpy(d_col, col_idx, sizeof(int32_t) * nnz, hipMemcpyHostToDevice);
+    if (e == hipSuccess && nnz > 0) e = hipMemcpy(d_val, values, sizeof(double) * nnz, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d_d, d.data(), sizeof(double) * n, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemset(d_F, 0, sizeof(double) * n * kNF);
+    if (e == hipSuccess) e = hipMemset(d_ccount, 0, sizeof(int32_t) * n);
     const unsigned blocks = (unsigned)((n + 255) / 256);
+    if (e == hipSuccess) {
+        k_ft_keys<<<blocks, 256>>>(n, d_rp, d_col, d_key, d_ccount);
+        e = hipGetLastError();
+    }
+    // sort only the bits that keys below n^2 can use
+    unsigned bits = 1;
+    while (bits < 64 && ((unsigned __int128)1 << bits) < (unsigned __int128)n * (unsigned __int128)n) ++bits;
+    size_t tmp_bytes = 0;
+    const uint64_t* ckey = d_key;   // inputs of the sort (d_val is read again by the merge)
+    const double* cval = d_val;
+    if (e == hipSuccess)
+        e = rocprim::radix_sort_pairs(nullptr, tmp_bytes, ckey, d_tkey, cval, d_tval, (size_t)nnz, 0u, bits);
+    alloc(&d_tmp, tmp_bytes);
+    if (e == hipSuccess)
+        e = rocprim::radix_sort_pairs(d_tmp, tmp_bytes, ckey, d_tkey, cval, d_tval, (size_t)nnz, 0u, bits);
+    if (e == hipSuccess) {
+        k_ft_scan<<<1, 1024>>>(n, d_ccount, d_tp);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        k_ft_merge<<<blocks, 256>>>(n, d_rp, d_col, d_val, d_tp, d_tkey, d_tval, nullptr, nullptr, d_cnt);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        k_ft_scan<<<1, 1024>>>(n, d_cnt, d_beg);
+        e = hipGetLastError();
+    }
+    int64_t nent = 0;
+    if (e == hipSuccess) e = hipMemcpy(&nent, d_beg + n, sizeof(int64_t), hipMemcpyDeviceToHost);
+    alloc((void**)&d_ent, sizeof(FEnt) * (size_t)nent);
+    if (e == hipSuccess) {
+        k_ft_merge<<<blocks, 256>>>(n, d_rp, d_col, d_val, d_tp, d_tkey, d_tval, d_beg, d_ent, d_cnt);
+        e = hipGetLastError();
+    }
+    alloc((void**)&d_F, sizeof(double) * (size_t)n * kNF);
+    alloc((void**)&d_out, sizeof(float) * (size_t)n * kNF);
+    if (e == hipSuccess) e = hipMemset(d_F, 0, sizeof(double) * n * kNF);
     if (e == hipSuccess) {
         k_features_pass1<<<blocks, 256>>>(n, d_beg, d_cnt, d_ent, d_d, d_F);
         e = hipGetLastError();
@@ -255,12 +340,7 @@ try {
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipMemcpy(out, d_out, sizeof(float) * n * kNF, hipMemcpyDeviceToHost);
-    (void)hipFree(d_beg);
-    (void)hipFree(d_cnt);
-    (void)hipFree(d_ent);
-    (void)hipFree(d_d);
-    (void)hipFree(d_F);
-    (void)hipFree(d_out);
+    for (void* p : owned) (void)hipFree(p);
     if (e != hipSuccess) {
         set_context_free_error(std::string("mcinv_features: ") + hipGetErrorString(e));
         return e == hipErrorOutOfMemory ? MCINV_ENOMEM : MCINV_EDEVICE;
