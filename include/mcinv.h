@@ -515,6 +515,18 @@ mcinv_status mcinv_gate_apply(const mcinv_gate* g, int64_t N, const float* X, ui
 mcinv_status mcinv_gate_read(const mcinv_gate* g, double* edges_a, double* edges_b, double* bin_err,
                              int64_t* bin_count, uint8_t* bin_fallback);
 void mcinv_gate_destroy(mcinv_gate* g);
+
+/* The surrogate's whole estimate of one matrix in one call: the features of
+ * the real CSR matrix (rules of mcinv_features) are computed on the network's
+ * device and fed to the network there, so only the predictions and the gate's
+ * two binning features cross to the host.  pred[n] = the network's output
+ * (c_ii (C^-1)_ii, as mcinv_mlp_predict on mcinv_features' output), fallback[n]
+ * = the gate's decision per row (as mcinv_gate_apply on those features).
+ * Both caller-allocated.  ESINGULAR / EINVAL as mcinv_features; the message is
+ * available from mcinv_mlp_last_error(m). */
+mcinv_status mcinv_mlp_estimate_matrix(mcinv_mlp* m, const mcinv_gate* g, int64_t n, int64_t nnz,
+                                       const int64_t* row_ptr, const int32_t* col_idx, const double* values,
+                                       float* pred, uint8_t* fallback);
 const char* mcinv_gate_last_error(void);
 
 #ifdef __cplusplus

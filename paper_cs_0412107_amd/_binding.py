@@ -174,6 +174,7 @@ SIGNATURES = {
     "mcinv_mlp_last_error": (ctypes.c_char_p, [_P]),
     "mcinv_gate_fit": (_I32, [ctypes.POINTER(mcinv_gate_config), _I64, _P, _P, _P, _P, ctypes.POINTER(_P)]),
     "mcinv_gate_apply": (_I32, [_P, _I64, _P, _P]),
+    "mcinv_mlp_estimate_matrix": (_I32, [_P, _P, _I64, _I64, _P, _P, _P, _P, _P]),
     "mcinv_gate_read": (_I32, [_P, _P, _P, _P, _P, _P]),
     "mcinv_gate_destroy": (None, [_P]),
     "mcinv_gate_last_error": (ctypes.c_char_p, []),
@@ -619,6 +620,19 @@ def mcinv_gate_apply(g, X):
     out = np.empty(N, dtype=np.uint8)
     _gcheck(lib().mcinv_gate_apply(g, int(N), _ptr(X), _ptr(out)))
     return out
+
+
+def mcinv_mlp_estimate_matrix(m, g, n, nnz, row_ptr, col_idx, values):
+    """(network predictions float32[n], gate fallback uint8[n]) for a real CSR
+    matrix, its features computed and consumed on the device."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    ci = np.ascontiguousarray(col_idx, dtype=np.int32)
+    v = np.ascontiguousarray(values, dtype=np.float64)
+    pred = np.empty(int(n), dtype=np.float32)
+    fb = np.empty(int(n), dtype=np.uint8)
+    _mcheck(m, lib().mcinv_mlp_estimate_matrix(m, g, int(n), int(nnz), _ptr(rp), _ptr(ci), _ptr(v), _ptr(pred),
+                                               _ptr(fb)))
+    return pred, fb
 
 
 def mcinv_gate_read(g, bins):

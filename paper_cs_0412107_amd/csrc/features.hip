@@ -18,6 +18,7 @@
 #include "../../include/mcinv.h"
 #include "boundary.h"
 #include "prep.h"
+#include "surrogate_internal.h"
 
 namespace mcinv {
 
@@ -238,28 +239,29 @@ __global__ __launch_bounds__(256) void k_features_pass2(int64_t n, const int64_t
     for (int k = 0; k < kNF; ++k) dst[k] = (float)o[k];
 }
 
-}  // namespace mcinv
+__global__ __launch_bounds__(256) void k_ft_pick(int64_t n, const float* F, int32_t a, int32_t b, float* out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[2 * i] = F[i * kNF + a];
+    out[2 * i + 1] = F[i * kNF + b];
+}
 
-using namespace mcinv;
-
-extern "C" mcinv_status mcinv_features(int32_t device, int64_t n, int64_t nnz, const int64_t* row_ptr,
-                                       const int32_t* col_idx, const double* values, float* out)
-try {
-    if (!out) {
-        set_context_free_error("mcinv_features: null output");
-        return MCINV_EINVAL;
-    }
+mcinv_status features_on_device(int32_t device, int64_t n, int64_t nnz, const int64_t* row_ptr,
+                                const int32_t* col_idx, const double* values, float** d_features, std::string* err)
+{
+    *d_features = nullptr;
     std::vector<cd> diag;
     bool singular = false;
     const std::string why = validate_csr(n, nnz, row_ptr, col_idx, values, false, diag, &singular);
     if (!why.empty()) {
-        set_context_free_error("mcinv_features: " + why);
+        *err = why;
         return singular ? MCINV_ESINGULAR : MCINV_EINVAL;
     }
     std::vector<double> d(n);
     for (int64_t i = 0; i < n; ++i) d[i] = diag[i].real();
     if (hipSetDevice(device) != hipSuccess) {
-        set_context_free_error("mcinv_features: no such device");
+        *err = "no such device";
         return MCINV_EDEVICE;
     }
     // device buffers, all released at the end whatever happens
@@ -339,11 +341,58 @@ try {
         k_features_pass2<<<blocks, 256>>>(n, d_beg, d_cnt, d_ent, d_F, d_out);
         e = hipGetLastError();
     }
-    if (e == hipSuccess) e = hipMemcpy(out, d_out, sizeof(float) * n * kNF, hipMemcpyDeviceToHost);
-    for (void* p : owned) (void)hipFree(p);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    for (void* p : owned)
+        if (p != (void*)d_out || e != hipSuccess) (void)hipFree(p);
+    if (e != hipSuccess) {
+        *err = hipGetErrorString(e);
+        return e == hipErrorOutOfMemory ? MCINV_ENOMEM : MCINV_EDEVICE;
+    }
+    *d_features = d_out;
+    return MCINV_OK;
+}
+
+mcinv_status features_pick_two(const float* d_features, int64_t n, int32_t a, int32_t b, float* out,
+                               std::string* err)
+{
+    float* d2 = nullptr;
+    hipError_t e = hipMalloc((void**)&d2, sizeof(float) * 2 * (size_t)std::max<int64_t>(n, 1));
+    if (e == hipSuccess && n > 0) {
+        k_ft_pick<<<(unsigned)((n + 255) / 256), 256>>>(n, d_features, a, b, d2);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && n > 0) e = hipMemcpy(out, d2, sizeof(float) * 2 * n, hipMemcpyDeviceToHost);
+    if (d2) (void)hipFree(d2);
+    if (e != hipSuccess) {
+        *err = hipGetErrorString(e);
+        return e == hipErrorOutOfMemory ? MCINV_ENOMEM : MCINV_EDEVICE;
+    }
+    return MCINV_OK;
+}
+
+}  // namespace mcinv
+
+using namespace mcinv;
+
+extern "C" mcinv_status mcinv_features(int32_t device, int64_t n, int64_t nnz, const int64_t* row_ptr,
+                                       const int32_t* col_idx, const double* values, float* out)
+try {
+    if (!out) {
+        set_context_free_error("mcinv_features: null output");
+        return MCINV_EINVAL;
+    }
+    float* d_F = nullptr;
+    std::string why;
+    const mcinv_status st = features_on_device(device, n, nnz, row_ptr, col_idx, values, &d_F, &why);
+    if (st != MCINV_OK) {
+        set_context_free_error("mcinv_features: " + why);
+        return st;
+    }
+    const hipError_t e = hipMemcpy(out, d_F, sizeof(float) * n * kNF, hipMemcpyDeviceToHost);
+    (void)hipFree(d_F);
     if (e != hipSuccess) {
         set_context_free_error(std::string("mcinv_features: ") + hipGetErrorString(e));
-        return e == hipErrorOutOfMemory ? MCINV_ENOMEM : MCINV_EDEVICE;
+        return MCINV_EDEVICE;
     }
     return MCINV_OK;
 } catch (...) {

@@ -22,6 +22,7 @@
 
 #include "../../include/mcinv.h"
 #include "boundary.h"
+#include "surrogate_internal.h"
 
 struct mcinv_gate {
     mcinv_gate_config cfg{};
@@ -63,6 +64,28 @@ thread_local std::string g_gerr;
 void set_err(const std::string& m) { g_gerr = m; }
 
 }  // namespace
+
+namespace mcinv {
+
+void gate_fallback_rows(const mcinv_gate* g, int64_t N, const float* X, int64_t ld, int32_t ca, int32_t cb,
+                        uint8_t* fallback)
+{
+    const int32_t B = g->cfg.bins;
+    for (int64_t i = 0; i < N; ++i) {
+        const double xa = X[i * ld + ca];
+        const double xb = X[i * ld + cb];
+        if (std::isnan(xa) || std::isnan(xb)) {
+            fallback[i] = 1;
+            continue;
+        }
+        fallback[i] = g->fallback[(size_t)(bin_of(g->ea, xa) * B + bin_of(g->eb, xb))];
+    }
+}
+
+int32_t gate_feature_a(const mcinv_gate* g) { return g->cfg.feature_a; }
+int32_t gate_feature_b(const mcinv_gate* g) { return g->cfg.feature_b; }
+
+}  // namespace mcinv
 
 extern "C" {
 
@@ -125,16 +148,7 @@ try {
         set_err("mcinv_gate_apply: bad arguments");
         return MCINV_EINVAL;
     }
-    const int32_t B = g->cfg.bins;
-    for (int64_t i = 0; i < N; ++i) {
-        const double xa = X[i * MCINV_N_FEATURES + g->cfg.feature_a];
-        const double xb = X[i * MCINV_N_FEATURES + g->cfg.feature_b];
-        if (std::isnan(xa) || std::isnan(xb)) {
-            fallback[i] = 1;
-            continue;
-        }
-        fallback[i] = g->fallback[(size_t)(bin_of(g->ea, xa) * B + bin_of(g->eb, xb))];
-    }
+    mcinv::gate_fallback_rows(g, N, X, MCINV_N_FEATURES, g->cfg.feature_a, g->cfg.feature_b, fallback);
     return MCINV_OK;
 } catch (...) {
     return mcinv::exception_status([&](mcinv_status, const std::string& m_) { set_err(m_); });

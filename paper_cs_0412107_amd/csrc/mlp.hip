@@ -30,6 +30,7 @@
 
 #include "../../include/mcinv.h"
 #include "boundary.h"
+#include "surrogate_internal.h"
 #include "device_common.h"
 #include "mfma_tile.h"
 
@@ -598,6 +599,33 @@ mcinv_status run_step(mcinv_mlp* m, int32_t R, bool apply, float lr, float* loss
 
 }  // namespace
 
+namespace mcinv {
+
+mcinv_status mlp_predict_device(mcinv_mlp* m, const float* dX, int64_t N, float* dout, std::string* err)
+{
+    hipError_t e = hipSuccess;
+    const int64_t chunk = (int64_t)64 * 65535;
+    for (int64_t r0 = 0; r0 < N && e == hipSuccess; r0 += chunk) {
+        MlpArgs a = base_args(m);
+        a.X = dX;
+        a.idx = nullptr;
+        a.row0 = r0;
+        a.R = (int32_t)std::min<int64_t>(chunk, N - r0);
+        a.backward = 0;
+        a.out = dout + r0;
+        k_mlp_fwd_bwd<<<dim3((unsigned)((a.R + 63) / 64)), dim3(256), 0, m->stream>>>(a);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+    if (e != hipSuccess) {
+        *err = hipGetErrorString(e);
+        return MCINV_EDEVICE;
+    }
+    return MCINV_OK;
+}
+
+}  // namespace mcinv
+
 extern "C" {
 
 mcinv_status mcinv_mlp_create(int32_t device, mcinv_mlp** out)
@@ -842,24 +870,50 @@ try {
         mfree(dX);
         return merr(m, MCINV_ENOMEM, "device allocation failed");
     }
+    std::string why;
+    mcinv_status st = MCINV_OK;
     hipError_t e = hipMemcpyAsync(dX, X, sizeof(float) * kF * N, hipMemcpyHostToDevice, m->stream);
-    const int64_t chunk = (int64_t)64 * 65535;
-    for (int64_t r0 = 0; r0 < N && e == hipSuccess; r0 += chunk) {
-        MlpArgs a = base_args(m);
-        a.X = dX;
-        a.idx = nullptr;
-        a.row0 = r0;
-        a.R = (int32_t)std::min<int64_t>(chunk, N - r0);
-        a.backward = 0;
-        a.out = dout + r0;
-        k_mlp_fwd_bwd<<<dim3((unsigned)((a.R + 63) / 64)), dim3(256), 0, m->stream>>>(a);
-        e = hipGetLastError();
-    }
-    if (e == hipSuccess) e = hipMemcpyAsync(out, dout, sizeof(float) * N, hipMemcpyDeviceToHost, m->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+    if (e == hipSuccess) st = mcinv::mlp_predict_device(m, dX, N, dout, &why);
+    if (e == hipSuccess && st == MCINV_OK)
+        e = hipMemcpyAsync(out, dout, sizeof(float) * N, hipMemcpyDeviceToHost, m->stream);
+    if (e == hipSuccess && st == MCINV_OK) e = hipStreamSynchronize(m->stream);
     mfree(dX);
     mfree(dout);
+    if (st != MCINV_OK) return merr(m, st, "predict: " + why);
     if (e != hipSuccess) return merr(m, MCINV_EDEVICE, std::string("predict: ") + hipGetErrorString(e));
+    return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { merr(m, s_, m_); });
+}
+
+mcinv_status mcinv_mlp_estimate_matrix(mcinv_mlp* m, const mcinv_gate* g, int64_t n, int64_t nnz,
+                                       const int64_t* row_ptr, const int32_t* col_idx, const double* values,
+                                       float* pred, uint8_t* fallback)
+try {
+    if (!m || !g || !pred || !fallback) return merr(m, MCINV_EINVAL, "estimate_matrix: null argument");
+    std::string why;
+    float* dF = nullptr;
+    mcinv_status st = mcinv::features_on_device(m->device, n, nnz, row_ptr, col_idx, values, &dF, &why);
+    if (st != MCINV_OK) return merr(m, st, "estimate_matrix: features: " + why);
+    float* dout = nullptr;
+    std::vector<float> two;
+    if (hipMalloc((void**)&dout, sizeof(float) * (size_t)std::max<int64_t>(n, 1)) != hipSuccess) {
+        st = MCINV_ENOMEM;
+        why = "device allocation failed";
+    }
+    if (st == MCINV_OK) st = mcinv::mlp_predict_device(m, dF, n, dout, &why);
+    if (st == MCINV_OK && hipMemcpy(pred, dout, sizeof(float) * n, hipMemcpyDeviceToHost) != hipSuccess) {
+        st = MCINV_EDEVICE;
+        why = "copying the predictions failed";
+    }
+    if (st == MCINV_OK) {
+        two.resize((size_t)n * 2);
+        st = mcinv::features_pick_two(dF, n, mcinv::gate_feature_a(g), mcinv::gate_feature_b(g), two.data(), &why);
+    }
+    if (dout) mfree(dout);
+    (void)hipFree(dF);
+    if (st != MCINV_OK) return merr(m, st, "estimate_matrix: " + why);
+    mcinv::gate_fallback_rows(g, n, two.data(), 2, 0, 1, fallback);
     return MCINV_OK;
 } catch (...) {
     return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { merr(m, s_, m_); });

@@ -95,6 +95,12 @@ class Network:
     def predict(self, X):
         return B.mcinv_mlp_predict(self.h, X)
 
+    def estimate_matrix(self, matrix, gate):
+        """(predictions, gate fallback flags) for a matrix, its features made
+        and used on the device (``mcinv_mlp_estimate_matrix``)."""
+        return B.mcinv_mlp_estimate_matrix(self.h, gate.h, matrix.n, matrix.nnz, matrix.row_ptr, matrix.col,
+                                           matrix.val)
+
 
 class Gate:
     """Per-bin validated error over two features (``mcinv_gate``)."""
@@ -122,7 +128,7 @@ class Gate:
 
 
 def estimate_diag(matrix, net, gate, sampler_factory, rel_se=0.01, max_sweeps=20000, check_every=20,
-                  burn_in=200, device=0):
+                  burn_in=200):
     """diag(C^-1): the network's prediction where the gate accepts it, the
     sampler's estimate (stop check over the rejected rows only) elsewhere.
 
@@ -131,11 +137,11 @@ def estimate_diag(matrix, net, gate, sampler_factory, rel_se=0.01, max_sweeps=20
     to 5e-5).
     Returns (estimate, source) with source 0 = network, 1 = sampler, and a
     dict of counts and sweeps."""
-    X = features(matrix, device)
-    y_hat = net.predict(X).astype(np.float64)
+    y_hat, fb = net.estimate_matrix(matrix, gate)
+    y_hat = y_hat.astype(np.float64)
+    fb = fb.astype(bool)
     d = _diag(matrix)
     est = y_hat / d
-    fb = gate.fallback(X)
     info = {"rows": int(matrix.n), "fallback_rows": int(fb.sum()), "sweeps": 0}
     if fb.any():
         with sampler_factory(matrix) as s:

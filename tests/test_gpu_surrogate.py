@@ -190,6 +190,15 @@ def test_training_beats_neumann_baselines_and_gate_falls_back():
         gate = sur.Gate(Xv, pv, yv, np.zeros_like(yv), feature_a=1, feature_b=5, bins=4, min_rows=20,
                         tol=0.005)
         m = mats[9]
+        # the one-call estimate equals features -> predict -> gate, bit for bit
+        X9 = sur.features(m)
+        p_one, fb_one = net.estimate_matrix(m, gate)
+        assert np.array_equal(p_one, net.predict(X9))
+        assert np.array_equal(fb_one.astype(bool), gate.fallback(X9))
+        bad = gen.diag_matrix(np.array([1.0, 0.0, 2.0]))
+        with pytest.raises(mc.McinvError) as ei:
+            net.estimate_matrix(bad, gate)
+        assert ei.value.code == mc.MCINV_ESINGULAR and "diagonal" in str(ei.value)
         est, src, info = sur.estimate_diag(
             m, net, gate, lambda mm: mc.Sampler(mm, pairs=256, groups=16, dtype="f32", seed=9),
             rel_se=0.02, max_sweeps=4000, check_every=20, burn_in=100)
