@@ -519,14 +519,15 @@ void mcinv_gate_destroy(mcinv_gate* g);
 /* The surrogate's whole estimate of one matrix in one call: the features of
  * the real CSR matrix (rules of mcinv_features) are computed on the network's
  * device and fed to the network there, so only the predictions and the gate's
- * two binning features cross to the host.  pred[n] = the network's output
- * (c_ii (C^-1)_ii, as mcinv_mlp_predict on mcinv_features' output), fallback[n]
- * = the gate's decision per row (as mcinv_gate_apply on those features).
- * Both caller-allocated.  ESINGULAR / EINVAL as mcinv_features; the message is
- * available from mcinv_mlp_last_error(m). */
+ * two binning features cross to the host.  est[n] = the surrogate's estimate
+ * of (C^-1)_ii: the network's output (c_ii (C^-1)_ii, as mcinv_mlp_predict on
+ * mcinv_features' output) divided by c_ii in fp64; fallback[n] = the gate's
+ * decision per row (as mcinv_gate_apply on those features), 1 where est must
+ * come from the sampler instead.  Both caller-allocated.  ESINGULAR / EINVAL
+ * as mcinv_features; the message is available from mcinv_mlp_last_error(m). */
 mcinv_status mcinv_mlp_estimate_matrix(mcinv_mlp* m, const mcinv_gate* g, int64_t n, int64_t nnz,
                                        const int64_t* row_ptr, const int32_t* col_idx, const double* values,
-                                       float* pred, uint8_t* fallback);
+                                       double* est, uint8_t* fallback);
 const char* mcinv_gate_last_error(void);
 
 #ifdef __cplusplus

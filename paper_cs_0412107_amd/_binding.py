@@ -623,16 +623,16 @@ def mcinv_gate_apply(g, X):
 
 
 def mcinv_mlp_estimate_matrix(m, g, n, nnz, row_ptr, col_idx, values):
-    """(network predictions float32[n], gate fallback uint8[n]) for a real CSR
-    matrix, its features computed and consumed on the device."""
+    """(estimates of (C^-1)_ii float64[n], gate fallback uint8[n]) for a real
+    CSR matrix, its features computed and consumed on the device."""
     rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
     ci = np.ascontiguousarray(col_idx, dtype=np.int32)
     v = np.ascontiguousarray(values, dtype=np.float64)
-    pred = np.empty(int(n), dtype=np.float32)
+    est = np.empty(int(n), dtype=np.float64)
     fb = np.empty(int(n), dtype=np.uint8)
-    _mcheck(m, lib().mcinv_mlp_estimate_matrix(m, g, int(n), int(nnz), _ptr(rp), _ptr(ci), _ptr(v), _ptr(pred),
+    _mcheck(m, lib().mcinv_mlp_estimate_matrix(m, g, int(n), int(nnz), _ptr(rp), _ptr(ci), _ptr(v), _ptr(est),
                                                _ptr(fb)))
-    return pred, fb
+    return est, fb
 
 
 def mcinv_gate_read(g, bins):

@@ -248,7 +248,8 @@ __global__ __launch_bounds__(256) void k_ft_pick(int64_t n, const float* F, int3
 }
 
 mcinv_status features_on_device(int32_t device, int64_t n, int64_t nnz, const int64_t* row_ptr,
-                                const int32_t* col_idx, const double* values, float** d_features, std::string* err)
+                                const int32_t* col_idx, const double* values, float** d_features, std::string* err,
+                                std::vector<double>* diag_out)
 {
     *d_features = nullptr;
     std::vector<cd> diag;
@@ -260,6 +261,7 @@ mcinv_status features_on_device(int32_t device, int64_t n, int64_t nnz, const in
     }
     std::vector<double> d(n);
     for (int64_t i = 0; i < n; ++i) d[i] = diag[i].real();
+    if (diag_out) *diag_out = d;
     if (hipSetDevice(device) != hipSuccess) {
         *err = "no such device";
         return MCINV_EDEVICE;

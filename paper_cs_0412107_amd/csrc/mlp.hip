@@ -888,12 +888,14 @@ try {
 
 mcinv_status mcinv_mlp_estimate_matrix(mcinv_mlp* m, const mcinv_gate* g, int64_t n, int64_t nnz,
                                        const int64_t* row_ptr, const int32_t* col_idx, const double* values,
-                                       float* pred, uint8_t* fallback)
+                                       double* est, uint8_t* fallback)
 try {
-    if (!m || !g || !pred || !fallback) return merr(m, MCINV_EINVAL, "estimate_matrix: null argument");
+    if (!m || !g || !est || !fallback) return merr(m, MCINV_EINVAL, "estimate_matrix: null argument");
     std::string why;
     float* dF = nullptr;
-    mcinv_status st = mcinv::features_on_device(m->device, n, nnz, row_ptr, col_idx, values, &dF, &why);
+    std::vector<double> diag;
+    mcinv_status st = mcinv::features_on_device(m->device, n, nnz, row_ptr, col_idx, values, &dF, &why, &diag);
+    std::vector<float> pred(st == MCINV_OK ? (size_t)n : 0);
     if (st != MCINV_OK) return merr(m, st, "estimate_matrix: features: " + why);
     float* dout = nullptr;
     std::vector<float> two;
@@ -902,7 +904,7 @@ try {
         why = "device allocation failed";
     }
     if (st == MCINV_OK) st = mcinv::mlp_predict_device(m, dF, n, dout, &why);
-    if (st == MCINV_OK && hipMemcpy(pred, dout, sizeof(float) * n, hipMemcpyDeviceToHost) != hipSuccess) {
+    if (st == MCINV_OK && hipMemcpy(pred.data(), dout, sizeof(float) * n, hipMemcpyDeviceToHost) != hipSuccess) {
         st = MCINV_EDEVICE;
         why = "copying the predictions failed";
     }
@@ -914,6 +916,7 @@ try {
     (void)hipFree(dF);
     if (st != MCINV_OK) return merr(m, st, "estimate_matrix: " + why);
     mcinv::gate_fallback_rows(g, n, two.data(), 2, 0, 1, fallback);
+    for (int64_t i = 0; i < n; ++i) est[i] = (double)pred[i] / diag[i];   // the network predicts c_ii (C^-1)_ii
     return MCINV_OK;
 } catch (...) {
     return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { merr(m, s_, m_); });

@@ -5,6 +5,7 @@
 
 #include <cstdint>
 #include <string>
+#include <vector>
 
 #include "../../include/mcinv.h"
 
@@ -13,8 +14,10 @@ namespace mcinv {
 // Features of a real CSR matrix (validated here) computed on `device`:
 // *d_features receives [n][MCINV_N_FEATURES] floats in device memory that the
 // caller releases with hipFree.  Returns a status; on failure *err says why.
+// diag (may be NULL) receives c_ii per row (host).
 mcinv_status features_on_device(int32_t device, int64_t n, int64_t nnz, const int64_t* row_ptr,
-                                const int32_t* col_idx, const double* values, float** d_features, std::string* err);
+                                const int32_t* col_idx, const double* values, float** d_features, std::string* err,
+                                std::vector<double>* diag = nullptr);
 
 // Columns a and b of device features [n][MCINV_N_FEATURES] into host out[n][2].
 mcinv_status features_pick_two(const float* d_features, int64_t n, int32_t a, int32_t b, float* out,

@@ -96,8 +96,8 @@ class Network:
         return B.mcinv_mlp_predict(self.h, X)
 
     def estimate_matrix(self, matrix, gate):
-        """(predictions, gate fallback flags) for a matrix, its features made
-        and used on the device (``mcinv_mlp_estimate_matrix``)."""
+        """(estimates of (C^-1)_ii, gate fallback flags) for a matrix, its
+        features made and used on the device (``mcinv_mlp_estimate_matrix``)."""
         return B.mcinv_mlp_estimate_matrix(self.h, gate.h, matrix.n, matrix.nnz, matrix.row_ptr, matrix.col,
                                            matrix.val)
 
@@ -137,11 +137,8 @@ def estimate_diag(matrix, net, gate, sampler_factory, rel_se=0.01, max_sweeps=20
     to 5e-5).
     Returns (estimate, source) with source 0 = network, 1 = sampler, and a
     dict of counts and sweeps."""
-    y_hat, fb = net.estimate_matrix(matrix, gate)
-    y_hat = y_hat.astype(np.float64)
+    est, fb = net.estimate_matrix(matrix, gate)
     fb = fb.astype(bool)
-    d = _diag(matrix)
-    est = y_hat / d
     info = {"rows": int(matrix.n), "fallback_rows": int(fb.sum()), "sweeps": 0}
     if fb.any():
         with sampler_factory(matrix) as s:
