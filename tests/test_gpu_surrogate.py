@@ -39,12 +39,15 @@ def _odd_matrix():
     return gen.from_dense(A)
 
 
-@pytest.mark.parametrize("case", ["pedigree", "random", "odd"])
+@pytest.mark.parametrize("case", ["pedigree", "random", "odd", "one", "diagonal"])
 def test_features_match_oracle(case):
     print_case(test="features", case=case)
     m = {"pedigree": lambda: gen.pedigree(3001, seed=41, lam=0.3, founders=0.1),
          "random": lambda: gen.random_dominant(1000, 4, seed=42, factor=1.3),
-         "odd": _odd_matrix}[case]()
+         "odd": _odd_matrix,
+         "one": lambda: gen.diag_matrix(np.array([-2.5])),                 # n = 1: one row, no neighbours
+         "diagonal": lambda: gen.diag_matrix(np.linspace(0.5, 3.0, 700)),  # no off-diagonal entries
+         }[case]()
     got = sur.features(m)
     ref = S.features(m)
     assert got.shape == (m.n, 32) and got.dtype == np.float32
