@@ -25,6 +25,22 @@ def _need_gpu():
         pytest.skip("no GPU")
 
 
+def _hub_matrix():
+    """Row 0 couples to every row and column 0 to about half of them, plus two
+    random entries per row: one long merged list next to short ones."""
+    rng = np.random.default_rng(23)
+    n = 2500
+    A = np.zeros((n, n))
+    A[0, 1:] = rng.uniform(-1, 1, n - 1)
+    half = np.arange(1, n)[rng.random(n - 1) < 0.5]
+    A[half, 0] = rng.uniform(-1, 1, half.size)
+    r = np.repeat(np.arange(n), 2)
+    A[r, rng.integers(0, n, 2 * n)] += rng.uniform(-1, 1, 2 * n)
+    np.fill_diagonal(A, 0)
+    np.fill_diagonal(A, 1.5 * np.maximum(np.abs(A).sum(axis=1), np.abs(A).sum(axis=0)) + 0.1)
+    return gen.from_dense(A)
+
+
 def _odd_matrix():
     """Small matrix with an isolated row, one-sided entries and negative diagonals."""
     rng = np.random.default_rng(3)
@@ -39,7 +55,7 @@ def _odd_matrix():
     return gen.from_dense(A)
 
 
-@pytest.mark.parametrize("case", ["pedigree", "random", "odd", "one", "diagonal"])
+@pytest.mark.parametrize("case", ["pedigree", "random", "odd", "one", "diagonal", "hub"])
 def test_features_match_oracle(case):
     print_case(test="features", case=case)
     m = {"pedigree": lambda: gen.pedigree(3001, seed=41, lam=0.3, founders=0.1),
@@ -47,6 +63,7 @@ def test_features_match_oracle(case):
          "odd": _odd_matrix,
          "one": lambda: gen.diag_matrix(np.array([-2.5])),                 # n = 1: one row, no neighbours
          "diagonal": lambda: gen.diag_matrix(np.linspace(0.5, 3.0, 700)),  # no off-diagonal entries
+         "hub": _hub_matrix,
          }[case]()
     got = sur.features(m)
     ref = S.features(m)
