@@ -266,13 +266,19 @@ mcinv_status features_on_device(int32_t device, int64_t n, int64_t nnz, const in
         *err = "no such device";
         return MCINV_EDEVICE;
     }
-    // device buffers, all released at the end whatever happens
-    std::vector<void*> owned;
+    // device buffers, released on every exit (the features buffer is handed over on success)
+    struct Owned {
+        std::vector<void*> p;
+        ~Owned()
+        {
+            for (void* x : p) (void)hipFree(x);
+        }
+    } owned;
     hipError_t e = hipSuccess;
     auto alloc = [&](void** p, size_t bytes) {
         *p = nullptr;
         if (e == hipSuccess) e = hipMalloc(p, std::max<size_t>(bytes, 1));
-        if (e == hipSuccess) owned.push_back(*p);
+        if (e == hipSuccess) owned.p.push_back(*p);
     };
     int64_t *d_rp = nullptr, *d_tp = nullptr, *d_beg = nullptr;
     int32_t *d_col = nullptr, *d_ccount = nullptr, *d_cnt = nullptr;
@@ -344,8 +350,7 @@ mcinv_status features_on_device(int32_t device, int64_t n, int64_t nnz, const in
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
-    for (void* p : owned)
-        if (p != (void*)d_out || e != hipSuccess) (void)hipFree(p);
+    if (e == hipSuccess) owned.p.erase(std::find(owned.p.begin(), owned.p.end(), (void*)d_out));
     if (e != hipSuccess) {
         *err = hipGetErrorString(e);
         return e == hipErrorOutOfMemory ? MCINV_ENOMEM : MCINV_EDEVICE;

@@ -893,13 +893,23 @@ try {
     if (!m || !g || !est || !fallback) return merr(m, MCINV_EINVAL, "estimate_matrix: null argument");
     std::string why;
     float* dF = nullptr;
+    float* dout = nullptr;
+    struct Release {   // the two device buffers, on every exit
+        float** a;
+        float** b;
+        ~Release()
+        {
+            if (*a) (void)hipFree(*a);
+            if (*b) (void)hipFree(*b);
+        }
+    } release{&dF, &dout};
     std::vector<double> diag;
     mcinv_status st = mcinv::features_on_device(m->device, n, nnz, row_ptr, col_idx, values, &dF, &why, &diag);
-    std::vector<float> pred(st == MCINV_OK ? (size_t)n : 0);
     if (st != MCINV_OK) return merr(m, st, "estimate_matrix: features: " + why);
-    float* dout = nullptr;
+    std::vector<float> pred((size_t)n);
     std::vector<float> two;
     if (hipMalloc((void**)&dout, sizeof(float) * (size_t)std::max<int64_t>(n, 1)) != hipSuccess) {
+        dout = nullptr;
         st = MCINV_ENOMEM;
         why = "device allocation failed";
     }
@@ -912,8 +922,6 @@ try {
         two.resize((size_t)n * 2);
         st = mcinv::features_pick_two(dF, n, mcinv::gate_feature_a(g), mcinv::gate_feature_b(g), two.data(), &why);
     }
-    if (dout) mfree(dout);
-    (void)hipFree(dF);
     if (st != MCINV_OK) return merr(m, st, "estimate_matrix: " + why);
     mcinv::gate_fallback_rows(g, n, two.data(), 2, 0, 1, fallback);
     for (int64_t i = 0; i < n; ++i) est[i] = (double)pred[i] / diag[i];   // the network predicts c_ii (C^-1)_ii
