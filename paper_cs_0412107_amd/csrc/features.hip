@@ -287,17 +287,34 @@ mcinv_status features_on_device(int32_t device, int64_t n, int64_t nnz, const in
     FEnt* d_ent = nullptr;
     float* d_out = nullptr;
     void* d_tmp = nullptr;
-    alloc((void**)&d_rp, sizeof(int64_t) * ((size_t)n + 1));
-    alloc((void**)&d_col, sizeof(int32_t) * (size_t)nnz);
-    alloc((void**)&d_val, sizeof(double) * (size_t)nnz);
-    alloc((void**)&d_key, sizeof(uint64_t) * (size_t)nnz);
-    alloc((void**)&d_tkey, sizeof(uint64_t) * (size_t)nnz);
-    alloc((void**)&d_tval, sizeof(double) * (size_t)nnz);
-    alloc((void**)&d_ccount, sizeof(int32_t) * (size_t)n);
-    alloc((void**)&d_tp, sizeof(int64_t) * ((size_t)n + 1));
-    alloc((void**)&d_cnt, sizeof(int32_t) * (size_t)n);
-    alloc((void**)&d_beg, sizeof(int64_t) * ((size_t)n + 1));
-    alloc((void**)&d_d, sizeof(double) * (size_t)n);
+    // sort only the bits that keys below n^2 can use
+    unsigned bits = 1;
+    while (bits < 64 && ((unsigned __int128)1 << bits) < (unsigned __int128)n * (unsigned __int128)n) ++bits;
+    size_t tmp_bytes = 0;
+    e = rocprim::radix_sort_pairs(nullptr, tmp_bytes, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+                                  (const double*)nullptr, (double*)nullptr, (size_t)nnz, 0u, bits);
+    // every scratch buffer is a 256-byte-aligned part of one allocation (few
+    // allocations per call: small matrices are called many times)
+    const std::pair<void**, size_t> parts[] = {
+        {(void**)&d_rp, sizeof(int64_t) * ((size_t)n + 1)}, {(void**)&d_col, sizeof(int32_t) * (size_t)nnz},
+        {(void**)&d_val, sizeof(double) * (size_t)nnz},     {(void**)&d_key, sizeof(uint64_t) * (size_t)nnz},
+        {(void**)&d_tkey, sizeof(uint64_t) * (size_t)nnz},  {(void**)&d_tval, sizeof(double) * (size_t)nnz},
+        {(void**)&d_ccount, sizeof(int32_t) * (size_t)n},   {(void**)&d_tp, sizeof(int64_t) * ((size_t)n + 1)},
+        {(void**)&d_cnt, sizeof(int32_t) * (size_t)n},      {(void**)&d_beg, sizeof(int64_t) * ((size_t)n + 1)},
+        {(void**)&d_d, sizeof(double) * (size_t)n},         {(void**)&d_F, sizeof(double) * (size_t)n * kNF},
+        {&d_tmp, tmp_bytes}};
+    auto padded = [](size_t b) { return (b + 255) / 256 * 256; };
+    size_t slab_bytes = 0;
+    for (const auto& pr : parts) slab_bytes += padded(pr.second);
+    char* slab = nullptr;
+    alloc((void**)&slab, slab_bytes);
+    if (e == hipSuccess) {
+        size_t at = 0;
+        for (const auto& pr : parts) {
+            *pr.first = slab + at;
+            at += padded(pr.second);
+        }
+    }
     if (e == hipSuccess) e = hipMemcpy(d_rp, row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice);
     if (e == hipSuccess && nnz > 0) e = hipMemcpy(d_col, col_idx, sizeof(int32_t) * nnz, hipMemcpyHostToDevice);
     if (e == hipSuccess && nnz > 0) e = hipMemcpy(d_val, values, sizeof(double) * nnz, hipMemcpyHostToDevice);
@@ -308,15 +325,8 @@ mcinv_status features_on_device(int32_t device, int64_t n, int64_t nnz, const in
         k_ft_keys<<<blocks, 256>>>(n, d_rp, d_col, d_key, d_ccount);
         e = hipGetLastError();
     }
-    // sort only the bits that keys below n^2 can use
-    unsigned bits = 1;
-    while (bits < 64 && ((unsigned __int128)1 << bits) < (unsigned __int128)n * (unsigned __int128)n) ++bits;
-    size_t tmp_bytes = 0;
     const uint64_t* ckey = d_key;   // inputs of the sort (d_val is read again by the merge)
     const double* cval = d_val;
-    if (e == hipSuccess)
-        e = rocprim::radix_sort_pairs(nullptr, tmp_bytes, ckey, d_tkey, cval, d_tval, (size_t)nnz, 0u, bits);
-    alloc(&d_tmp, tmp_bytes);
     if (e == hipSuccess)
         e = rocprim::radix_sort_pairs(d_tmp, tmp_bytes, ckey, d_tkey, cval, d_tval, (size_t)nnz, 0u, bits);
     if (e == hipSuccess) {
@@ -338,7 +348,6 @@ mcinv_status features_on_device(int32_t device, int64_t n, int64_t nnz, const in
         k_ft_merge<<<blocks, 256>>>(n, d_rp, d_col, d_val, d_tp, d_tkey, d_tval, d_beg, d_ent, d_cnt);
         e = hipGetLastError();
     }
-    alloc((void**)&d_F, sizeof(double) * (size_t)n * kNF);
     alloc((void**)&d_out, sizeof(float) * (size_t)n * kNF);
     if (e == hipSuccess) e = hipMemset(d_F, 0, sizeof(double) * n * kNF);
     if (e == hipSuccess) {
