@@ -5,7 +5,8 @@
 // terms of that series and neighbourhood statistics (list in include/mcinv.h,
 // mcinv_features).  Pass 1 computes the per-row terms; pass 2 the statistics
 // over each row's merged neighbours (row i or column i of C) from pass 1's
-// output.  fp64 arithmetic, one thread per row, fp32 output.
+// output.  fp64 arithmetic (pass 1: eight lanes per row; pass 2: one thread
+// per row), fp32 output.
 #include <hip/hip_runtime.h>
 #include <rocprim/device/device_radix_sort.hpp>
 
@@ -120,28 +121,35 @@ __global__ __launch_bounds__(256) void k_ft_merge(int64_t n, const int64_t* rp, 
     if (!o) cnt[i] = k;
 }
 
+// Pass 1: kRowLanes lanes per row, each taking every kRowLanes-th merged
+// neighbour; the partial sums meet in an xor-shuffle tree within the lane
+// group (fixed order, so the result is deterministic).
+constexpr int kRowLanes = 8;
+
 __global__ __launch_bounds__(256) void k_features_pass1(int64_t n, const int64_t* beg, const int32_t* cnt,
                                                         const FEnt* ent, const double* d, double* F)
 {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const FEnt* e = ent + beg[i];
-    const int32_t c = cnt[i];
-    const double di = d[i], adi = fabs(di);
-    double rs = 0, cs = 0, nr = 0, nc = 0, m2 = 0, m3 = 0, a2 = 0, sq = 0, srow = 0, scol = 0;
-    for (int32_t t = 0; t < c; ++t) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = gid / kRowLanes;
+    const int lane = (int)(gid % kRowLanes);
+    const bool valid = i < n;   // a lane group lies in one row, so groups are wholly valid or not
+    const FEnt* e = valid ? ent + beg[i] : ent;
+    const int32_t c = valid ? cnt[i] : 0;
+    const double di = valid ? d[i] : 1.0;
+    double v[11] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};   // rs cs nr nc m2 m3 a2 sq srow scol (unused)
+    for (int32_t t = lane; t < c; t += kRowLanes) {
         const int32_t j = e[t].col;
         const double cij = e[t].cij, cji = e[t].cji, dj = d[j];
-        rs += fabs(cij);
-        cs += fabs(cji);
-        nr += cij != 0.0 ? 1.0 : 0.0;
-        nc += cji != 0.0 ? 1.0 : 0.0;
+        v[0] += fabs(cij);
+        v[1] += fabs(cji);
+        v[2] += cij != 0.0 ? 1.0 : 0.0;
+        v[3] += cji != 0.0 ? 1.0 : 0.0;
         const double mij = cij / di, mji = cji / dj;
-        m2 += mij * mji;
-        a2 += fabs(mij) * fabs(mji);
-        sq += mij * mij;
-        srow += cij;
-        scol += cji;
+        v[4] += mij * mji;
+        v[6] += fabs(mij) * fabs(mji);
+        v[7] += mij * mij;
+        v[8] += cij;
+        v[9] += cji;
         if (cij != 0.0) {
             // sum_k m_jk m_ki over the stored entries of row j
             const FEnt* ej = ent + beg[j];
@@ -153,9 +161,16 @@ __global__ __launch_bounds__(256) void k_features_pass1(int64_t n, const int64_t
                 const double cki = lookup_cji(e, c, k);
                 inner += (ej[u].cij / dj) * (cki / d[k]);
             }
-            m3 += mij * inner;
+            v[5] += mij * inner;
         }
     }
+#pragma unroll
+    for (int q = 0; q < 10; ++q)
+        for (int off = 1; off < kRowLanes; off <<= 1) v[q] += __shfl_xor(v[q], off);
+    if (!valid || lane != 0) return;
+    const double adi = fabs(di);
+    const double rs = v[0], cs = v[1], nr = v[2], nc = v[3], m2 = v[4], m3 = v[5], a2 = v[6], sq = v[7],
+                 srow = v[8], scol = v[9];
     double* f = F + i * kNF;
     f[0] = log(adi);
     f[1] = rs / adi;
@@ -351,7 +366,7 @@ mcinv_status features_on_device(int32_t device, int64_t n, int64_t nnz, const in
     alloc((void**)&d_out, sizeof(float) * (size_t)n * kNF);
     if (e == hipSuccess) e = hipMemset(d_F, 0, sizeof(double) * n * kNF);
     if (e == hipSuccess) {
-        k_features_pass1<<<blocks, 256>>>(n, d_beg, d_cnt, d_ent, d_d, d_F);
+        k_features_pass1<<<(unsigned)((n * kRowLanes + 255) / 256), 256>>>(n, d_beg, d_cnt, d_ent, d_d, d_F);
         e = hipGetLastError();
     }
     if (e == hipSuccess) {
