@@ -67,14 +67,15 @@ __global__ __launch_bounds__(256) void k_ft_keys(int64_t n, const int64_t* rp, c
 }
 
 // out[k] = in[0] + ... + in[k-1] for k = 0..n (one workgroup: a chunk per
-// thread, the chunk sums scanned in LDS)
-__global__ __launch_bounds__(1024) void k_ft_scan(int64_t n, const int32_t* in, int64_t* out)
+// thread, the chunk sums scanned in LDS); used on the per-tile sums below
+template <typename T>
+__global__ __launch_bounds__(1024) void k_ft_scan(int64_t n, const T* in, int64_t* out)
 {
     __shared__ int64_t part[1024];
     const int64_t per = (n + 1023) / 1024;
     const int64_t b = (int64_t)threadIdx.x * per, e = b + per < n ? b + per : n;
     int64_t s = 0;
-    for (int64_t k = b; k < e; ++k) s += in[k];
+    for (int64_t k = b; k < e; ++k) s += (int64_t)in[k];
     part[threadIdx.x] = s;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {
@@ -86,9 +87,57 @@ __global__ __launch_bounds__(1024) void k_ft_scan(int64_t n, const int32_t* in, 
     int64_t run = part[threadIdx.x] - s;
     for (int64_t k = b; k < e; ++k) {
         out[k] = run;
-        run += in[k];
+        run += (int64_t)in[k];
     }
     if (threadIdx.x == 1023) out[n] = part[1023];
+}
+
+// Exclusive scan of int32 counts over tiles of 1024: the tiles' sums, their
+// scan (k_ft_scan), then each tile's own scan plus its offset.
+__global__ __launch_bounds__(1024) void k_ft_tile_sums(int64_t n, const int32_t* in, int64_t* sums)
+{
+    __shared__ int64_t ws[16];
+    const int64_t k = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    int64_t v = k < n ? (int64_t)in[k] : 0;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t t = 0;
+        for (int w = 0; w < 16; ++w) t += ws[w];
+        sums[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_ft_tile_scan(int64_t n, const int32_t* in, const int64_t* offs,
+                                                       int64_t* out)
+{
+    __shared__ int64_t ws[16];
+    const int64_t k = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t x = k < n ? (int64_t)in[k] : 0;
+    int64_t v = x;   // inclusive scan within the wave
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t y = __shfl_up(v, off);
+        if (lane >= off) v += y;
+    }
+    if (lane == 63) ws[w] = v;
+    __syncthreads();
+    int64_t before = offs[blockIdx.x];
+    for (int q = 0; q < w; ++q) before += ws[q];
+    if (k < n) out[k] = before + v - x;
+    if (k == n - 1) out[n] = before + v;
+}
+
+// out[0..n] = exclusive prefix sums of in[0..n); tsum / toff hold
+// ceil(n / 1024) and ceil(n / 1024) + 1 values
+inline hipError_t scan_counts(int64_t n, const int32_t* in, int64_t* out, int64_t* tsum, int64_t* toff)
+{
+    const int64_t nt = (n + 1023) / 1024;
+    k_ft_tile_sums<<<(unsigned)nt, 1024>>>(n, in, tsum);
+    k_ft_scan<int64_t><<<1, 1024>>>(nt, tsum, toff);
+    k_ft_tile_scan<<<(unsigned)nt, 1024>>>(n, in, toff, out);
+    return hipGetLastError();
 }
 
 // Row i's merged list: the union of row i (col, val) and column i (the sorted
@@ -302,6 +351,8 @@ mcinv_status features_on_device(int32_t device, int64_t n, int64_t nnz, const in
     FEnt* d_ent = nullptr;
     float* d_out = nullptr;
     void* d_tmp = nullptr;
+    int64_t *d_tsum = nullptr, *d_toff = nullptr;
+    const int64_t ntiles = (n + 1023) / 1024;
     // sort only the bits that keys below n^2 can use
     unsigned bits = 1;
     while (bits < 64 && ((unsigned __int128)1 << bits) < (unsigned __int128)n * (unsigned __int128)n) ++bits;
@@ -317,6 +368,7 @@ mcinv_status features_on_device(int32_t device, int64_t n, int64_t nnz, const in
         {(void**)&d_ccount, sizeof(int32_t) * (size_t)n},   {(void**)&d_tp, sizeof(int64_t) * ((size_t)n + 1)},
         {(void**)&d_cnt, sizeof(int32_t) * (size_t)n},      {(void**)&d_beg, sizeof(int64_t) * ((size_t)n + 1)},
         {(void**)&d_d, sizeof(double) * (size_t)n},         {(void**)&d_F, sizeof(double) * (size_t)n * kNF},
+        {(void**)&d_tsum, sizeof(int64_t) * (size_t)ntiles}, {(void**)&d_toff, sizeof(int64_t) * ((size_t)ntiles + 1)},
         {&d_tmp, tmp_bytes}};
     auto padded = [](size_t b) { return (b + 255) / 256 * 256; };
     size_t slab_bytes = 0;
@@ -344,18 +396,12 @@ mcinv_status features_on_device(int32_t device, int64_t n, int64_t nnz, const in
     const double* cval = d_val;
     if (e == hipSuccess)
         e = rocprim::radix_sort_pairs(d_tmp, tmp_bytes, ckey, d_tkey, cval, d_tval, (size_t)nnz, 0u, bits);
-    if (e == hipSuccess) {
-        k_ft_scan<<<1, 1024>>>(n, d_ccount, d_tp);
-        e = hipGetLastError();
-    }
+    if (e == hipSuccess) e = scan_counts(n, d_ccount, d_tp, d_tsum, d_toff);
     if (e == hipSuccess) {
         k_ft_merge<<<blocks, 256>>>(n, d_rp, d_col, d_val, d_tp, d_tkey, d_tval, nullptr, nullptr, d_cnt);
         e = hipGetLastError();
     }
-    if (e == hipSuccess) {
-        k_ft_scan<<<1, 1024>>>(n, d_cnt, d_beg);
-        e = hipGetLastError();
-    }
+    if (e == hipSuccess) e = scan_counts(n, d_cnt, d_beg, d_tsum, d_toff);
     int64_t nent = 0;
     if (e == hipSuccess) e = hipMemcpy(&nent, d_beg + n, sizeof(int64_t), hipMemcpyDeviceToHost);
     alloc((void**)&d_ent, sizeof(FEnt) * (size_t)nent);
