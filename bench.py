@@ -83,13 +83,14 @@ def tuned_order(pkg, m, P, G, dtype, hermitian=False):
     return order
 
 
-def time_to_1pct(pkg, torch, m, P, G, seed, dtype, moments, burn_in, rel=0.01, check=10, max_sweeps=20000,
-                 hermitian=False, xcd_order=0, noise=0):
+def time_to_1pct(pkg, torch, m, P, G, seed, dtype, moments, burn_in, rel=0.01, check=2, max_sweeps=20000,
+                 hermitian=False, xcd_order=0, noise=0, keep_pairs=None):
     """Wall time to max_i SE_i/|est_i| <= rel on the whole diagonal, counted
     from the start of burn-in (a fixed count, or "coupled": until the coupled
     paths agree to BURN_TOL), sampling checked every `check` sweeps; the
     context set-up before it (matrix preparation and upload) is reported
-    separately."""
+    separately.  keep_pairs: chain pairs whose final z and w columns are
+    returned (under "_state"), for a comparison with the oracle."""
     torch.cuda.synchronize()
     t_setup = time.perf_counter()
     s = pkg.Sampler(m, pairs=P, groups=G, dtype=dtype, seed=seed, moments=moments, use_torch_stream=True,
@@ -109,7 +110,10 @@ def time_to_1pct(pkg, torch, m, P, G, seed, dtype, moments, burn_in, rel=0.01, c
     t = time.perf_counter() - t0
     out = {"seconds": t, "setup_seconds": t_setup, "burn_in": nb, "burn_in_rule": burn_desc,
            "sample_sweeps": done, "max_rel_se": ach, "form": f"{dtype} sweeps, {moments} blocks",
-           "noise": ["normal", "Z2"][noise], "xcd_order": ORDER_NAMES[xcd_order]}
+           "noise": ["normal", "Z2"][noise], "xcd_order": ORDER_NAMES[xcd_order], "check_every": check}
+    if keep_pairs is not None:
+        out["_state"] = {"pairs": np.asarray(keep_pairs), "z": s.state(0)[:, keep_pairs],
+                         "w": s.state(1)[:, keep_pairs], "sweeps": nb + done, "seed": seed}
     if dtype == "f32":
         # the same chains in fp64 (same matrix values, noise, burn-in and sample
         # sweeps; the fp64 path is the one tested against the oracle to 1e-12):
@@ -242,16 +246,36 @@ def hermitian_form(pkg, torch, gen, w, steps=20):
     return out
 
 
-def dirac_form(pkg, torch, gen):
-    """The paper's second example, case 1: free Wilson-Dirac matrix on an 18^4
-    lattice (K = 0.1, rank 419904, 14 nonzeros per row), trace of the inverse
-    to the paper's stopping rule (Geyer standard error below 1e-5 of the
-    estimate), coupled burn-in to 5e-5; compared with the closed form."""
-    from oracle import theory  # the exact value only (a closed form), not the sampler
+def paper_dirac_values():
+    """The paper's printed values for its second example (Sec. 3.2): exact
+    traces (Tables 4, 5, two decimals) and the CC method's burn-in, sample
+    count, effective length, variance, MC standard error and estimate."""
+    gold = os.path.join(ROOT, "tests", "golden")
+    with open(os.path.join(gold, "dirac_free_field.json")) as f:
+        cases = {c["N"]: c for c in json.load(f)["cases"]}
+    with open(os.path.join(gold, "paper_tables.json")) as f:
+        rows = {r["case"]: r for r in json.load(f)["rows"]}
+    burn = {18: 18, 20: 18}   # Tables 4, 5: burn-in cycles N
+    out = {}
+    for N in (18, 20):
+        r = rows[f"{N}^4"]
+        out[N] = {"exact": cases[N]["exact_trace"], "burn_in": burn[N], "samples": r["samples"],
+                  "n_eff": r["n_eff"], "var": r["var"], "se": r["se"], "estimate_re": r["estimate"],
+                  "table": cases[N]["table"]}
+    return out
+
+
+def dirac_form(pkg, torch, gen, N):
+    """The paper's second example: free Wilson-Dirac matrix on an N^4 lattice
+    (K = 0.1, 14 nonzeros per row; case 1 N = 18, case 2 N = 20), trace of
+    the inverse to the paper's stopping rule (Geyer standard error below 1e-5
+    of the estimate), coupled burn-in to 5e-5; compared with the exact value
+    and the run statistics the paper prints (Tables 3-5)."""
     w = gen.WORKLOADS["dirac"]
-    m = gen.round_values(gen.dirac(w["N"], w["K"]), np.complex64)
+    paper = paper_dirac_values()[N]
+    m = gen.round_values(gen.dirac(N, w["K"]), np.complex64)
     P, G, seed = w["pairs"], w["groups"], w["noise_seed"]
-    exact = theory.dirac_free_trace(w["N"], w["K"])
+    exact = paper["exact"]
     order = tuned_order(pkg, m, P, G, "c64")
 
     def run(noise):
@@ -259,28 +283,75 @@ def dirac_form(pkg, torch, gen):
         t0 = time.perf_counter()
         s = pkg.Sampler(m, pairs=P, groups=G, dtype="c64", seed=seed, use_torch_stream=True, xcd_order=order,
                         noise=noise)
-        N, _, _ = s.burn_in_coupled(BURN_TOL, 10000)
+        nb, _, _ = s.burn_in_coupled(BURN_TOL, 10000)
         s.request(diag=False, trace=True)
         done, ach = s.sample_until_trace(w["rel_se"], 20000, 20)
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
-        est, se = s.trace()
+        st = s.trace_stats()
+        est, se = st["mean"], st["se"]
         t1 = time.perf_counter()
         s.sample(10)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t1) * 1e3 / 10
         s.close()
-        return {"seconds": t, "burn_in": N, "sample_sweeps": done, "rel_se": ach,
-                "estimate": [float(np.real(est)), float(np.imag(est))], "se": float(se),
-                "z_score": float((np.real(est) - exact) / se), "ms_per_sweep": ms}
+        z = float((est.real - exact) / se)
+        return {"seconds": t, "burn_in": nb, "sample_sweeps": done, "rel_se": ach,
+                "estimate": [est.real, est.imag], "se": se, "z_score": z, "within_5se": abs(z) <= 5.0,
+                "variance_series": st["var"], "effective_length_series": st["n_eff"],
+                "variance_per_pair": st["var"] * P, "effective_length_pair_sweeps": st["n_eff"] * P,
+                "ms_per_sweep": ms}
 
-    out = {"workload": f"free Wilson-Dirac 18^4 (n={m.n}, nnz={m.nnz}), K={w['K']}, {P} pairs, complex64",
-           "exact": exact, **run(pkg.MCINV_NOISE_NORMAL), "xcd_order": ORDER_NAMES[order],
-           "paper_case1": {"burn_in": 18, "sample_cycles": 10832, "chain_pairs": 1}}
+    out = {"workload": f"free Wilson-Dirac {N}^4 (n={m.n}, nnz={m.nnz}), K={w['K']}, {P} pairs, complex64",
+           "exact_paper": exact, **run(pkg.MCINV_NOISE_NORMAL), "xcd_order": ORDER_NAMES[order],
+           "paper": {"table": paper["table"], "chain_pairs": 1, "burn_in": paper["burn_in"],
+                     "samples": paper["samples"], "effective_length": paper["n_eff"], "variance": paper["var"],
+                     "mc_se": paper["se"], "estimate_re": paper["estimate_re"], "exact": exact},
+           "note": ("one sweep advances all P pairs; the series averages them, so variance_per_pair and "
+                    "effective_length_pair_sweeps are the single-chain figures the paper's tables print")}
     out["nonzero_updates_per_s"] = 2.0 * m.nnz * P / (out["ms_per_sweep"] / 1e3)
     # the paper's preferred Z2 noise (Sec. 1) on the same workload and rule
     out["z2_noise"] = run(pkg.MCINV_NOISE_RADEMACHER)
     return out
+
+
+def lattice_form(pkg, torch, gen, steps=20, check=2):
+    """Random-phase complex non-hermitian 16^4 lattice operator (c64 sweeps,
+    fp64 sums, 1024 pairs): sampling throughput with the sweep kernel's
+    roofline fraction, and the time to 1% on every diagonal entry."""
+    w = gen.WORKLOADS["lattice"]
+    m = gen.round_values(gen.lattice(w["L"], k=w["k"], seed=w["seed"]), np.complex64)
+    P, G, seed = w["pairs"], w["groups"], w["noise_seed"]
+    order = tuned_order(pkg, m, P, G, "c64")
+    s = pkg.Sampler(m, pairs=P, groups=G, dtype="c64", seed=seed, use_torch_stream=True, profile=True,
+                    xcd_order=order)
+    s.burn_in(10)
+    s.request(diag=True, trace=True)
+    s.sample(3)
+    s.reset_profile()
+    torch.cuda.synchronize()
+    e0, e1 = (torch.cuda.Event(enable_timing=True) for _ in range(2))
+    e0.record()
+    s.sample(steps)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    info = s.info()
+    s.close()
+    B = algorithmic_bytes_per_sweep(m.n, m.nnz, P, 8, 8)
+    sweep_ms = info["sweep_kernel_ms"] / steps
+    launches = info["sweep_kernel_launches"] / steps
+    ttt = time_to_1pct(pkg, torch, m, P, G, seed + 1, "c64", "fp64", "coupled", xcd_order=order, check=check)
+    return {"workload": f"random-phase lattice {w['L']}^4 (n={m.n}, nnz={m.nnz}), {P} chain pairs in {G} groups, "
+                        "complex64 sweeps, fp64 sums, diag + trace",
+            "nonzero_updates_per_s": 2.0 * m.nnz * P / (ms / 1e3), "ms_per_step": ms,
+            "roofline": {"bound": "hbm", "achieved": B / (sweep_ms / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": B / (sweep_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                         "algorithmic_bytes_per_sweep": B, "sweep_kernel_ms": sweep_ms,
+                         "launches_per_sweep": launches,
+                         "kernel": "k_sweep<Cx<float>, true, false> (all colour launches of one sweep)"},
+            "launch_order": ORDER_NAMES[order],
+            "time_to_1pct": ttt}
 
 
 def qtrace_form(pkg, torch, gen, w, steps=20):
@@ -352,9 +423,8 @@ def surrogate_form(pkg, torch, gen, n_train, n_val, rel_label=0.005, rel=0.01, s
     torch.cuda.synchronize()
     t_label = time.perf_counter() - t0
     Y, YSE = [], []
-    for j, x in enumerate(mats):
-        est, se = b.diag(j)
-        y, yse = sur.labels_from_estimates(x, est, se)
+    for j in range(len(mats)):
+        y, yse = b.labels(j)
         Y.append(y)
         YSE.append(yse)
     b.close()
@@ -437,6 +507,11 @@ def surrogate_form(pkg, torch, gen, n_train, n_val, rel_label=0.005, rel=0.01, s
                              "preparation); speedup_vs_plain compares it with the plain sampler's set-up + burn-in "
                              "+ sampling",
                      "speedup_vs_plain": (plain["seconds"] + plain["setup_seconds"]) / t_sur,
+                     "one_off_cost_seconds": t_label + t_feat + t_train,
+                     "break_even_matrices": (t_label + t_feat + t_train) /
+                     max(plain["seconds"] + plain["setup_seconds"] - t_sur, 1e-9),
+                     "break_even_note": ("held-out matrices of this size after which labelling, features and "
+                                         "training are paid back by the per-matrix saving"),
                      "accepted_rows": int(acc.sum()), "fallback_rows": int((~acc).sum()),
                      "fallback_sweeps": info["sweeps"],
                      "accepted_rms_rel_diff_vs_plain": float(np.sqrt(np.mean(r[acc] ** 2))) if acc.any() else None,
@@ -450,21 +525,95 @@ def surrogate_form(pkg, torch, gen, n_train, n_val, rel_label=0.005, rel=0.01, s
     }
 
 
-def cpu_baseline(m, seed, P, G, budget_s):
-    """The oracle (single-threaded C, fp64) on a bounded sample of the same
-    workload: a few chain pairs, as many sweeps as fit the time budget."""
+def host_description():
+    """CPU model, logical CPUs and the CPUs this process may run on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except AttributeError:
+        allowed = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "cpus_allowed": allowed}
+
+
+def cpu_baseline(m, seed, P, G, budget_s, check=None):
+    """The oracle (C, fp64, one thread per chain-pair subset) on a bounded
+    sample of the same workload: a few chain pairs, as many sweeps as fit a
+    time budget.  Three legs: the plain test build on one core, the same
+    source built for the host (FAST_FLAGS) on one core, and that build on
+    every allowed core (independent chain pairs per thread, no algorithmic
+    change; ctypes releases the interpreter lock during each oracle call).
+    With ``check`` (a GPU run's seed, sweep count, sampled pairs and their
+    final states) the one-core leg of the host build sweeps exactly those
+    pairs for exactly those sweeps, and the GPU states' error against it is
+    reported."""
+    import threading
+
     import oracle
-    pids = np.arange(8, dtype=np.int64) * (P // 8)
-    run = oracle.Run(m, seed=seed, pairs=P, groups=G, pair_ids=pids)
-    t0 = time.perf_counter()
-    sweeps = 0
-    while time.perf_counter() - t0 < budget_s:
-        run.burn_in(1)
-        sweeps += 1
-    t = time.perf_counter() - t0
-    ups = 2.0 * m.nnz * pids.size * sweeps / t
-    return dict(value=ups, unit="nonzero-updates/s", cores=1, kind="oracle",
-                sample=f"{pids.size} of {P} chain pairs, {sweeps} sweeps, n={m.n}, {t:.1f} s")
+    host = host_description()
+    threads = max(1, min(host["cpus_allowed"] or 1, 16))
+    per = 8   # chain pairs per oracle run (thread)
+
+    def pair_ids(k, t):
+        # k pairs spread over the P pairs, offset per thread
+        return (np.arange(k, dtype=np.int64) * (P // k) + t) % P
+
+    def leg(fast, nthreads, seconds):
+        runs = [oracle.Run(m, seed=seed, pairs=P, groups=G, pair_ids=pair_ids(per, t), fast=fast)
+                for t in range(nthreads)]
+        counts = [0] * nthreads
+
+        def work(t):
+            t0 = time.perf_counter()
+            while time.perf_counter() - t0 < seconds:
+                runs[t].burn_in(1)
+                counts[t] += 1
+        t0 = time.perf_counter()
+        ths = [threading.Thread(target=work, args=(t,)) for t in range(nthreads)]
+        for th in ths:
+            th.start()
+        for th in ths:
+            th.join()
+        t = time.perf_counter() - t0
+        ups = 2.0 * m.nnz * per * sum(counts) / t
+        return ups, sum(counts), t
+
+    u_plain, sw_plain, t_plain = leg(False, 1, budget_s / 3)
+    prec = None
+    if check is None:
+        u_fast, sw_fast, t_fast = leg(True, 1, budget_s / 3)
+    else:
+        pids = np.asarray(check["pairs"], dtype=np.int64)
+        run = oracle.Run(m, seed=check["seed"], pairs=P, groups=G, pair_ids=pids, fast=True)
+        t0 = time.perf_counter()
+        run.burn_in(check["sweeps"])
+        t_fast = time.perf_counter() - t0
+        sw_fast = check["sweeps"]
+        u_fast = 2.0 * m.nnz * pids.size * sw_fast / t_fast
+        prec = {"pairs": pids.tolist(), "sweeps": int(sw_fast)}
+        for name, gpu, ora in (("z", check["z"], run.z), ("w", check["w"], run.w)):
+            g = np.asarray(gpu).astype(np.complex128)
+            prec[f"max_rel_err_{name}"] = float(np.max(np.abs(g - ora)) / np.max(np.abs(ora)))
+            prec[f"max_abs_err_{name}"] = float(np.max(np.abs(g - ora)))
+        prec["note"] = ("chain states of the precision form (32-bit sweeps) after its burn-in and sample sweeps "
+                        "against the fp64 oracle on the same noise, on sampled pairs")
+    u_all, sw_all, t_all = leg(True, threads, budget_s / 3)
+    import oracle as _o
+    extra = {} if prec is None else {"precision_check": prec}
+    return dict(value=u_all, unit="nonzero-updates/s", cores=threads, kind="oracle", **extra,
+                value_1core=u_fast, value_1core_plain_build=u_plain, value_all_cores=u_all,
+                flags={"plain": "-O2", "fast": " ".join(_o.FAST_FLAGS)},
+                cpu_model=host["cpu_model"], nproc=host["nproc"], cpus_allowed=host["cpus_allowed"],
+                sample=(f"n={m.n}, {per} of {P} chain pairs per thread; plain build 1 thread {sw_plain} sweeps "
+                        f"in {t_plain:.1f} s, fast build 1 thread {sw_fast} sweeps in {t_fast:.1f} s, fast build "
+                        f"{threads} threads {sw_all} pair-block sweeps in {t_all:.1f} s"))
 
 
 def main():
@@ -473,15 +622,20 @@ def main():
     ap.add_argument("--workload", choices=["pedigree", "lattice", "dirac"], default="pedigree")
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--cpu-budget", type=float, default=18.0, help="seconds for the three CPU-baseline legs")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-ttt", action="store_true", help="skip the time-to-1%% phase")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-form comparison")
     ap.add_argument("--no-surrogate", action="store_true", help="skip the learned-surrogate form")
-    ap.add_argument("--no-dirac", action="store_true", help="skip the free Wilson-Dirac form")
-    ap.add_argument("--surrogate-train", type=int, default=192,
+    ap.add_argument("--no-dirac", action="store_true", help="skip the free Wilson-Dirac forms (18^4 and 20^4)")
+    ap.add_argument("--no-lattice", action="store_true", help="skip the random-phase lattice form")
+    ap.add_argument("--surrogate-train", type=int, default=2000,
                     help="training matrices of the surrogate form (the full workload has 2000)")
-    ap.add_argument("--surrogate-val", type=int, default=32)
+    ap.add_argument("--surrogate-val", type=int, default=100)
+    ap.add_argument("--stores", type=int, default=0,
+                    help="sweep state stores of the headline sampler: 0 automatic, 1 non-temporal, 2 temporal")
+    ap.add_argument("--pairs", type=int, default=0,
+                    help="chain pairs of the headline sampler (0: the workload's own)")
     ap.add_argument("--pass-tiles", type=int, default=0,
                     help="256-pair tiles per pass of the headline sampler (0: all tiles in every colour launch)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -500,6 +654,8 @@ def main():
 
     w = gen.WORKLOADS[args.workload]
     P, G, seed, dtype = w["pairs"], w["groups"], w["noise_seed"], w["dtype"]
+    if args.pairs > 0:
+        P, G = args.pairs, min(G, max(1, args.pairs // 4))
     if args.workload == "pedigree":
         m = gen.round_values(gen.pedigree(w["n"], seed=w["seed"]), np.float32)
         desc = f"pedigree n={m.n} nnz={m.nnz}, {P} chain pairs in {G} groups, fp32 sweeps, " \
@@ -518,7 +674,7 @@ def main():
     torch.cuda.set_device(0)
 
     s = pkg.Sampler(m, pairs=P, groups=G, dtype=dtype, seed=seed, use_torch_stream=True, profile=True,
-                    moments="bf16x3" if dtype == "f32" else "fp64", pass_tiles=args.pass_tiles)
+                    moments="bf16x3" if dtype == "f32" else "fp64", pass_tiles=args.pass_tiles, stores=args.stores)
     info0 = s.info()
     s.burn_in(w.get("burn_in", 60))
     order, ms_orders = s.tune_launch(2)   # setup: picks the fastest workgroup order
@@ -567,11 +723,13 @@ def main():
                    "step": "one sampling sweep (all colours, fused diag/trace moments, trace reduction"
                            + (", block moments)" if blk is not None else ")"),
                    "tiles_per_pass": args.pass_tiles if args.pass_tiles > 0 else "all",
+                   "stores": ["automatic", "non-temporal", "temporal"][args.stores],
                    "launch_order": {"chosen": ORDER_NAMES[order],
                                     "burn_in_ms_per_sweep": dict(zip(ORDER_NAMES, map(float, ms_orders)))}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": profiled_traffic(args.workload) if args.pass_tiles == 0 else None,
+                     "traffic": profiled_traffic(args.workload)
+                     if args.pass_tiles == 0 and args.stores == 0 and args.pairs == 0 else None,
                      "algorithmic_bytes_per_launch": B / launches,
                      "avg_launch_ms": sweep_ms / launches,
                      "kernel": f"k_sweep<{'float' if dtype == 'f32' else 'Cx<float>'}, true, false> "
@@ -595,9 +753,11 @@ def main():
         forms["precision"] = time_to_1pct(pkg, torch, m, P, G, seed + 1, dtype,
                                           "bf16x3" if dtype == "f32" else "fp64", w.get("burn_in", 60),
                                           xcd_order=order)
+        check_pairs = np.array([0, 1, 2, 3, P // 2, P // 2 + 1, P - 2, P - 1])
         forms["precision_coupled"] = time_to_1pct(pkg, torch, m, P, G, seed + 1, dtype,
                                                   "bf16x3" if dtype == "f32" else "fp64", "coupled",
-                                                  xcd_order=order)
+                                                  xcd_order=order, keep_pairs=check_pairs)
+        precision_state = forms["precision_coupled"].pop("_state")
         # the paper's preferred Z2 noise (Sec. 1): no transcendental functions, and a
         # diagonal-dominant C loses the variance its diagonal would add
         forms["precision_coupled_z2"] = time_to_1pct(pkg, torch, m, P, G, seed + 1, dtype,
@@ -624,10 +784,18 @@ def main():
         if args.workload == "pedigree":
             forms["qtrace"] = qtrace_form(pkg, torch, gen, w)
             log(f"Q trace: {forms['qtrace']['qtrace_ms_per_sample']:.3f} ms per sample")
+        if args.workload == "pedigree" and not args.no_lattice:
+            forms["lattice"] = lattice_form(pkg, torch, gen)
+            log(f"lattice 16^4: {forms['lattice']['nonzero_updates_per_s']:.3e} nonzero-updates/s, roofline "
+                f"{forms['lattice']['roofline']['frac']:.3f}, time to 1% "
+                f"{forms['lattice']['time_to_1pct']['seconds']:.3f} s")
         if args.workload == "pedigree" and not args.no_dirac:
-            forms["dirac"] = dirac_form(pkg, torch, gen)
-            log(f"dirac 18^4: {forms['dirac']['seconds']:.2f} s to 1e-5 ({forms['dirac']['sample_sweeps']} sweeps); "
-                f"Z2 noise {forms['dirac']['z2_noise']['seconds']:.2f} s ({forms['dirac']['z2_noise']['sample_sweeps']} sweeps)")
+            for N in (18, 20):
+                f = dirac_form(pkg, torch, gen, N)
+                forms[f"dirac{N}"] = f
+                log(f"dirac {N}^4: {f['seconds']:.2f} s to 1e-5 ({f['burn_in']} + {f['sample_sweeps']} sweeps), "
+                    f"z = {f['z_score']:.2f}; Z2 noise {f['z2_noise']['seconds']:.2f} s "
+                    f"({f['z2_noise']['sample_sweeps']} sweeps, z = {f['z2_noise']['z_score']:.2f})")
         if args.workload == "pedigree" and not args.no_surrogate:
             forms["surrogate"] = surrogate_form(pkg, torch, gen, args.surrogate_train, args.surrogate_val)
         result["forms"] = forms
@@ -654,14 +822,18 @@ def main():
 
     if not args.no_cpu:
         log("cpu baseline (oracle) ...")
-        cb = cpu_baseline(m, seed, P, G, args.cpu_budget)
+        cb = cpu_baseline(m, seed, P, G, args.cpu_budget,
+                          None if args.no_ttt else precision_state)
+        if "precision_check" in cb and "forms" in result:
+            result["forms"]["precision_coupled"]["vs_fp64_oracle_sampled_pairs"] = cb["precision_check"]
         ttt = result.get("time_to_1pct")
         if ttt is not None:
             # the same sweeps (burn-in + samples) the GPU needed, at the oracle's rate for all P pairs
             sweeps = ttt["burn_in"] + ttt["sample_sweeps"]
             cb["time_to_1pct_s_extrapolated"] = sweeps * 2.0 * m.nnz * P / cb["value"]
+            cb["time_to_1pct_s_extrapolated_1core"] = sweeps * 2.0 * m.nnz * P / cb["value_1core"]
             cb["time_to_1pct_note"] = (f"{sweeps} sweeps of {P} pairs (the GPU run's coupled burn-in and "
-                                       f"samples) at the measured oracle rate")
+                                       f"samples) at the measured oracle rates (all cores; one core)")
         result["cpu_baseline"] = cb
     print(json.dumps(result), flush=True)
 

@@ -118,6 +118,11 @@ typedef struct {
                               noise of pair pair_offset + p, so contexts that split
                               one run's pairs between them (one per GPU) reproduce
                               its chains; their moment sums add up to the run's */
+    int32_t  stores;       /* sweep state stores: 0 automatic (non-temporal when
+                              every colour launch covers all pair tiles, since the
+                              new rows are read again only by later launches;
+                              temporal in tile passes, whose later colours gather
+                              them from the cache), 1 non-temporal, 2 temporal   */
 } mcinv_config;
 
 typedef struct {
@@ -194,6 +199,17 @@ mcinv_status mcinv_sample_until_trace(mcinv_ctx* ctx, double rel_se, int64_t max
  * SE is NaN while fewer than two clusters hold samples. */
 mcinv_status mcinv_read_estimates(mcinv_ctx* ctx, uint32_t quantity, double* est,
                                   double* stderr_, int64_t capacity);
+
+/* The quantities the paper's Tables 2, 4 and 5 report for a trace (Sec. 2.3,
+ * Sec. 3): Geyer's initial positive sequence on the per-sweep series x_k =
+ * (1/P) sum_p t_p^(k) of MCINV_REQ_TRACE or MCINV_REQ_QTRACE.  stats[7]:
+ * mean (re, im; im 0 for a real C), gamma_0 (the series' variance, summed
+ * over re and im), sigma^2 = -gamma_0 + 2 sum_m Gamma_m, the effective length
+ * S gamma_0 / sigma^2, the standard error sqrt(sigma^2 / S), and S.  The
+ * series averages P chain pairs, so gamma_0 P and (effective length) P are
+ * the single-pair figures the tables print.  ESTATE: not requested or no
+ * samples. */
+mcinv_status mcinv_read_trace_stats(mcinv_ctx* ctx, uint32_t quantity, double* stats);
 
 /* Copy chain state z (which = 0) or w (which = 1) to host as [n][P] in the
  * sweep precision, original row order.  bytes must be >= n * P * elem size. */
@@ -361,7 +377,10 @@ mcinv_status mcinv_batch_burn_in_coupled(mcinv_batch* b, double tol, int64_t max
                                          double* max_diff);
 
 /* Sample in chunks until max over all matrices and rows of SE/|est| of the
- * diagonal is <= rel_se (or max_sweeps). */
+ * diagonal is <= rel_se (or max_sweeps).  With fewer than 16 chain groups the
+ * error clusters are time batches of ceil(expected_samples / 16) sweeps; both
+ * stopping rules return EINVAL when those are shorter than 16 sweeps (short
+ * batches of an autocorrelated chain understate the SE). */
 mcinv_status mcinv_batch_sample_until(mcinv_batch* b, double rel_se, int64_t max_sweeps, int64_t check_every,
                                       int64_t* sweeps_done, double* achieved);
 
@@ -386,6 +405,13 @@ mcinv_status mcinv_batch_matrix_samples(mcinv_batch* b, int64_t* samples, uint8_
  * mcinv_read_estimates (real). */
 mcinv_status mcinv_batch_read_estimates(mcinv_batch* b, int64_t m, uint32_t quantity, double* est,
                                         double* stderr_, int64_t capacity);
+
+/* Training labels of the learned surrogate for matrix m: the sampler's
+ * diagonal estimate (eq 1/C) scaled to the surrogate's target,
+ * y[i] = c_ii (C^-1)_ii, and its standard error y_se[i] = |c_ii| SE_i, both
+ * float64[n] in original row order (capacity >= n).  Errors as
+ * mcinv_batch_read_estimates(MCINV_REQ_DIAG). */
+mcinv_status mcinv_batch_read_labels(mcinv_batch* b, int64_t m, double* y, double* y_se, int64_t capacity);
 
 /* Chain state of matrix m, [n][P] fp32, original row order. */
 mcinv_status mcinv_batch_read_state(mcinv_batch* b, int64_t m, int32_t which, float* host, int64_t bytes);
@@ -507,13 +533,17 @@ typedef struct mcinv_gate mcinv_gate;
  * non-finite label. */
 mcinv_status mcinv_gate_fit(const mcinv_gate_config* cfg, int64_t N, const float* X, const double* pred,
                             const double* y, const double* y_se, mcinv_gate** out);
-/* fallback[i] = 1 when row i's bin needs the sampler (or a binning feature is NaN). */
+/* fallback[i] = 1 when row i's bin needs the sampler, or a binning feature is
+ * NaN or lies outside the [min, max] range of the validation rows (the outer
+ * bins are open-ended, so such a row has no validated error). */
 mcinv_status mcinv_gate_apply(const mcinv_gate* g, int64_t N, const float* X, uint8_t* fallback);
 /* edges_a, edges_b [bins-1]; bin_err, bin_count, bin_fallback [bins * bins],
  * bin (a, b) at a * bins + b.  bin_err is the value compared with tol (the
- * upper bound when ucb_z > 0; +inf for an empty bin).  Any may be NULL. */
+ * upper bound when ucb_z > 0; +inf for an empty bin).  range[4]: min and max
+ * of feature_a, then of feature_b, over the validation rows.  Any may be
+ * NULL. */
 mcinv_status mcinv_gate_read(const mcinv_gate* g, double* edges_a, double* edges_b, double* bin_err,
-                             int64_t* bin_count, uint8_t* bin_fallback);
+                             int64_t* bin_count, uint8_t* bin_fallback, double* range);
 void mcinv_gate_destroy(mcinv_gate* g);
 
 /* The surrogate's whole estimate of one matrix in one call: the features of
@@ -522,8 +552,9 @@ void mcinv_gate_destroy(mcinv_gate* g);
  * two binning features cross to the host.  est[n] = the surrogate's estimate
  * of (C^-1)_ii: the network's output (c_ii (C^-1)_ii, as mcinv_mlp_predict on
  * mcinv_features' output) divided by c_ii in fp64; fallback[n] = the gate's
- * decision per row (as mcinv_gate_apply on those features), 1 where est must
- * come from the sampler instead.  Both caller-allocated.  ESINGULAR / EINVAL
+ * decision per row (as mcinv_gate_apply on those features), or 1 where the
+ * network's output is not finite: 1 where est must come from the sampler
+ * instead.  Both caller-allocated.  ESINGULAR / EINVAL
  * as mcinv_features; the message is available from mcinv_mlp_last_error(m). */
 mcinv_status mcinv_mlp_estimate_matrix(mcinv_mlp* m, const mcinv_gate* g, int64_t n, int64_t nnz,
                                        const int64_t* row_ptr, const int32_t* col_idx, const double* values,

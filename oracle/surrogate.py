@@ -310,16 +310,23 @@ def gate_fit(X, pred, y, y_se, fa, fb, bins, min_rows, tol, ucb_z=0.0):
             q = chi2_lower_quantile(float(cnt[b]), ucb_z) if ucb_z > 0 else float(cnt[b])
             err[b] = np.sqrt(max(r2[b] - s2[b], 0.0) / q)
     fallback = (cnt < min_rows) | ~(err <= tol)
+    xa = X[:, fa].astype(np.float64)
+    xb = X[:, fb].astype(np.float64)
     return {"edges_a": ea, "edges_b": eb, "err": err, "count": cnt, "fallback": fallback,
-            "fa": fa, "fb": fb, "bins": bins}
+            "fa": fa, "fb": fb, "bins": bins,
+            "range_a": (xa.min(), xa.max()), "range_b": (xb.min(), xb.max())}
 
 
 def gate_apply(g, X):
-    """1 where a row's bin needs the sampler (or a binning feature is not a number)."""
+    """1 where a row's bin needs the sampler, where a binning feature is not a
+    number, or where it lies outside the range the validation rows covered
+    (the outer bins are open-ended: such a row has no validated error)."""
     X = np.asarray(X, dtype=np.float32)
     xa = X[:, g["fa"]].astype(np.float64)
     xb = X[:, g["fb"]].astype(np.float64)
     b = gate_bin(g["edges_a"], xa) * g["bins"] + gate_bin(g["edges_b"], xb)
     out = g["fallback"][b].astype(np.uint8)
-    out[np.isnan(xa) | np.isnan(xb)] = 1
+    (la, ha), (lb, hb) = g["range_a"], g["range_b"]
+    inside = (xa >= la) & (xa <= ha) & (xb >= lb) & (xb <= hb)   # False for NaN
+    out[~inside] = 1
     return out

@@ -16,6 +16,7 @@ from ._binding import (DTYPES, MCINV_MOMENTS_BF16X3, MCINV_MOMENTS_FP64, MCINV_N
 
 from ._binding import (mcinv_batch_autotune, mcinv_batch_burn_in, mcinv_batch_create, mcinv_batch_destroy,
                        mcinv_batch_get_info, mcinv_batch_load_csr, mcinv_batch_read_estimates,
+                       mcinv_batch_read_labels,
                        mcinv_batch_read_state, mcinv_batch_sample, mcinv_batch_sample_until,
                        mcinv_batch_set_block, mcinv_batch_set_requested)
 
@@ -44,7 +45,7 @@ class Sampler:
 
     def __init__(self, matrix, pairs, groups=1, dtype="f32", seed=0, noise=MCINV_NOISE_NORMAL,
                  moments="fp64", device=0, stream_id=0, use_torch_stream=False, profile=False, pass_tiles=0,
-                 hermitian=False, xcd_order=0, pair_offset=0):
+                 hermitian=False, xcd_order=0, pair_offset=0, stores=0):
         self.dtype = DTYPES[dtype] if isinstance(dtype, str) else int(dtype)
         self.is_complex = self.dtype in (DTYPES["c64"], DTYPES["c128"])
         mom = MCINV_MOMENTS_BF16X3 if moments == "bf16x3" else MCINV_MOMENTS_FP64
@@ -52,7 +53,7 @@ class Sampler:
         self.ctx = mcinv_create(device=device, sweep_dtype=self.dtype, moments=mom, noise=noise,
                                 n_pairs=pairs, n_groups=groups, stream_id=stream_id, seed=seed,
                                 stream=stream, profile=profile, pass_tiles=pass_tiles, hermitian=hermitian,
-                                xcd_order=xcd_order, pair_offset=pair_offset)
+                                xcd_order=xcd_order, pair_offset=pair_offset, stores=stores)
         self.n = matrix.n
         self.P = pairs
         self.nI = self.nJ = self.ne = 0
@@ -149,6 +150,12 @@ class Sampler:
         """(estimate, Geyer SE) of tr(C^-1)."""
         est, se = mcinv_read_estimates(self.ctx, MCINV_REQ_TRACE, 1, self.is_complex)
         return est[0], se[0]
+
+    def trace_stats(self, q=False):
+        """Geyer statistics of the trace series (tr C^-1, or tr(Q C^-1) with q):
+        mean, variance, sigma2, effective length, SE, samples."""
+        from ._binding import MCINV_REQ_QTRACE, MCINV_REQ_TRACE, mcinv_read_trace_stats
+        return mcinv_read_trace_stats(self.ctx, MCINV_REQ_QTRACE if q else MCINV_REQ_TRACE)
 
     def state(self, which):
         """Chain state z (which=0) or w (1), [n][pairs], original row order."""
@@ -260,6 +267,11 @@ class BatchSampler:
 
     def diag(self, m):
         return mcinv_batch_read_estimates(self.b, m, MCINV_REQ_DIAG, self.n[m])
+
+    def labels(self, m):
+        """Surrogate training labels of matrix m: c_ii (C^-1)_ii and their
+        standard errors (``mcinv_batch_read_labels``)."""
+        return mcinv_batch_read_labels(self.b, m, self.n[m])
 
     def block(self, m):
         est, se = mcinv_batch_read_estimates(self.b, m, MCINV_REQ_BLOCK, self.bdim * self.bdim)

@@ -58,6 +58,7 @@ class mcinv_config(ctypes.Structure):
         ("xcd_order", ctypes.c_int32),
         ("hermitian", ctypes.c_int32),
         ("pair_offset", ctypes.c_int64),
+        ("stores", ctypes.c_int32),
     ]
 
 
@@ -128,6 +129,7 @@ SIGNATURES = {
     "mcinv_sample": (_I32, [_P, _I64]),
     "mcinv_sample_until": (_I32, [_P, _D, _I64, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_D)]),
     "mcinv_sample_until_trace": (_I32, [_P, _D, _I64, _I64, ctypes.POINTER(_I64), ctypes.POINTER(_D)]),
+    "mcinv_read_trace_stats": (_I32, [_P, _U32, _P]),
     "mcinv_read_estimates": (_I32, [_P, _U32, _P, _P, _I64]),
     "mcinv_read_state": (_I32, [_P, _I32, _P, _I64]),
     "mcinv_write_state": (_I32, [_P, _I32, _P, _I64]),
@@ -155,6 +157,7 @@ SIGNATURES = {
     "mcinv_batch_matrix_samples": (_I32, [_P, _P, _P]),
     "mcinv_batch_read_estimates": (_I32, [_P, _I64, _U32, _P, _P, _I64]),
     "mcinv_batch_read_state": (_I32, [_P, _I64, _I32, _P, _I64]),
+    "mcinv_batch_read_labels": (_I32, [_P, _I64, _P, _P, _I64]),
     "mcinv_batch_autotune": (_I32, [_P, _I32, ctypes.POINTER(_I32), ctypes.POINTER(_I32), ctypes.POINTER(_I32),
                                     ctypes.POINTER(_D)]),
     "mcinv_batch_get_info": (_I32, [_P, ctypes.POINTER(mcinv_batch_info)]),
@@ -175,7 +178,7 @@ SIGNATURES = {
     "mcinv_gate_fit": (_I32, [ctypes.POINTER(mcinv_gate_config), _I64, _P, _P, _P, _P, ctypes.POINTER(_P)]),
     "mcinv_gate_apply": (_I32, [_P, _I64, _P, _P]),
     "mcinv_mlp_estimate_matrix": (_I32, [_P, _P, _I64, _I64, _P, _P, _P, _P, _P]),
-    "mcinv_gate_read": (_I32, [_P, _P, _P, _P, _P, _P]),
+    "mcinv_gate_read": (_I32, [_P, _P, _P, _P, _P, _P, _P]),
     "mcinv_gate_destroy": (None, [_P]),
     "mcinv_gate_last_error": (ctypes.c_char_p, []),
 }
@@ -215,10 +218,10 @@ def mcinv_last_error(ctx=None):
 
 def mcinv_create(device=0, sweep_dtype=MCINV_R32, moments=MCINV_MOMENTS_FP64, noise=MCINV_NOISE_NORMAL,
                  n_pairs=1, n_groups=1, stream_id=0, seed=0, stream=None, profile=False, pass_tiles=0,
-                 hermitian=False, xcd_order=0, pair_offset=0):
+                 hermitian=False, xcd_order=0, pair_offset=0, stores=0):
     cfg = mcinv_config(device, sweep_dtype, moments, noise, n_pairs, n_groups, stream_id,
                        seed & 0xFFFFFFFFFFFFFFFF, stream, 1 if profile else 0, int(pass_tiles), int(xcd_order),
-                       1 if hermitian else 0, int(pair_offset))
+                       1 if hermitian else 0, int(pair_offset), int(stores))
     h = ctypes.c_void_p()
     _check(None, lib().mcinv_create(ctypes.byref(cfg), ctypes.byref(h)))
     return h
@@ -291,6 +294,15 @@ def mcinv_read_estimates(ctx, quantity, count, is_complex):
     if is_complex:
         est = est.view(np.complex128)
     return est, se
+
+
+def mcinv_read_trace_stats(ctx, quantity):
+    """Geyer statistics of the trace series: dict of mean, variance (gamma_0),
+    sigma2, n_eff, se and samples."""
+    st = np.empty(7, dtype=np.float64)
+    _check(ctx, lib().mcinv_read_trace_stats(ctx, quantity, _ptr(st)))
+    return {"mean": complex(st[0], st[1]), "var": float(st[2]), "sigma2": float(st[3]), "n_eff": float(st[4]),
+            "se": float(st[5]), "samples": int(st[6])}
 
 
 def mcinv_read_state(ctx, which, n, P, sweep_dtype):
@@ -461,6 +473,13 @@ def mcinv_batch_read_estimates(b, m, quantity, count):
     se = np.empty(count, dtype=np.float64)
     _bcheck(b, lib().mcinv_batch_read_estimates(b, int(m), quantity, _ptr(est), _ptr(se), int(count)))
     return est, se
+
+
+def mcinv_batch_read_labels(b, m, count):
+    y = np.empty(count, dtype=np.float64)
+    y_se = np.empty(count, dtype=np.float64)
+    _bcheck(b, lib().mcinv_batch_read_labels(b, int(m), _ptr(y), _ptr(y_se), int(count)))
+    return y, y_se
 
 
 def mcinv_batch_read_state(b, m, which, n, P):
@@ -641,8 +660,10 @@ def mcinv_gate_read(g, bins):
     err = np.empty(bins * bins, dtype=np.float64)
     cnt = np.empty(bins * bins, dtype=np.int64)
     fb = np.empty(bins * bins, dtype=np.uint8)
-    _gcheck(lib().mcinv_gate_read(g, _ptr(ea), _ptr(eb), _ptr(err), _ptr(cnt), _ptr(fb)))
-    return {"edges_a": ea, "edges_b": eb, "err": err, "count": cnt, "fallback": fb.astype(bool)}
+    rng = np.empty(4, dtype=np.float64)
+    _gcheck(lib().mcinv_gate_read(g, _ptr(ea), _ptr(eb), _ptr(err), _ptr(cnt), _ptr(fb), _ptr(rng)))
+    return {"edges_a": ea, "edges_b": eb, "err": err, "count": cnt, "fallback": fb.astype(bool),
+            "range_a": (float(rng[0]), float(rng[1])), "range_b": (float(rng[2]), float(rng[3]))}
 
 
 def mcinv_gate_destroy(g):

@@ -65,6 +65,8 @@ struct mcinv_ctx {
     bool real_values = true;
     int64_t n = 0, nnz = 0, n_off = 0;
     int32_t ncolors = 0;
+    uint64_t value_hash = 0;     // FNV-1a of the prepared coefficients (checkpoint fingerprint)
+    uint64_t q_hash = 0;         // FNV-1a of Q's position-order pattern and values
     std::vector<int64_t> perm, pos, color_ptr, tpart_off;
     std::vector<int32_t> color;
     int64_t npart = 0;
@@ -127,6 +129,18 @@ struct mcinv_ctx {
 };
 
 namespace {
+
+// FNV-1a over raw bytes (checkpoint fingerprints).
+uint64_t fnv1a(uint64_t h, const void* p, size_t bytes)
+{
+    const unsigned char* b = (const unsigned char*)p;
+    for (size_t k = 0; k < bytes; ++k) {
+        h ^= b[k];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+constexpr uint64_t kFnvBasis = 1469598103934665603ull;
 
 mcinv_status fail(mcinv_ctx* c, mcinv_status code, const std::string& msg)
 {
@@ -356,6 +370,7 @@ mcinv_status run_sweeps(mcinv_ctx* c, int64_t nsw, bool sample, V* z, V* w, int6
         while (cs > 0 && (c->color_ptr[cs] - c->color_ptr[cs - 1]) * pt < kSmallLaunchRows) --cs;
         if (pt >= T) cs = c->ncolors;
         launches_per_sweep = (T + pt - 1) / pt * cs + (c->ncolors - cs);
+        a.nt_stores = c->cfg.stores == 1 || (c->cfg.stores == 0 && pt >= T);
         for (int64_t t0 = 0; t0 < T; t0 += pt) {
             for (int32_t col = 0; col < cs; ++col) {
                 a.row_begin = c->color_ptr[col];
@@ -579,6 +594,7 @@ try {
         return fail(nullptr, MCINV_EINVAL, "bf16x3 block moments need a real fp32 sweep");
     if (cfg->n_pairs < 1 || cfg->n_pairs > (int64_t)1 << 30) return fail(nullptr, MCINV_EINVAL, "n_pairs out of range");
     if (cfg->xcd_order < 0 || cfg->xcd_order > 2) return fail(nullptr, MCINV_EINVAL, "xcd_order must be 0, 1 or 2");
+    if (cfg->stores < 0 || cfg->stores > 2) return fail(nullptr, MCINV_EINVAL, "stores must be 0, 1 or 2");
     if (cfg->pair_offset < 0 || cfg->pair_offset % 4 != 0 || cfg->pair_offset + cfg->n_pairs > ((int64_t)1 << 34))
         return fail(nullptr, MCINV_EINVAL, "pair_offset must be a non-negative multiple of 4 (pairs below 2^34)");
     const int64_t P = cfg->n_pairs, G = cfg->n_groups;
@@ -699,6 +715,22 @@ try {
     c->color = h.color;
     c->color_ptr = h.color_ptr;
     c->real_values = real_values;
+    {
+        // the values a restored chain continues under: coefficients and scales
+        uint64_t vh = kFnvBasis;
+        for (const MergedEntry& e : h.ent) {
+            vh = fnv1a(vh, &e.col, sizeof(e.col));
+            vh = fnv1a(vh, &e.u, sizeof(e.u));
+            vh = fnv1a(vh, &e.v, sizeof(e.v));
+        }
+        for (size_t q = 0; q < h.a.size(); ++q) {
+            vh = fnv1a(vh, &h.a[q], sizeof(h.a[q]));
+            vh = fnv1a(vh, &h.b[q], sizeof(h.b[q]));
+            vh = fnv1a(vh, &h.diag[q], sizeof(h.diag[q]));
+        }
+        c->value_hash = vh;
+    }
+    c->q_hash = 0;
     c->tpart_off.assign(ncolors + 1, 0);
     for (int32_t k = 0; k < ncolors; ++k) {
         const int64_t rows = color_ptr[k + 1] - color_ptr[k];
@@ -983,6 +1015,31 @@ try {
     return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { fail(c, s_, m_); });
 }
 
+mcinv_status mcinv_read_trace_stats(mcinv_ctx* c, uint32_t quantity, double* stats)
+try {
+    MC_TRY(check_ready(c));
+    if (quantity != MCINV_REQ_TRACE && quantity != MCINV_REQ_QTRACE)
+        return fail(c, MCINV_EINVAL, "quantity must be MCINV_REQ_TRACE or MCINV_REQ_QTRACE");
+    if (!c->requested || !(c->flags & quantity)) return fail(c, MCINV_ESTATE, "quantity was not requested");
+    if (!stats) return fail(c, MCINV_EINVAL, "null output");
+    if (c->samples < 1) return fail(c, MCINV_ESTATE, "no samples yet");
+    const double* series = quantity == MCINV_REQ_TRACE ? c->d_series : c->d_qseries;
+    HIP_TRY(c, launch_geyer(series, c->samples, c->comps, 1.0 / (double)c->P, c->d_geyer, c->stream));
+    double g[6];
+    HIP_TRY(c, hipMemcpyAsync(g, c->d_geyer, sizeof(g), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    stats[0] = g[0];                 // mean, real part
+    stats[1] = c->comps == 2 ? g[1] : 0.0;
+    stats[2] = g[2];                 // gamma_0: variance of the per-sweep values
+    stats[3] = g[3];                 // sigma^2 of the initial positive sequence
+    stats[4] = g[4];                 // effective length S gamma_0 / sigma^2
+    stats[5] = g[5];                 // standard error sqrt(sigma^2 / S)
+    stats[6] = (double)c->samples;   // S
+    return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { fail(c, s_, m_); });
+}
+
 mcinv_status mcinv_read_state(mcinv_ctx* c, int32_t which, void* host, int64_t bytes)
 try {
     MC_TRY(check_ready(c));
@@ -1078,6 +1135,11 @@ try {
     default: MC_TRY(upload_q<Cx<double>>(c, rp, col, val)); break;
     }
     c->q_nnz = nnz;
+    uint64_t qh = kFnvBasis;
+    qh = fnv1a(qh, rp.data(), sizeof(int64_t) * rp.size());
+    qh = fnv1a(qh, col.data(), sizeof(int64_t) * col.size());
+    qh = fnv1a(qh, val.data(), sizeof(cd) * val.size());
+    c->q_hash = qh;
     return MCINV_OK;
 } catch (...) {
     return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { fail(c, s_, m_); });
@@ -1117,9 +1179,12 @@ struct CkptHeader {
 
 }  // extern "C"
 
-static uint64_t fingerprint(const mcinv_ctx* c)
+// The matrix a checkpoint belongs to: pattern sizes, colour order, the
+// prepared coefficients and scales (a same-pattern matrix with other values
+// must not continue the chains), and Q when the Q trace is accumulated.
+static uint64_t fingerprint(const mcinv_ctx* c, bool with_q)
 {
-    uint64_t h = 1469598103934665603ull;  // FNV-1a over the colour order and pattern sizes
+    uint64_t h = kFnvBasis;
     auto mix = [&](int64_t v) {
         for (int b = 0; b < 8; ++b) {
             h ^= (uint64_t)((v >> (8 * b)) & 0xff);
@@ -1131,6 +1196,11 @@ static uint64_t fingerprint(const mcinv_ctx* c)
     mix(c->n_off);
     for (int64_t v : c->perm) mix(v);
     for (int64_t v : c->color_ptr) mix(v);
+    mix((int64_t)c->value_hash);
+    if (with_q) {
+        mix(c->q_nnz);
+        mix((int64_t)c->q_hash);
+    }
     return h;
 }
 
@@ -1162,7 +1232,7 @@ static mcinv_status save_body(mcinv_ctx* c, FILE* f)
 {
     CkptHeader hd{};
     std::memcpy(hd.magic, "MCINVCK1", 8);
-    hd.version = 2;
+    hd.version = 3;
     hd.n = c->n;
     hd.nnz = c->nnz;
     hd.n_off = c->n_off;
@@ -1175,7 +1245,7 @@ static mcinv_status save_body(mcinv_ctx* c, FILE* f)
     hd.stream_id = c->cfg.stream_id;
     hd.seed = c->cfg.seed;
     hd.pair_offset = c->cfg.pair_offset;
-    hd.fingerprint = fingerprint(c);
+    hd.fingerprint = fingerprint(c, c->requested && (c->flags & MCINV_REQ_QTRACE));
     hd.flags = c->flags;
     hd.nI = c->nI;
     hd.nJ = c->nJ;
@@ -1213,9 +1283,10 @@ static mcinv_status save_body(mcinv_ctx* c, FILE* f)
 static mcinv_status restore_body(mcinv_ctx* c, FILE* f)
 {
     CkptHeader hd{};
-    if (!read_all(f, &hd, sizeof(hd)) || std::memcmp(hd.magic, "MCINVCK1", 8) != 0 || hd.version != 2)
+    if (!read_all(f, &hd, sizeof(hd)) || std::memcmp(hd.magic, "MCINVCK1", 8) != 0 || hd.version != 3)
         return fail(c, MCINV_EINVAL, "not an mcinv checkpoint");
-    if (hd.n != c->n || hd.nnz != c->nnz || hd.n_off != c->n_off || hd.fingerprint != fingerprint(c))
+    if (hd.n != c->n || hd.nnz != c->nnz || hd.n_off != c->n_off ||
+        hd.fingerprint != fingerprint(c, hd.requested && (hd.flags & MCINV_REQ_QTRACE)))
         return fail(c, MCINV_EINVAL, "checkpoint was taken on a different matrix");
     if (hd.P != c->P || hd.G != c->G || hd.dtype != c->cfg.sweep_dtype || hd.hermitian != (c->cfg.hermitian ? 1 : 0) ||
         hd.noise != c->cfg.noise || hd.stream_id != (int64_t)c->cfg.stream_id || hd.seed != c->cfg.seed ||

@@ -425,6 +425,24 @@ mcinv_status check_after(mcinv_batch* b)
     return MCINV_OK;
 }
 
+// With fewer than 16 chain groups the diagonal's error clusters include time
+// batches, which must be long against the chains' autocorrelation to be
+// independent (the single path accepts a stop only once its batches span 16
+// sweeps); here their length is fixed by expected_samples, so a stopping rule
+// on shorter batches is refused up front.
+constexpr int64_t kMinStopBatchLen = 16;
+
+mcinv_status check_stop_batches(mcinv_batch* b)
+{
+    if (b->nslots_diag > 1 && b->batch_len < kMinStopBatchLen)
+        return bfail(b, MCINV_EINVAL,
+                     "with fewer than 16 chain groups the error clusters are time batches of " +
+                         std::to_string(b->batch_len) + " sweeps; a stopping rule needs batches of at least " +
+                         std::to_string(kMinStopBatchLen) + " (set_requested with expected_samples >= " +
+                         std::to_string(kMinStopBatchLen * kBlockSlots) + ")");
+    return MCINV_OK;
+}
+
 std::vector<double> slot_lengths(int64_t samples, int64_t L, int32_t nslots)
 {
     std::vector<double> len(nslots, 0.0);
@@ -820,6 +838,7 @@ try {
     if (!b->requested || !(b->flags & MCINV_REQ_DIAG))
         return bfail(b, MCINV_ESTATE, "sample_until needs MCINV_REQ_DIAG requested");
     if (check_every < 1 || max_sweeps < 0) return bfail(b, MCINV_EINVAL, "bad sweep counts");
+    BTRY(check_stop_batches(b));
     int64_t done = 0;
     double maxrel = INFINITY;
     while (done < max_sweeps) {
@@ -845,6 +864,7 @@ try {
     if (!b->requested || !(b->flags & MCINV_REQ_DIAG))
         return bfail(b, MCINV_ESTATE, "sample_until_each needs MCINV_REQ_DIAG requested");
     if (check_every < 1 || max_sweeps < 0) return bfail(b, MCINV_EINVAL, "bad sweep counts");
+    BTRY(check_stop_batches(b));
     int64_t done = 0;
     int64_t left = std::count(b->active.begin(), b->active.end(), (uint8_t)1);
     // Once a matrix has stopped, the item lists change at every few checks:
@@ -924,6 +944,26 @@ try {
     if (stderr_)
         BHIP(b, hipMemcpyAsync(stderr_, b->d_se + offset, sizeof(double) * count, hipMemcpyDeviceToHost, b->stream));
     BHIP(b, hipStreamSynchronize(b->stream));
+    return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { bfail(b, s_, m_); });
+}
+
+mcinv_status mcinv_batch_read_labels(mcinv_batch* b, int64_t m, double* y, double* y_se, int64_t capacity)
+try {
+    BTRY(check_batch(b));
+    if (m < 0 || m >= b->M) return bfail(b, MCINV_EINVAL, "matrix index out of range");
+    const Prepared& pm = b->prep[m];
+    const int64_t n = pm.n;
+    if (capacity < n || !y || !y_se) return bfail(b, MCINV_EINVAL, "null output or capacity too small");
+    std::vector<double> est((size_t)n), se((size_t)n);
+    BTRY(mcinv_batch_read_estimates(b, m, MCINV_REQ_DIAG, est.data(), se.data(), n));
+    // estimates are in original row order; c_ii is kept per sweep position
+    for (int64_t i = 0; i < n; ++i) {
+        const double d = pm.diag[(size_t)pm.pos[i]].real();
+        y[i] = d * est[(size_t)i];
+        y_se[i] = std::fabs(d) * se[(size_t)i];
+    }
     return MCINV_OK;
 } catch (...) {
     return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { bfail(b, s_, m_); });

@@ -11,8 +11,10 @@
 // freedom for (sum of squared errors) / (true mean square), so dividing by
 // that distribution's lower quantile (Wilson-Hilferty approximation) bounds
 // the true error from above.  A bin needs the sampler when it holds fewer than
-// min_rows rows or its error exceeds tol.  Host code, float64, rows summed in
-// order.
+// min_rows rows or its error exceeds tol.  The outer bins are open-ended, so
+// a row whose binning features lie outside the range the validation rows
+// covered has no validated error at all: it goes to the sampler too.  Host
+// code, float64, rows summed in order.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -27,6 +29,7 @@
 struct mcinv_gate {
     mcinv_gate_config cfg{};
     std::vector<double> ea, eb, err;
+    double lo_a = 0.0, hi_a = 0.0, lo_b = 0.0, hi_b = 0.0;   // validated feature ranges
     std::vector<int64_t> count;
     std::vector<uint8_t> fallback;
 };
@@ -74,8 +77,8 @@ void gate_fallback_rows(const mcinv_gate* g, int64_t N, const float* X, int64_t 
     for (int64_t i = 0; i < N; ++i) {
         const double xa = X[i * ld + ca];
         const double xb = X[i * ld + cb];
-        if (std::isnan(xa) || std::isnan(xb)) {
-            fallback[i] = 1;
+        if (!(xa >= g->lo_a && xa <= g->hi_a && xb >= g->lo_b && xb <= g->hi_b)) {
+            fallback[i] = 1;   // NaN, or outside what the validation rows covered
             continue;
         }
         fallback[i] = g->fallback[(size_t)(bin_of(g->ea, xa) * B + bin_of(g->eb, xb))];
@@ -116,6 +119,15 @@ try {
     const int32_t B = cfg->bins;
     g->ea = quantile_edges(X, N, cfg->feature_a, B);
     g->eb = quantile_edges(X, N, cfg->feature_b, B);
+    g->lo_a = g->hi_a = X[cfg->feature_a];
+    g->lo_b = g->hi_b = X[cfg->feature_b];
+    for (int64_t i = 1; i < N; ++i) {
+        const double xa = X[i * MCINV_N_FEATURES + cfg->feature_a], xb = X[i * MCINV_N_FEATURES + cfg->feature_b];
+        g->lo_a = std::min(g->lo_a, xa);
+        g->hi_a = std::max(g->hi_a, xa);
+        g->lo_b = std::min(g->lo_b, xb);
+        g->hi_b = std::max(g->hi_b, xb);
+    }
     std::vector<double> r2((size_t)B * B, 0.0), s2((size_t)B * B, 0.0);
     g->count.assign((size_t)B * B, 0);
     for (int64_t i = 0; i < N; ++i) {
@@ -155,7 +167,7 @@ try {
 }
 
 mcinv_status mcinv_gate_read(const mcinv_gate* g, double* edges_a, double* edges_b, double* bin_err,
-                             int64_t* bin_count, uint8_t* bin_fallback)
+                             int64_t* bin_count, uint8_t* bin_fallback, double* range)
 try {
     if (!g) {
         set_err("mcinv_gate_read: null gate");
@@ -166,6 +178,12 @@ try {
     if (bin_err) std::memcpy(bin_err, g->err.data(), sizeof(double) * g->err.size());
     if (bin_count) std::memcpy(bin_count, g->count.data(), sizeof(int64_t) * g->count.size());
     if (bin_fallback) std::memcpy(bin_fallback, g->fallback.data(), g->fallback.size());
+    if (range) {
+        range[0] = g->lo_a;
+        range[1] = g->hi_a;
+        range[2] = g->lo_b;
+        range[3] = g->hi_b;
+    }
     return MCINV_OK;
 } catch (...) {
     return mcinv::exception_status([&](mcinv_status, const std::string& m_) { set_err(m_); });

@@ -924,7 +924,10 @@ try {
     }
     if (st != MCINV_OK) return merr(m, st, "estimate_matrix: " + why);
     mcinv::gate_fallback_rows(g, n, two.data(), 2, 0, 1, fallback);
-    for (int64_t i = 0; i < n; ++i) est[i] = (double)pred[i] / diag[i];   // the network predicts c_ii (C^-1)_ii
+    for (int64_t i = 0; i < n; ++i) {
+        est[i] = (double)pred[i] / diag[i];   // the network predicts c_ii (C^-1)_ii
+        if (!std::isfinite(pred[i])) fallback[i] = 1;
+    }
     return MCINV_OK;
 } catch (...) {
     return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { merr(m, s_, m_); });

@@ -34,6 +34,7 @@ struct SweepArgs {
     typename Real<V>::type thresh;
     int32_t xcd_order;       // 0: natural workgroup order; 1: contiguous tile ranges per XCD;
                              // 2: runs of 16 consecutive row blocks per XCD
+    int32_t nt_stores;       // nonzero: store new state rows non-temporally
 };
 
 // Launch over pair tiles [a.tile0, a.tile0 + ntiles).  herm: C is hermitian

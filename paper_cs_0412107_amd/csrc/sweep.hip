@@ -45,21 +45,29 @@ __device__ inline Quad<V> load_quad(const V* p)
     return *reinterpret_cast<const Quad<V>*>(p);
 }
 
-// The new state row is read again only by rows of later colours (other
-// launches): store it non-temporally so it does not displace the neighbour
-// slices the current launch is gathering from L2 (measured 3-5% faster).
+// The new state row is read again only by rows of later colours.  When every
+// launch covers all pair tiles those reads come in later launches, so the row
+// is stored non-temporally and does not displace the neighbour slices the
+// current launch is gathering (measured 3-5% faster); in tile passes the later
+// colours of the same pass gather it soon after, and a temporal store keeps it
+// in the caches for them.
 template <typename V>
-__device__ inline void store_quad(V* p, const Quad<V>& q)
+__device__ inline void store_quad(V* p, const Quad<V>& q, bool nt)
 {
     static_assert(sizeof(Quad<V>) % 16 == 0, "quads are whole 16-byte vectors");
     const uint4* src = reinterpret_cast<const uint4*>(&q);
     uint4* dst = reinterpret_cast<uint4*>(p);
+    if (nt) {
 #pragma unroll
-    for (int k = 0; k < (int)(sizeof(Quad<V>) / 16); ++k) {
-        __builtin_nontemporal_store(src[k].x, &dst[k].x);
-        __builtin_nontemporal_store(src[k].y, &dst[k].y);
-        __builtin_nontemporal_store(src[k].z, &dst[k].z);
-        __builtin_nontemporal_store(src[k].w, &dst[k].w);
+        for (int k = 0; k < (int)(sizeof(Quad<V>) / 16); ++k) {
+            __builtin_nontemporal_store(src[k].x, &dst[k].x);
+            __builtin_nontemporal_store(src[k].y, &dst[k].y);
+            __builtin_nontemporal_store(src[k].z, &dst[k].z);
+            __builtin_nontemporal_store(src[k].w, &dst[k].w);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < (int)(sizeof(Quad<V>) / 16); ++k) dst[k] = src[k];
     }
 }
 
@@ -167,8 +175,8 @@ __global__ __launch_bounds__(256) void k_sweep(const SweepArgs<V> a)
             wn.v[j] = HERM ? zn.v[j] : noisy_update(s.b, phi[j], aw[j]);
         }
         if (active) {
-            store_quad(a.z + q * a.ld + p0, zn);
-            if constexpr (!HERM) store_quad(a.w + q * a.ld + p0, wn);
+            store_quad(a.z + q * a.ld + p0, zn, a.nt_stores != 0);
+            if constexpr (!HERM) store_quad(a.w + q * a.ld + p0, wn, a.nt_stores != 0);
         }
 
         // Divergence guard (Sec. 2.2): a runaway or non-finite state.

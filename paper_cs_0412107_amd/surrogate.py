@@ -3,7 +3,8 @@
 Writing C = D (I + M), the series C^-1 = sum_k (-M)^k D^-1 gives
 y_i = c_ii (C^-1)_ii = 1 + (M^2)_ii - (M^3)_ii + ...; a small network predicts
 y_i from 32 local features of row i (``mcinv_features``), trained on the
-sampler's estimates (eq 1/C) weighted by their standard errors.  A gate fitted
+sampler's estimates (eq 1/C, scaled to c_ii (C^-1)_ii by
+``mcinv_batch_read_labels``) weighted by their standard errors.  A gate fitted
 on validation matrices sends the rows whose validated error exceeds the
 tolerance back to the sampler, whose stop check then covers only those rows.
 
@@ -17,24 +18,9 @@ import numpy as np
 from . import _binding as B
 
 
-def _diag(matrix):
-    rp, col, val = matrix.row_ptr, matrix.col, np.asarray(matrix.val)
-    d = np.zeros(matrix.n)
-    rows = np.repeat(np.arange(matrix.n), np.diff(rp))
-    on = col == rows
-    d[rows[on]] = val[on].real
-    return d
-
-
 def features(matrix, device=0):
     """[n][32] float32 features of a real matrix (CSR with row_ptr, col, val)."""
     return B.mcinv_features(device, matrix.n, matrix.nnz, matrix.row_ptr, matrix.col, matrix.val)
-
-
-def labels_from_estimates(matrix, est, se):
-    """y = c_ii (C^-1)_ii and its standard error from sampler estimates."""
-    d = _diag(matrix)
-    return d * np.asarray(est), np.abs(d) * np.asarray(se)
 
 
 def init_params(seed):
@@ -136,7 +122,8 @@ def estimate_diag(matrix, net, gate, sampler_factory, rel_se=0.01, max_sweeps=20
     ``burn_in`` is a sweep count or "coupled" (until the coupled paths agree
     to 5e-5).
     Returns (estimate, source) with source 0 = network, 1 = sampler, and a
-    dict of counts and sweeps."""
+    dict of counts and sweeps (with the sampler's standard errors of every row
+    under "se" when any row fell back)."""
     est, fb = net.estimate_matrix(matrix, gate)
     fb = fb.astype(bool)
     info = {"rows": int(matrix.n), "fallback_rows": int(fb.sum()), "sweeps": 0}
@@ -149,7 +136,7 @@ def estimate_diag(matrix, net, gate, sampler_factory, rel_se=0.01, max_sweeps=20
             s.request(diag=True, trace=False)
             s.set_stop_rows(np.nonzero(fb)[0])
             done, achieved = s.sample_until(rel_se, max_sweeps, check_every)
-            sd, _ = s.diag()
+            sd, sse = s.diag()
         est[fb] = np.asarray(sd).real[fb]
-        info.update(sweeps=int(done), achieved=float(achieved))
+        info.update(sweeps=int(done), achieved=float(achieved), se=np.asarray(sse))
     return est, fb.astype(np.uint8), info

@@ -246,3 +246,34 @@ def test_batched_full_size_sampled_pairs():
             ora.burn_in(k)
             assert rel_err(b.state(m, 0)[:, pids], ora.z) <= 1e-5
             assert rel_err(b.state(m, 1)[:, pids], ora.w) <= 1e-5
+
+
+def test_stop_rule_needs_long_time_batches(mats):
+    """With fewer than 16 chain groups the diagonal's error clusters are time
+    batches of ceil(expected_samples / 16) sweeps: both stopping rules refuse
+    batches shorter than 16 sweeps (their SE would run small), and with long
+    enough batches the stopped estimates lie within their errors of the exact
+    inverse."""
+    print_case(test="batch_stop_batches")
+    sub = [mats[0], mats[4], mats[9]]
+    P, G, seed = 64, 4, 31
+    with mc.BatchSampler(sub, pairs=P, groups=G, seed=seed) as b:
+        b.burn_in(40)
+        b.request(diag=True, expected_samples=100)   # batches of 7 sweeps
+        for call in (b.sample_until, b.sample_until_each):
+            with pytest.raises(mc.McinvError) as ei:
+                call(0.05, 400, 10)
+            assert ei.value.code == mc.MCINV_EINVAL
+        b.request(diag=True, expected_samples=640)   # batches of 40 sweeps
+        done, ach = b.sample_until_each(0.02, 4000, 20)
+        samples, active = b.matrix_samples()
+        assert not active.any() and ach <= 0.02
+        assert samples.min() >= 16 * 2   # at least two time batches per matrix
+        z = []
+        for m, mat in enumerate(sub):
+            exact = np.diag(np.linalg.inv(gen.to_dense(mat)))
+            d, se = b.diag(m)
+            z.append((d - exact) / se)
+        z = np.concatenate(z)
+        assert np.max(np.abs(z)) < 4.5
+        assert 0.5 <= np.mean(z ** 2) <= 1.6

@@ -158,3 +158,44 @@ def test_restore_rejects_corrupt_counts(tmp_path):
         got = b.diag()
     for x, y in zip(got, ref):
         assert np.array_equal(np.asarray(x), np.asarray(y))
+
+
+def test_restore_rejects_same_pattern_other_values(tmp_path):
+    """The fingerprint covers the matrix values, not only its pattern: a
+    checkpoint does not restore onto a matrix with the same pattern and other
+    values (its chains and sums belong to the first matrix), nor, when the Q
+    trace is accumulated, onto another Q with the same pattern."""
+    import scipy.sparse as sp
+    print_case(test="checkpoint_values")
+    m = oracle_matrix(gen.pedigree(700, seed=96), "f32")
+    other = gen.CSR(n=m.n, row_ptr=m.row_ptr.copy(), col=m.col.copy(), val=m.val.copy())
+    k = int(np.nonzero(other.col != np.repeat(np.arange(m.n), np.diff(m.row_ptr)))[0][0])
+    other.val[k] *= 0.5                        # one off-diagonal value changed
+    Q = sp.random(m.n, m.n, density=3.0 / m.n, random_state=np.random.default_rng(5), format="csr") + \
+        sp.identity(m.n)
+    Q2 = Q.copy()
+    Q2.data[0] += 1.0
+    path = str(tmp_path / "ck.bin")
+    pathq = str(tmp_path / "ckq.bin")
+    with mc.Sampler(m, pairs=32, dtype="f32", seed=4) as a:
+        a.burn_in(2)
+        a.save(path)
+        a.set_trace_matrix(Q)
+        a.request(diag=True, trace=True, qtrace=True)
+        a.sample(3)
+        a.save(pathq)
+    with mc.Sampler(other, pairs=32, dtype="f32", seed=4) as b:
+        with pytest.raises(mc.McinvError) as ei:
+            b.restore(path)
+        assert ei.value.code == mc.MCINV_EINVAL
+        assert b.info()["sweeps_done"] == 0
+    with mc.Sampler(m, pairs=32, dtype="f32", seed=4) as b:
+        b.restore(path)                         # the same matrix restores
+        assert b.info()["sweeps_done"] == 2
+        b.set_trace_matrix(Q2)
+        with pytest.raises(mc.McinvError) as ei:
+            b.restore(pathq)
+        assert ei.value.code == mc.MCINV_EINVAL
+        b.set_trace_matrix(Q)
+        b.restore(pathq)
+        assert b.info()["samples_done"] == 3

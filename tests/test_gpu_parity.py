@@ -65,8 +65,8 @@ def test_coloring_matches_oracle(name, maker):
 
 # ------------------------------------------------------------ chain state --
 STATE_CASES = [
-    ("random200", "f64", 6, [1, 2, 10, 100]),
-    ("random200", "f32", 6, [1, 2, 10, 100]),
+    ("random200", "f64", 6, [1, 2, 10, 100, 1000]),
+    ("random200", "f32", 6, [1, 2, 10, 100, 1000]),
     ("pedigree2000", "f32", 300, [1, 5, 30]),
     ("pedigree2000", "f64", 260, [1, 5, 30]),
     ("lattice4", "c64", 64, [1, 3, 20]),

@@ -232,6 +232,27 @@ def test_training_beats_neumann_baselines_and_gate_falls_back():
         if acc.any():
             assert np.sqrt(np.mean(rel[acc] ** 2)) <= 0.02
         gate.close()
+        # a gate that must send rows back: bins holding fewer validation rows than
+        # the median bin fall back, and so do held-out rows beyond the validated
+        # range; the sampler then covers exactly those rows, to its tolerance
+        cnt = sur.Gate(Xv, pv, yv, np.zeros_like(yv), feature_a=1, feature_b=5, bins=4, min_rows=1,
+                       tol=1.0).table()["count"]
+        forced = sur.Gate(Xv, pv, yv, np.zeros_like(yv), feature_a=1, feature_b=5, bins=4,
+                          min_rows=int(np.median(cnt[cnt > 0])) + 1, tol=1.0)
+        fb_ref = forced.fallback(F[9])
+        assert fb_ref.any() and not fb_ref.all()
+        est, src, info = sur.estimate_diag(
+            m, net, forced, lambda mm: mc.Sampler(mm, pairs=256, groups=32, dtype="f32", seed=9),
+            rel_se=0.02, max_sweeps=4000, check_every=20, burn_in=100)
+        src = src.astype(bool)
+        assert np.array_equal(src, fb_ref)
+        assert info["fallback_rows"] == int(fb_ref.sum()) and info["sweeps"] > 0
+        assert info["achieved"] <= 0.02
+        z = (est[src] - exact[src]) / info["se"][src]
+        assert np.max(np.abs(z)) <= 5.0, np.max(np.abs(z))
+        # accepted rows keep the network's value, the rest the sampler's
+        np.testing.assert_array_equal(est[~src], e_one[~src])
+        forced.close()
 
 
 def test_features_full_size_sampled_rows():

@@ -241,6 +241,12 @@ def test_chi2_lower_quantile_matches_scipy_and_covers():
     assert g["err"][0] < 0.01 < g["err"][1] and g["err"][3] < 0.01 < g["err"][2]
     assert g["fallback"].tolist() == [False, True, True, False]
     assert not g0["fallback"].any()
+    # rows beyond the validated range of either binning feature fall back even
+    # though their (open-ended) outer bin is trusted; the range's own ends do not
+    Xq = np.zeros((6, 32), dtype=np.float32)
+    Xq[:, 0] = [0, 209, -1, 210, 50, 50]
+    Xq[:, 1] = [0, 209, 0, 0, -0.5, 1000]
+    assert S.gate_apply(g0, Xq).tolist() == [0, 0, 1, 1, 1, 1]
 
 
 def test_gate_library_matches_oracle():
@@ -267,9 +273,13 @@ def test_gate_library_matches_oracle():
             assert np.array_equal(got["count"], ref["count"])
             np.testing.assert_allclose(got["err"], ref["err"], rtol=1e-12)
             assert np.array_equal(got["fallback"], ref["fallback"])
+            assert got["range_a"] == ref["range_a"] and got["range_b"] == ref["range_b"]
             Xq = rng.standard_normal((777, 32)).astype(np.float32) * 1.5
             Xq[::50, 1] = np.nan
-            assert np.array_equal(mc.mcinv_gate_apply(h, Xq), S.gate_apply(ref, Xq))
+            Xq[3::50, 5] = 1e6   # beyond the validated range
+            out = mc.mcinv_gate_apply(h, Xq)
+            assert np.array_equal(out, S.gate_apply(ref, Xq))
+            assert out[3::50].all() and out[::50].all()
         finally:
             mc.mcinv_gate_destroy(h)
     with pytest.raises(mc.McinvError):
