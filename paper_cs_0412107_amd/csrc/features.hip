@@ -8,7 +8,6 @@
 // output.  fp64 arithmetic (pass 1: eight lanes per row; pass 2: one thread
 // per row), fp32 output.
 #include <hip/hip_runtime.h>
-#include <rocprim/device/device_radix_sort.hpp>
 
 #include <algorithm>
 #include <cmath>
@@ -48,22 +47,90 @@ __device__ inline double lookup_cji(const FEnt* e, int32_t cnt, int32_t k)
     return 0.0;
 }
 
-// The merged neighbour lists are built on the device.  The transpose of C
-// comes from one radix sort of the keys j * n + i (entry c_ij), which orders
-// the entries by column, then by row, and carries c_ij along: column i's
-// entries are then the keys in [i * n, (i + 1) * n), rows ascending.
+// The merged neighbour lists are built on the device.  The transpose of C is
+// a counting sort by column: column counts, their prefix sums (column
+// pointers), a scatter of every entry into its column's segment (slots taken
+// with atomics, so in no fixed order), then each entry's rank among its
+// segment's rows puts the segment in ascending row order -- the same result
+// whatever order the scatter took.
 
-// key of every entry and the entry count of every column (thread per row)
-__global__ __launch_bounds__(256) void k_ft_keys(int64_t n, const int64_t* rp, const int32_t* col, uint64_t* key,
-                                                 int32_t* ccount)
+// Validation of the CSR arrays (thread per row) and the diagonal c_ii.
+// flag[0]: lowest row with a pattern error (-1: row_ptr does not start at 0 or
+// end at nnz); flag[1]: lowest row without a nonzero diagonal; both start at
+// INT64_MAX.  Row ranges outside [0, nnz] are flagged and not read.
+__global__ __launch_bounds__(256) void k_ft_validate(int64_t n, int64_t nnz, const int64_t* rp, const int32_t* col,
+                                                     const double* val, double* d, unsigned long long* flag)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0 && (rp[0] != 0 || rp[n] != nnz)) atomicMin(flag, 0ull);
+    if (i >= n) return;
+    const int64_t b = rp[i], e = rp[i + 1];
+    bool bad = b < 0 || e < b || e > nnz;
+    bool found = false;
+    double di = 0.0;
+    for (int64_t k = b; k < e && !bad; ++k) {
+        const int32_t c = col[k];
+        if (c < 0 || c >= n || (k > b && c <= col[k - 1]))
+            bad = true;
+        else if (c == i) {
+            di = val[k];
+            found = true;
+        }
+    }
+    if (bad) {
+        atomicMin(flag, (unsigned long long)(i + 1));
+        return;
+    }
+    d[i] = di;
+    if (!found || di == 0.0) atomicMin(flag + 1, (unsigned long long)i);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_ft_fill(int64_t count, T* p, T v)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < count) p[k] = v;
+}
+
+// entry count of every column (thread per row)
+__global__ __launch_bounds__(256) void k_ft_colcount(int64_t n, const int64_t* rp, const int32_t* col,
+                                                     int32_t* ccount)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) atomicAdd(ccount + col[e], 1);
+}
+
+// every entry c_ij into column j's segment (cursor: zeroed counts)
+__global__ __launch_bounds__(256) void k_ft_scatter(int64_t n, const int64_t* rp, const int32_t* col,
+                                                    const double* val, const int64_t* tp, int32_t* cursor,
+                                                    int32_t* trow_u, int32_t* tcol_u, double* tval_u)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
         const int32_t j = col[e];
-        key[e] = (uint64_t)j * (uint64_t)n + (uint64_t)i;
-        atomicAdd(ccount + j, 1);
+        const int64_t at = tp[j] + atomicAdd(cursor + j, 1);
+        trow_u[at] = (int32_t)i;
+        tcol_u[at] = j;
+        tval_u[at] = val[e];
     }
+}
+
+// thread per transposed entry: its rank among the rows of its column (rows
+// are distinct within a column) is its place in ascending order
+__global__ __launch_bounds__(256) void k_ft_rank(int64_t nnz, const int64_t* tp, const int32_t* trow_u,
+                                                 const int32_t* tcol_u, const double* tval_u, int32_t* trow,
+                                                 double* tval)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nnz) return;
+    const int32_t j = tcol_u[t], r = trow_u[t];
+    const int64_t b = tp[j], e = tp[j + 1];
+    int64_t rank = 0;
+    for (int64_t u = b; u < e; ++u) rank += trow_u[u] < r ? 1 : 0;
+    trow[b + rank] = r;
+    tval[b + rank] = tval_u[t];
 }
 
 // out[k] = in[0] + ... + in[k-1] for k = 0..n (one workgroup: a chunk per
@@ -131,33 +198,34 @@ __global__ __launch_bounds__(1024) void k_ft_tile_scan(int64_t n, const int32_t*
 
 // out[0..n] = exclusive prefix sums of in[0..n); tsum / toff hold
 // ceil(n / 1024) and ceil(n / 1024) + 1 values
-inline hipError_t scan_counts(int64_t n, const int32_t* in, int64_t* out, int64_t* tsum, int64_t* toff)
+inline hipError_t scan_counts(int64_t n, const int32_t* in, int64_t* out, int64_t* tsum, int64_t* toff,
+                              hipStream_t st)
 {
     const int64_t nt = (n + 1023) / 1024;
-    k_ft_tile_sums<<<(unsigned)nt, 1024>>>(n, in, tsum);
-    k_ft_scan<int64_t><<<1, 1024>>>(nt, tsum, toff);
-    k_ft_tile_scan<<<(unsigned)nt, 1024>>>(n, in, toff, out);
+    k_ft_tile_sums<<<(unsigned)nt, 1024, 0, st>>>(n, in, tsum);
+    k_ft_scan<int64_t><<<1, 1024, 0, st>>>(nt, tsum, toff);
+    k_ft_tile_scan<<<(unsigned)nt, 1024, 0, st>>>(n, in, toff, out);
     return hipGetLastError();
 }
 
-// Row i's merged list: the union of row i (col, val) and column i (the sorted
-// keys tkey[tp[i] .. tp[i+1]) with values tval), ascending, without i itself.
+// Row i's merged list: the union of row i (col, val) and column i (rows
+// trow[tp[i] .. tp[i+1]), ascending, with values tval), ascending, without i
+// itself.
 // Counting pass (out == nullptr) writes cnt[i]; the writing pass fills
 // out + beg[i].
 __global__ __launch_bounds__(256) void k_ft_merge(int64_t n, const int64_t* rp, const int32_t* col,
-                                                  const double* val, const int64_t* tp, const uint64_t* tkey,
+                                                  const double* val, const int64_t* tp, const int32_t* trow,
                                                   const double* tval, const int64_t* beg, FEnt* out, int32_t* cnt)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    const uint64_t base = (uint64_t)i * (uint64_t)n;
     int64_t e = rp[i], t = tp[i];
     const int64_t e_end = rp[i + 1], t_end = tp[i + 1];
     FEnt* o = out ? out + beg[i] : nullptr;
     int32_t k = 0;
     while (e < e_end || t < t_end) {
         const int64_t je = e < e_end ? (int64_t)col[e] : INT64_MAX;
-        const int64_t jt = t < t_end ? (int64_t)(tkey[t] - base) : INT64_MAX;
+        const int64_t jt = t < t_end ? (int64_t)trow[t] : INT64_MAX;
         const int64_t j = je < jt ? je : jt;
         const bool has_e = je == j, has_t = jt == j;
         if (j != i) {
@@ -311,6 +379,138 @@ __global__ __launch_bounds__(256) void k_ft_pick(int64_t n, const float* F, int3
     out[2 * i + 1] = F[i * kNF + b];
 }
 
+// Device buffers of one features computation, all carved (256-byte aligned)
+// from one region: its size for a matrix of n rows and nnz entries, and the
+// carving.  The merged lists take the bound 2 nnz (every entry in both its
+// row's and its column's list).
+struct FeatBuffers {
+    int32_t* ccount;                 // n: column counts, then scatter cursors
+    int64_t* tp;                     // n + 1: column pointers
+    int32_t *trow_u, *tcol_u;        // nnz: scattered entries
+    double* tval_u;                  // nnz
+    int32_t* trow;                   // nnz: rows ascending within each column
+    double* tval;                    // nnz
+    int32_t* cnt;                    // n: merged list lengths
+    int64_t* beg;                    // n + 1: merged list offsets
+    double* d;                       // n: c_ii
+    double* F;                       // n x 32: pass-1 terms
+    int64_t *tsum, *toff;            // scan tiles
+    FEnt* ent;                       // 2 nnz: merged lists
+    unsigned long long* flag;        // 2: validation
+};
+
+template <class F>
+void feat_parts(int64_t n, int64_t nnz, F&& part)
+{
+    const size_t N = (size_t)n, Z = (size_t)nnz, T = (size_t)((n + 1023) / 1024);
+    part(0, sizeof(int32_t) * N);
+    part(1, sizeof(int64_t) * (N + 1));
+    part(2, sizeof(int32_t) * Z);
+    part(3, sizeof(int32_t) * Z);
+    part(4, sizeof(double) * Z);
+    part(5, sizeof(int32_t) * Z);
+    part(6, sizeof(double) * Z);
+    part(7, sizeof(int32_t) * N);
+    part(8, sizeof(int64_t) * (N + 1));
+    part(9, sizeof(double) * N);
+    part(10, sizeof(double) * N * kNF);
+    part(11, sizeof(int64_t) * std::max<size_t>(T, 1));
+    part(12, sizeof(int64_t) * (T + 1));
+    part(13, sizeof(FEnt) * std::max<size_t>(2 * Z, 1));
+    part(14, sizeof(unsigned long long) * 2);
+}
+
+inline size_t pad256(size_t b) { return (b + 255) / 256 * 256; }
+
+size_t feat_bytes(int64_t n, int64_t nnz)
+{
+    size_t total = 0;
+    feat_parts(n, nnz, [&](int, size_t b) { total += pad256(b); });
+    return total;
+}
+
+FeatBuffers feat_carve(char* base, int64_t n, int64_t nnz)
+{
+    void* at[15];
+    size_t off = 0;
+    feat_parts(n, nnz, [&](int k, size_t b) {
+        at[k] = base + off;
+        off += pad256(b);
+    });
+    FeatBuffers f;
+    f.ccount = (int32_t*)at[0];
+    f.tp = (int64_t*)at[1];
+    f.trow_u = (int32_t*)at[2];
+    f.tcol_u = (int32_t*)at[3];
+    f.tval_u = (double*)at[4];
+    f.trow = (int32_t*)at[5];
+    f.tval = (double*)at[6];
+    f.cnt = (int32_t*)at[7];
+    f.beg = (int64_t*)at[8];
+    f.d = (double*)at[9];
+    f.F = (double*)at[10];
+    f.tsum = (int64_t*)at[11];
+    f.toff = (int64_t*)at[12];
+    f.ent = (FEnt*)at[13];
+    f.flag = (unsigned long long*)at[14];
+    return f;
+}
+
+inline unsigned grid_for(int64_t count) { return (unsigned)((std::max<int64_t>(count, 1) + 255) / 256); }
+
+// Validation on the device (the diagonal into fb.d); the flags are read back
+// with a synchronisation: flag[0] / flag[1] as k_ft_validate writes them.
+hipError_t features_validate(int64_t n, int64_t nnz, const int64_t* rp, const int32_t* col, const double* val,
+                             const FeatBuffers& fb, unsigned long long flags[2], hipStream_t st)
+{
+    k_ft_fill<unsigned long long><<<1, 256, 0, st>>>(2, fb.flag, ~0ull);
+    k_ft_validate<<<grid_for(n), 256, 0, st>>>(n, nnz, rp, col, val, fb.d, fb.flag);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(flags, fb.flag, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    return e;
+}
+
+// Status and message of the validation flags.
+mcinv_status validation_status(const unsigned long long flags[2], const char** why)
+{
+    if (flags[0] != ~0ull) {
+        *why = flags[0] == 0 ? "row_ptr[0] must be 0 and row_ptr[n] nnz"
+                             : "a row has a bad entry range, a column out of range or columns not strictly "
+                               "increasing";
+        return MCINV_EINVAL;
+    }
+    if (flags[1] != ~0ull) {
+        *why = "a row has no nonzero diagonal entry";
+        return MCINV_ESINGULAR;
+    }
+    return MCINV_OK;
+}
+
+// The features of a validated matrix (device CSR arrays; fb.d holds c_ii)
+// into out [n][32] float, all launches on st.
+hipError_t features_kernels(int64_t n, int64_t nnz, const int64_t* rp, const int32_t* col, const double* val,
+                            const FeatBuffers& fb, float* out, hipStream_t st)
+{
+    const unsigned rows = grid_for(n);
+    k_ft_fill<int32_t><<<rows, 256, 0, st>>>(n, fb.ccount, 0);
+    k_ft_colcount<<<rows, 256, 0, st>>>(n, rp, col, fb.ccount);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = scan_counts(n, fb.ccount, fb.tp, fb.tsum, fb.toff, st);
+    if (e != hipSuccess) return e;
+    k_ft_fill<int32_t><<<rows, 256, 0, st>>>(n, fb.ccount, 0);
+    k_ft_scatter<<<rows, 256, 0, st>>>(n, rp, col, val, fb.tp, fb.ccount, fb.trow_u, fb.tcol_u, fb.tval_u);
+    k_ft_rank<<<grid_for(nnz), 256, 0, st>>>(nnz, fb.tp, fb.trow_u, fb.tcol_u, fb.tval_u, fb.trow, fb.tval);
+    k_ft_merge<<<rows, 256, 0, st>>>(n, rp, col, val, fb.tp, fb.trow, fb.tval, nullptr, nullptr, fb.cnt);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = scan_counts(n, fb.cnt, fb.beg, fb.tsum, fb.toff, st)) != hipSuccess) return e;
+    k_ft_merge<<<rows, 256, 0, st>>>(n, rp, col, val, fb.tp, fb.trow, fb.tval, fb.beg, fb.ent, fb.cnt);
+    k_ft_fill<double><<<grid_for(n * kNF), 256, 0, st>>>(n * kNF, fb.F, 0.0);
+    k_features_pass1<<<grid_for(n * kRowLanes), 256, 0, st>>>(n, fb.beg, fb.cnt, fb.ent, fb.d, fb.F);
+    k_features_pass2<<<rows, 256, 0, st>>>(n, fb.beg, fb.cnt, fb.ent, fb.F, out);
+    return hipGetLastError();
+}
+
 mcinv_status features_on_device(int32_t device, int64_t n, int64_t nnz, const int64_t* row_ptr,
                                 const int32_t* col_idx, const double* values, float** d_features, std::string* err,
                                 std::vector<double>* diag_out)
@@ -323,9 +523,10 @@ mcinv_status features_on_device(int32_t device, int64_t n, int64_t nnz, const in
         *err = why;
         return singular ? MCINV_ESINGULAR : MCINV_EINVAL;
     }
-    std::vector<double> d(n);
-    for (int64_t i = 0; i < n; ++i) d[i] = diag[i].real();
-    if (diag_out) *diag_out = d;
+    if (diag_out) {
+        diag_out->resize(n);
+        for (int64_t i = 0; i < n; ++i) (*diag_out)[i] = diag[i].real();
+    }
     if (hipSetDevice(device) != hipSuccess) {
         *err = "no such device";
         return MCINV_EDEVICE;
@@ -344,87 +545,40 @@ mcinv_status features_on_device(int32_t device, int64_t n, int64_t nnz, const in
         if (e == hipSuccess) e = hipMalloc(p, std::max<size_t>(bytes, 1));
         if (e == hipSuccess) owned.p.push_back(*p);
     };
-    int64_t *d_rp = nullptr, *d_tp = nullptr, *d_beg = nullptr;
-    int32_t *d_col = nullptr, *d_ccount = nullptr, *d_cnt = nullptr;
-    double *d_val = nullptr, *d_tval = nullptr, *d_d = nullptr, *d_F = nullptr;
-    uint64_t *d_key = nullptr, *d_tkey = nullptr;
-    FEnt* d_ent = nullptr;
-    float* d_out = nullptr;
-    void* d_tmp = nullptr;
-    int64_t *d_tsum = nullptr, *d_toff = nullptr;
-    const int64_t ntiles = (n + 1023) / 1024;
-    // sort only the bits that keys below n^2 can use
-    unsigned bits = 1;
-    while (bits < 64 && ((unsigned __int128)1 << bits) < (unsigned __int128)n * (unsigned __int128)n) ++bits;
-    size_t tmp_bytes = 0;
-    e = rocprim::radix_sort_pairs(nullptr, tmp_bytes, (const uint64_t*)nullptr, (uint64_t*)nullptr,
-                                  (const double*)nullptr, (double*)nullptr, (size_t)nnz, 0u, bits);
-    // every scratch buffer is a 256-byte-aligned part of one allocation (few
+    // the CSR copy and every scratch buffer are parts of one allocation (few
     // allocations per call: small matrices are called many times)
-    const std::pair<void**, size_t> parts[] = {
-        {(void**)&d_rp, sizeof(int64_t) * ((size_t)n + 1)}, {(void**)&d_col, sizeof(int32_t) * (size_t)nnz},
-        {(void**)&d_val, sizeof(double) * (size_t)nnz},     {(void**)&d_key, sizeof(uint64_t) * (size_t)nnz},
-        {(void**)&d_tkey, sizeof(uint64_t) * (size_t)nnz},  {(void**)&d_tval, sizeof(double) * (size_t)nnz},
-        {(void**)&d_ccount, sizeof(int32_t) * (size_t)n},   {(void**)&d_tp, sizeof(int64_t) * ((size_t)n + 1)},
-        {(void**)&d_cnt, sizeof(int32_t) * (size_t)n},      {(void**)&d_beg, sizeof(int64_t) * ((size_t)n + 1)},
-        {(void**)&d_d, sizeof(double) * (size_t)n},         {(void**)&d_F, sizeof(double) * (size_t)n * kNF},
-        {(void**)&d_tsum, sizeof(int64_t) * (size_t)ntiles}, {(void**)&d_toff, sizeof(int64_t) * ((size_t)ntiles + 1)},
-        {&d_tmp, tmp_bytes}};
-    auto padded = [](size_t b) { return (b + 255) / 256 * 256; };
-    size_t slab_bytes = 0;
-    for (const auto& pr : parts) slab_bytes += padded(pr.second);
+    const size_t csr_bytes = pad256(sizeof(int64_t) * (n + 1)) + pad256(sizeof(int32_t) * nnz) +
+                             pad256(sizeof(double) * nnz);
     char* slab = nullptr;
-    alloc((void**)&slab, slab_bytes);
-    if (e == hipSuccess) {
-        size_t at = 0;
-        for (const auto& pr : parts) {
-            *pr.first = slab + at;
-            at += padded(pr.second);
-        }
-    }
-    if (e == hipSuccess) e = hipMemcpy(d_rp, row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice);
-    if (e == hipSuccess && nnz > 0) e = hipMemcpy(d_col, col_idx, sizeof(int32_t) * nnz, hipMemcpyHostToDevice);
-    if (e == hipSuccess && nnz > 0) e = hipMemcpy(d_val, values, sizeof(double) * nnz, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemcpy(d_d, d.data(), sizeof(double) * n, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMemset(d_ccount, 0, sizeof(int32_t) * n);
-    const unsigned blocks = (unsigned)((n + 255) / 256);
-    if (e == hipSuccess) {
-        k_ft_keys<<<blocks, 256>>>(n, d_rp, d_col, d_key, d_ccount);
-        e = hipGetLastError();
-    }
-    const uint64_t* ckey = d_key;   // inputs of the sort (d_val is read again by the merge)
-    const double* cval = d_val;
-    if (e == hipSuccess)
-        e = rocprim::radix_sort_pairs(d_tmp, tmp_bytes, ckey, d_tkey, cval, d_tval, (size_t)nnz, 0u, bits);
-    if (e == hipSuccess) e = scan_counts(n, d_ccount, d_tp, d_tsum, d_toff);
-    if (e == hipSuccess) {
-        k_ft_merge<<<blocks, 256>>>(n, d_rp, d_col, d_val, d_tp, d_tkey, d_tval, nullptr, nullptr, d_cnt);
-        e = hipGetLastError();
-    }
-    if (e == hipSuccess) e = scan_counts(n, d_cnt, d_beg, d_tsum, d_toff);
-    int64_t nent = 0;
-    if (e == hipSuccess) e = hipMemcpy(&nent, d_beg + n, sizeof(int64_t), hipMemcpyDeviceToHost);
-    alloc((void**)&d_ent, sizeof(FEnt) * (size_t)nent);
-    if (e == hipSuccess) {
-        k_ft_merge<<<blocks, 256>>>(n, d_rp, d_col, d_val, d_tp, d_tkey, d_tval, d_beg, d_ent, d_cnt);
-        e = hipGetLastError();
-    }
+    float* d_out = nullptr;
+    alloc((void**)&slab, csr_bytes + feat_bytes(n, nnz));
     alloc((void**)&d_out, sizeof(float) * (size_t)n * kNF);
-    if (e == hipSuccess) e = hipMemset(d_F, 0, sizeof(double) * n * kNF);
     if (e == hipSuccess) {
-        k_features_pass1<<<(unsigned)((n * kRowLanes + 255) / 256), 256>>>(n, d_beg, d_cnt, d_ent, d_d, d_F);
-        e = hipGetLastError();
+        int64_t* d_rp = (int64_t*)slab;
+        int32_t* d_col = (int32_t*)(slab + pad256(sizeof(int64_t) * (n + 1)));
+        double* d_val = (double*)((char*)d_col + pad256(sizeof(int32_t) * nnz));
+        const FeatBuffers fb = feat_carve(slab + csr_bytes, n, nnz);
+        e = hipMemcpy(d_rp, row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(d_col, col_idx, sizeof(int32_t) * nnz, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(d_val, values, sizeof(double) * nnz, hipMemcpyHostToDevice);
+        unsigned long long flags[2] = {0, 0};
+        if (e == hipSuccess) e = features_validate(n, nnz, d_rp, d_col, d_val, fb, flags, nullptr);
+        if (e == hipSuccess) {
+            const char* w = nullptr;
+            const mcinv_status vs = validation_status(flags, &w);
+            if (vs != MCINV_OK) {   // the host check above passed, so the two disagree
+                *err = std::string("device validation: ") + w;
+                return MCINV_EINTERNAL;
+            }
+        }
+        if (e == hipSuccess) e = features_kernels(n, nnz, d_rp, d_col, d_val, fb, d_out, nullptr);
+        if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
     }
-    if (e == hipSuccess) {
-        k_features_pass2<<<blocks, 256>>>(n, d_beg, d_cnt, d_ent, d_F, d_out);
-        e = hipGetLastError();
-    }
-    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
-    if (e == hipSuccess) owned.p.erase(std::find(owned.p.begin(), owned.p.end(), (void*)d_out));
     if (e != hipSuccess) {
         *err = hipGetErrorString(e);
         return e == hipErrorOutOfMemory ? MCINV_ENOMEM : MCINV_EDEVICE;
     }
+    owned.p.erase(std::find(owned.p.begin(), owned.p.end(), (void*)d_out));
     *d_features = d_out;
     return MCINV_OK;
 }
