@@ -459,6 +459,25 @@ const char* mcinv_batch_last_error(const mcinv_batch* b);
 mcinv_status mcinv_features(int32_t device, int64_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
                             const double* values, float* out);
 
+/* mcinv_features for callers that cannot allocate memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same features, bit for bit, from the same kernels, but every array is
+ * DEVICE memory the caller owns -- row_ptr int64[n+1], col_idx int32[nnz],
+ * values float64[nnz] in, out float32[n][32] -- and the scratch buffers
+ * (column counts and pointers, the transposed entries, the merged neighbour
+ * lists, the per-row terms) come from a fixed 32 MiB device array of the
+ * library, which each GPU keeps for the life of the process.  Limits: 1 <= n
+ * <= 32768 and n <= nnz <= 262144, else EINVAL.  The CSR rules of
+ * mcinv_load_csr are checked on the device (EINVAL for a pattern error,
+ * ESINGULAR for a missing or zero diagonal; the message, from
+ * mcinv_last_error(NULL), names the kind of error but not the row).  Runs on
+ * `stream` (a hipStream_t, NULL for the default stream) and synchronises it
+ * before returning.  No device or host memory is allocated on success (an
+ * error message may allocate).  Calls on one GPU share its scratch array, so
+ * calls that overlap on one GPU (from several host threads) race. */
+mcinv_status mcinv_features_noalloc(int32_t device, int64_t n, int64_t nnz, const int64_t* row_ptr,
+                                    const int32_t* col_idx, const double* values, float* out, void* stream);
+
 /* The network: 32 -> 128 -> 128 -> 1, GELU (erf form) after the two hidden
  * layers.  Parameters, float32, in this order (20865 values):
  *   W1[32][128] (input-major), b1[128], W2[128][128] (input-major), b2[128],

@@ -162,6 +162,7 @@ SIGNATURES = {
                                     ctypes.POINTER(_D)]),
     "mcinv_batch_get_info": (_I32, [_P, ctypes.POINTER(mcinv_batch_info)]),
     "mcinv_batch_last_error": (ctypes.c_char_p, [_P]),
+    "mcinv_features_noalloc": (_I32, [_I32, _I64, _I64, _P, _P, _P, _P, _P]),
     "mcinv_features": (_I32, [_I32, _I64, _I64, _P, _P, _P, _P]),
     "mcinv_mlp_create": (_I32, [_I32, ctypes.POINTER(_P)]),
     "mcinv_mlp_destroy": (None, [_P]),
@@ -516,6 +517,14 @@ def mcinv_features(device, n, nnz, row_ptr, col_idx, values):
     out = np.empty((int(n), MCINV_N_FEATURES), dtype=np.float32)
     _check(None, lib().mcinv_features(int(device), int(n), int(nnz), _ptr(rp), _ptr(ci), _ptr(v), _ptr(out)))
     return out
+
+
+def mcinv_features_noalloc(device, n, nnz, row_ptr, col_idx, values, out, stream=None):
+    """Device-array form (``mcinv_features_noalloc``): row_ptr, col_idx, values
+    and out are device addresses (ints, e.g. torch ``data_ptr()``)."""
+    _check(None, lib().mcinv_features_noalloc(int(device), int(n), int(nnz), ctypes.c_void_p(row_ptr),
+                                              ctypes.c_void_p(col_idx), ctypes.c_void_p(values),
+                                              ctypes.c_void_p(out), stream))
 
 
 def _mcheck(m, status):

@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cmath>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -623,6 +624,89 @@ try {
     (void)hipFree(d_F);
     if (e != hipSuccess) {
         set_context_free_error(std::string("mcinv_features: ") + hipGetErrorString(e));
+        return MCINV_EDEVICE;
+    }
+    return MCINV_OK;
+} catch (...) {
+    return mcinv::exception_status([&](mcinv_status, const std::string& m_) { set_context_free_error(m_); });
+}
+
+// ---------------------------------------------------------------------------
+// Features that allocate nothing: the caller's device arrays in and out, the
+// scratch buffers carved from a file-scope device array of fixed size.  Each
+// GPU holds its own copy of the array; its address on a device comes from
+// hipGetSymbolAddress on that device's first call (the array's name is only a
+// host-side stand-in and never reaches a kernel).  Every call on a GPU reuses
+// that GPU's array, so calls on one GPU must not overlap.
+namespace {
+
+constexpr int64_t kNoAllocMaxRows = 32768;
+constexpr int64_t kNoAllocMaxNnz = 262144;
+constexpr size_t kNoAllocScratchBytes = (size_t)32 << 20;
+constexpr int kNoAllocMaxDevices = 64;
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+// The scratch array's device address on the current device (looked up once per device).
+hipError_t scratch_on(int32_t device, void** ptr)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = p;
+    }
+    *ptr = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" mcinv_status mcinv_features_noalloc(int32_t device, int64_t n, int64_t nnz, const int64_t* row_ptr,
+                                               const int32_t* col_idx, const double* values, float* out,
+                                               void* stream)
+try {
+    if (!row_ptr || !col_idx || !values || !out) {
+        set_context_free_error("mcinv_features_noalloc: null device array");
+        return MCINV_EINVAL;
+    }
+    if (n < 1 || nnz < n || n > kNoAllocMaxRows || nnz > kNoAllocMaxNnz) {
+        set_context_free_error("mcinv_features_noalloc: needs 1 <= n <= 32768 and n <= nnz <= 262144 (the "
+                               "fixed scratch size); use mcinv_features for larger matrices");
+        return MCINV_EINVAL;
+    }
+    static_assert(kNoAllocMaxRows <= INT32_MAX, "row indices are 32-bit");
+    if (device < 0 || device >= kNoAllocMaxDevices || hipSetDevice(device) != hipSuccess) {
+        set_context_free_error("mcinv_features_noalloc: no such device");
+        return MCINV_EDEVICE;
+    }
+    void* base = nullptr;
+    hipError_t e = scratch_on(device, &base);
+    if (e == hipSuccess && feat_bytes(n, nnz) > kNoAllocScratchBytes) e = hipErrorInvalidValue;   // guarded above
+    const hipStream_t st = (hipStream_t)stream;
+    const FeatBuffers fb = feat_carve((char*)base, n, nnz);
+    unsigned long long flags[2] = {0, 0};
+    if (e == hipSuccess) e = features_validate(n, nnz, row_ptr, col_idx, values, fb, flags, st);
+    if (e == hipSuccess) {
+        const char* why = nullptr;
+        const mcinv_status vs = validation_status(flags, &why);
+        if (vs != MCINV_OK) {
+            set_context_free_error(std::string("mcinv_features_noalloc: ") + why);
+            return vs;
+        }
+        e = features_kernels(n, nnz, row_ptr, col_idx, values, fb, out, st);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        set_context_free_error(std::string("mcinv_features_noalloc: ") + hipGetErrorString(e));
         return MCINV_EDEVICE;
     }
     return MCINV_OK;
