@@ -818,6 +818,12 @@ def main():
     if args.copy_calibration:
         result["copy_calibration"] = {"bytes_read": nbytes, "bytes_written": nbytes, "ms": cms,
                                       "GBps": 2 * nbytes / (cms / 1e3) / 1e9}
+        # two more reference kernels for the counter scale: a read-only 1 GiB
+        # sum and a write-only 1 GiB fill
+        tot = src.sum()
+        dst.fill_(2.0)
+        torch.cuda.synchronize()
+        result["copy_calibration"]["sum_check"] = float(tot)
     del src, dst
 
     if not args.no_cpu:
