@@ -6,16 +6,17 @@
 // Kernels
 //   k_mlp_fwd_bwd : one wave = 16 rows.  Layer 1 and 2 products on
 //                   v_mfma_f32_16x16x32_bf16 (A = activations, B = weights
-//                   from global), GELU in fp32, output layer in fp32.  With
-//                   `backward`: the weighted-MSE gradient flows back through
+//                   from global), GELU in fp32, output layer in fp32.  The
+//                   training instance (BWD): the weighted-MSE gradient flows back through
 //                   layer 3 (fp32), layer 2 (dgrad on MFMA) and both GELUs;
 //                   activations and deltas go out transposed as bf16 for the
 //                   weight gradients, bias / w3 partial sums per workgroup.
 //   k_mlp_wgrad   : dW1 = X^T dz1, dW2 = h1^T dz2 over the step's rows
-//                   (32 x 32 tile per workgroup, the rows split over
-//                   workgroups and over its 4 waves, summed in a fixed order).
-//   k_mlp_update  : gradient assembly (partials summed in a fixed order),
-//                   Adam step, bf16 copies of the weights.
+//                   (the whole 128 x 128 or 32 x 128 output per workgroup,
+//                   one sub-tile per wave, the rows split over workgroups).
+//   k_mlp_update  : gradient assembly (every partial summed in a fixed
+//                   order), Adam step, bf16 copies of the weights.
+// Training draws each step's rows from Philox inside k_mlp_fwd_bwd.
 // Rounding points (what the oracle reproduces): the normalised features,
 // W1, W2, h1 and dz2 enter MFMA products as bf16 (nearest even); h2, w3, the
 // biases and every elementwise step stay fp32.
@@ -41,10 +42,12 @@ constexpr int oW1 = 0, ob1 = kF * kH, oW2 = ob1 + kH, ob2 = oW2 + kH * kH, ow3 =
 constexpr int kParams = ob3 + 1;     // 20865
 constexpr int kPart = 3 * kH + 2;    // db1, db2, dw3, db3, loss
 constexpr int kActLd = kH + 8;       // LDS row pitch (bf16) of one wave's activations
+constexpr int kWRow = ob2 + kPart;   // one weight-gradient partial row: W1 | b1 gap | W2 | block sums
 
 typedef unsigned short bf16_t;
 
-__device__ inline bf16_t to_bf16(float x) { return bf16_rne(x); }
+// round to nearest even (one v_cvt_pk_bf16_f32 on gfx950)
+__device__ inline bf16_t to_bf16(float x) { return __builtin_bit_cast(bf16_t, (__bf16)x); }
 
 __device__ inline bf16x8 load_bf16x8(const bf16_t* p)
 {
@@ -58,8 +61,10 @@ struct MlpArgs {
     const float* w;          // row weights [N]
     const int64_t* idx;      // rows of this call, or null: rows row0 + r
     int64_t row0;
+    int32_t draw;            // nonzero: rows drawn from Philox (key, step) over N rows
+    uint32_t key0, key1, step;
+    int64_t N;
     int32_t R;               // rows of this call
-    int32_t backward;
     const float* mean;       // feature normalisation: (x - mean) * inv_std
     const float* inv_std;
     const bf16_t* W1T;       // [128][32]
@@ -95,65 +100,115 @@ __device__ inline void store_transposed(const bf16_t (*src)[kActLd], int ncols, 
     }
 }
 
-__global__ __launch_bounds__(256) void k_mlp_fwd_bwd(const MlpArgs a)
+// GELU (erf form) and its derivative at z: h = z Phi(z) and gp = Phi(z) +
+// z phi(z), with Phi(z) = (1 + erf(z / sqrt 2)) / 2 and phi(z) = exp(-z^2 / 2)
+// / sqrt(2 pi).
+template <bool GP>
+__device__ inline void gelu_terms(float z, float& h, float& gp)
 {
-    // act: h1 (bf16) as layer 2's A operand, then dz2 (bf16) as the dgrad A
-    // operand; gp1: gelu'(z1) kept from the forward pass for the backward
-    // one, so no first-layer pre-activations stay in registers.
+    constexpr float kRs2 = 0.70710678118654752f, kRs2pi = 0.39894228040143268f;
+    const float e = erff(z * kRs2);
+    h = 0.5f * z * (1.0f + e);
+    gp = GP ? 0.5f * (1.0f + e) + z * expf(-0.5f * z * z) * kRs2pi : 0.0f;
+}
+
+// The four rows 4kg .. 4kg+3 of column c that a lane holds in an MFMA result
+// (bf16) into the transposed buffer dst[c][R] at rows r0w + 4kg .. (8 bytes;
+// r0w is a multiple of 16, so the store is aligned).
+__device__ inline void store_col4(bf16_t* dst, int64_t R, int64_t r0w, int c, int kg, const bf16_t v[4])
+{
+    uint2 w;
+    w.x = (uint32_t)v[0] | ((uint32_t)v[1] << 16);
+    w.y = (uint32_t)v[2] | ((uint32_t)v[3] << 16);
+    *reinterpret_cast<uint2*>(dst + (int64_t)c * R + r0w + 4 * kg) = w;
+}
+
+// Orders a wave's own LDS accesses (each wave works in its private slice of
+// the workgroup's LDS, so no workgroup barrier is needed between its phases).
+__device__ inline void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Row of the training data for step row r: the caller's list, a contiguous
+// range, or the Philox draw floor(x N / 2^64) of the step (counter (r, step,
+// 0x5EED, 0xA11CE), x = (o0 << 32) | o1).
+__device__ inline int64_t mlp_row(const MlpArgs& a, int64_t r)
+{
+    if (a.draw) {
+        uint32_t c0 = (uint32_t)r, c1 = a.step, c2 = 0x5EEDu, c3 = 0xA11CEu;
+        Philox::block(c0, c1, c2, c3, a.key0, a.key1);
+        const uint64_t x = ((uint64_t)c0 << 32) | c1;
+        return (int64_t)(((unsigned __int128)x * (uint64_t)a.N) >> 64);
+    }
+    return a.idx ? a.idx[r] : a.row0 + r;
+}
+
+#ifndef MCINV_MLP_MIN_BLOCKS
+#define MCINV_MLP_MIN_BLOCKS 2   // workgroups per CU the register budget is sized for
+#endif
+template <bool BWD>
+__global__ __launch_bounds__(256, MCINV_MLP_MIN_BLOCKS) void k_mlp_fwd_bwd(const MlpArgs a)
+{
+    // act (wave-private): the normalised features (written out transposed
+    // for the weight gradients), then h1 (bf16) as layer 2's A operand, then
+    // dz2 (bf16) as the dgrad A operand.  h1, dz2 and dz1 also go straight
+    // from the MFMA result layout to their transposed buffers.  gelu'(z1)
+    // and layer 2's GELU values stay in registers for the backward pass.
     __shared__ __align__(16) bf16_t act[4][16][kActLd];
-    __shared__ __align__(16) bf16_t dz1s[4][16][kActLd];
-    __shared__ float gp1[4][16][kH + 4];
     __shared__ float part[4][kPart];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int i16 = lane & 15, kg = lane >> 4;
     const int64_t r0w = (int64_t)blockIdx.x * 64 + wid * 16;
-    auto row_of = [&](int64_t r) { return a.idx ? a.idx[r] : a.row0 + r; };
     const float* P = a.P;
-    constexpr float kRs2 = 0.70710678118654752f, kRs2pi = 0.39894228040143268f;
 
     // ---- layer 1: A = normalised features (row i16, features 8kg..8kg+7)
     const int64_t ra = r0w + i16;
     const bool aok = ra < a.R;
+    const int64_t rowa = aok ? mlp_row(a, ra) : 0;
     bf16x8 a1;
     {
-        unsigned short u[8];
-        const float* x = a.X + (aok ? row_of(ra) : 0) * kF + 8 * kg;
+        u16x8 u;
+        const float* x = a.X + rowa * kF + 8 * kg;
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const float xn = aok ? (x[e] - a.mean[8 * kg + e]) * a.inv_std[8 * kg + e] : 0.0f;
             u[e] = to_bf16(xn);
-            if (a.backward) act[wid][i16][8 * kg + e] = u[e];
+            if (BWD) act[wid][i16][8 * kg + e] = u[e];
         }
-        u16x8 v;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = u[e];
-        a1 = __builtin_bit_cast(bf16x8, v);
+        a1 = __builtin_bit_cast(bf16x8, u);
     }
-    if (a.backward) {   // backward launches cover whole 64-row blocks
-        __syncthreads();
+    if (BWD) {   // backward launches cover whole 64-row blocks
+        wave_lds_sync();
         store_transposed(act[wid], kF, a.XT, a.R, r0w, lane);
-        __syncthreads();
+        wave_lds_sync();
     }
-    // z1 -> h1 = GELU(z1) into LDS (bf16) and h1^T; gelu'(z1) into LDS
+    // z1 -> h1 = GELU(z1) into LDS (bf16) and h1^T; gelu'(z1) kept in registers
+    float gp1[8][4];
+#pragma unroll
     for (int n = 0; n < 8; ++n) {
         const bf16x8 b = load_bf16x8(a.W1T + (16 * n + i16) * kF + 8 * kg);
         const f32x4 z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
         const float bias = P[ob1 + 16 * n + i16];
+        bf16_t hb[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const float zz = z[v] + bias;
-            const float e = erff(zz * kRs2);
-            const bf16_t hb = to_bf16(0.5f * zz * (1.0f + e));
-            act[wid][4 * kg + v][16 * n + i16] = hb;
-            if (a.backward)
-                gp1[wid][4 * kg + v][16 * n + i16] = 0.5f * (1.0f + e) + zz * expf(-0.5f * zz * zz) * kRs2pi;
+            float hv, gv;
+            gelu_terms<BWD>(z[v] + bias, hv, gv);
+            hb[v] = to_bf16(hv);
+            act[wid][4 * kg + v][16 * n + i16] = hb[v];
+            gp1[n][v] = gv;
         }
+        if (BWD) store_col4(a.h1T, a.R, r0w, 16 * n + i16, kg, hb);
+        __builtin_amdgcn_sched_barrier(0);
     }
-    __syncthreads();
-    if (a.backward) store_transposed(act[wid], kH, a.h1T, a.R, r0w, lane);
+    wave_lds_sync();
 
-    // ---- layer 2
-    f32x4 z2[8];
+    // ---- layer 2, and layer 3 (fp32) on the fly: out_v for rows r0w + 4kg + v
+    float h2[8][4], gp2[8][4];
+    float out[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int n = 0; n < 8; ++n) {
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
@@ -164,26 +219,20 @@ __global__ __launch_bounds__(256) void k_mlp_fwd_bwd(const MlpArgs a)
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b, acc, 0, 0, 0);
         }
         const float bias = P[ob2 + 16 * n + i16];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) z2[n][v] = acc[v] + bias;
-        // one column block at a time: hoisting every block's weight loads
-        // measured 1.4x slower (register pressure, two waves per SIMD)
-        __builtin_amdgcn_sched_barrier(0);
-    }
-
-    // ---- layer 3 (fp32): out_v for rows r0w + 4kg + v
-    float out[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int n = 0; n < 8; ++n) {
         const float w3 = P[ow3 + 16 * n + i16];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) out[v] += 0.5f * z2[n][v] * (1.0f + erff(z2[n][v] * kRs2)) * w3;
+        for (int v = 0; v < 4; ++v) {
+            gelu_terms<BWD>(acc[v] + bias, h2[n][v], gp2[n][v]);
+            out[v] += h2[n][v] * w3;
+        }
+        __builtin_amdgcn_sched_barrier(0);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         for (int off = 1; off < 16; off <<= 1) out[v] += __shfl_xor(out[v], off);
         out[v] += P[ob3];
     }
-    if (!a.backward) {
+    if (!BWD) {
         if (i16 == 0)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
@@ -193,14 +242,15 @@ __global__ __launch_bounds__(256) void k_mlp_fwd_bwd(const MlpArgs a)
         return;
     }
 
-    // ---- loss gradient
+    // ---- loss gradient (the rows 4kg + v of this lane's group: their data
+    // rows come from the lanes i16 = 4kg + v that loaded them)
     float dout[4], lossp = 0.f, db3 = 0.f;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const int64_t rd = r0w + 4 * kg + v;
+        const int64_t row = __shfl(rowa, 4 * kg + v);
         float dv = 0.f;
         if (rd < a.R) {
-            const int64_t row = row_of(rd);
             const float diff = out[v] - a.y[row];
             dv = 2.0f * a.w[row] * diff * a.inv_denom;
             lossp += a.w[row] * diff * diff * a.inv_denom;
@@ -209,27 +259,28 @@ __global__ __launch_bounds__(256) void k_mlp_fwd_bwd(const MlpArgs a)
         db3 += dv;
     }
 
-    // ---- layer 3 backward and layer 2 deltas, written straight to LDS (bf16)
+    // ---- layer 3 backward and layer 2 deltas, written to LDS (bf16); every
+    // lane has finished reading h1 (wave order)
     float dw3p[8], db2p[8];
-    __syncthreads();  // every wave is done reading h1 from LDS
+    wave_lds_sync();
 #pragma unroll
     for (int n = 0; n < 8; ++n) {
         const float w3 = P[ow3 + 16 * n + i16];
         float s3 = 0.f, s2 = 0.f;
+        bf16_t db[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const float zz = z2[n][v];
-            const float e = erff(zz * kRs2);
-            s3 += 0.5f * zz * (1.0f + e) * dout[v];
-            const float d = dout[v] * w3 * (0.5f * (1.0f + e) + zz * expf(-0.5f * zz * zz) * kRs2pi);
+            s3 += h2[n][v] * dout[v];
+            const float d = dout[v] * w3 * gp2[n][v];
             s2 += d;
-            act[wid][4 * kg + v][16 * n + i16] = to_bf16(d);
+            db[v] = to_bf16(d);
+            act[wid][4 * kg + v][16 * n + i16] = db[v];
         }
+        store_col4(a.dz2T, a.R, r0w, 16 * n + i16, kg, db);
         dw3p[n] = s3;
         db2p[n] = s2;
     }
-    __syncthreads();
-    store_transposed(act[wid], kH, a.dz2T, a.R, r0w, lane);
+    wave_lds_sync();
 
     // ---- dgrad of layer 2: dh1 = dz2 W2^T, then through GELU
     float db1p[8];
@@ -243,18 +294,17 @@ __global__ __launch_bounds__(256) void k_mlp_fwd_bwd(const MlpArgs a)
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b, acc, 0, 0, 0);
         }
         float s1 = 0.f;
+        bf16_t db[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const float d = acc[v] * gp1[wid][4 * kg + v][16 * n + i16];
+            const float d = acc[v] * gp1[n][v];
             s1 += d;
-            dz1s[wid][4 * kg + v][16 * n + i16] = to_bf16(d);
+            db[v] = to_bf16(d);
         }
+        store_col4(a.dz1T, a.R, r0w, 16 * n + i16, kg, db);
         db1p[n] = s1;
         __builtin_amdgcn_sched_barrier(0);
     }
-
-    __syncthreads();
-    store_transposed(dz1s[wid], kH, a.dz1T, a.R, r0w, lane);
 
     // ---- per-wave sums over its 16 rows (the 4 row groups kg), then per block
 #pragma unroll
@@ -287,71 +337,85 @@ __global__ __launch_bounds__(256) void k_mlp_fwd_bwd(const MlpArgs a)
         a.part[(int64_t)blockIdx.x * kPart + k] = ((part[0][k] + part[1][k]) + part[2][k]) + part[3][k];
 }
 
-// dW (rows x 128) = L Rt^T over K training rows: L is [rows][K], Rt is
-// [128][K] (bf16, the transposed activations / deltas).  Workgroup (tile,
-// ks) covers the rows [ks Kc, (ks + 1) Kc) of the step; its wave `wid` takes
-// the 32-row slabs wid, wid + 4, ... of that range and the four partial tiles
-// are summed in order.  The ks partials go to wpart[ks][W1 | b1 gap | W2] and
-// are summed in order of ks by the update kernel.
-__global__ __launch_bounds__(256) void k_mlp_wgrad(const bf16_t* XT, const bf16_t* dz1T, const bf16_t* h1T,
-                                                   const bf16_t* dz2T, int32_t K, int32_t Kc, float* wpart)
+// dW (M x 128) = L Rt^T over a chunk of the step's K rows: L is [M][K], Rt
+// is [128][K] (bf16, the transposed activations / deltas).  blockIdx.x = 0:
+// dW2 (M = 128: L = h1^T, Rt = dz2^T), 1: dW1 (M = 32: L = X^T, Rt = dz1^T);
+// blockIdx.y = ks covers rows [ks Kc, (ks + 1) Kc).  Each wave owns one
+// output sub-tile (dW2: 64 x 64, waves in a 2 x 2 grid; dW1: 32 x 32, waves
+// side by side) over the whole chunk, so every L and Rt element of the chunk
+// is read once per workgroup; the partial tile goes to wpart[ks][W1 | b1
+// gap | W2] and the update kernel sums the ks partials in a fixed order.
+template <int TI, int TJ>
+__device__ inline void wgrad_tile(const bf16_t* L, const bf16_t* Rt, int64_t K, int kb0, int kb1, int r0, int c0,
+                                  float* out, int lane)
 {
-    __shared__ float red[4][32][33];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int i16 = lane & 15, kg = lane >> 4;
-    // tiles 0..3: dW1 (32 x 128), tiles 4..19: dW2 (128 x 128)
-    const int tile = blockIdx.x;
-    const int ks = blockIdx.y;
-    const bf16_t *L, *Rt;
-    int r0, c0, base;
-    if (tile < 4) {
-        L = XT; Rt = dz1T; r0 = 0; c0 = 32 * tile; base = oW1;
-    } else {
-        L = h1T; Rt = dz2T; r0 = 32 * ((tile - 4) / 4); c0 = 32 * ((tile - 4) % 4); base = oW2;
+    f32x4 acc[TI][TJ];
+#pragma unroll
+    for (int i = 0; i < TI; ++i)
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const bf16_t* La[TI];
+    const bf16_t* Rb[TJ];
+#pragma unroll
+    for (int i = 0; i < TI; ++i) La[i] = L + (int64_t)(r0 + 16 * i + i16) * K + 8 * kg;
+#pragma unroll
+    for (int j = 0; j < TJ; ++j) Rb[j] = Rt + (int64_t)(c0 + 16 * j + i16) * K + 8 * kg;
+    // the next k step's fragments are loaded while this one's MFMAs run
+    bf16x8 av[TI], bv[TJ];
+    if (kb0 < kb1) {
+#pragma unroll
+        for (int i = 0; i < TI; ++i) av[i] = load_bf16x8(La[i] + kb0);
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) bv[j] = load_bf16x8(Rb[j] + kb0);
     }
-    f32x4 acc[2][2];
+    for (int kb = kb0; kb < kb1; kb += 32) {
+        bf16x8 an[TI], bn[TJ];
+        const int kn = kb + 32 < kb1 ? kb + 32 : kb;
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < TI; ++i) an[i] = load_bf16x8(La[i] + kn);
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const int k_end = min(K, (ks + 1) * Kc);   // Kc and K: multiples of 32
-    for (int kb = ks * Kc + 32 * wid; kb < k_end; kb += 128) {
-        bf16x8 av[2], bv[2];
+        for (int j = 0; j < TJ; ++j) bn[j] = load_bf16x8(Rb[j] + kn);
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            av[t] = load_bf16x8(L + (int64_t)(r0 + 16 * t + i16) * K + kb + 8 * kg);
-            bv[t] = load_bf16x8(Rt + (int64_t)(c0 + 16 * t + i16) * K + kb + 8 * kg);
-        }
+        for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < TJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
 #pragma unroll
-            for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
+        for (int i = 0; i < TI; ++i) av[i] = an[i];
+#pragma unroll
+        for (int j = 0; j < TJ; ++j) bv[j] = bn[j];
     }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < TI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < TJ; ++j)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) red[wid][16 * i + 4 * kg + v][16 * j + i16] = acc[i][j][v];
-    __syncthreads();
-    float* out = wpart + (int64_t)ks * ob2;
-    for (int t = threadIdx.x; t < 32 * 32; t += 256) {
-        const int r = t / 32, c = t % 32;
-        const float s = ((red[0][r][c] + red[1][r][c]) + red[2][r][c]) + red[3][r][c];
-        out[base + (r0 + r) * kH + c0 + c] = s;
-    }
+            for (int v = 0; v < 4; ++v) out[(r0 + 16 * i + 4 * kg + v) * kH + c0 + 16 * j + i16] = acc[i][j][v];
 }
 
-// psum[k] = sum over the forward/backward workgroups of part[b][k]: one
-// wave per k, lane l summing b = l, l + 64, ... in order, then a fixed
-// butterfly across the lanes.
-__global__ __launch_bounds__(64) void k_mlp_reduce_parts(const float* part, int32_t blocks, float* psum)
+// blockIdx.x = 2: the forward/backward workgroups' partial sums (biases,
+// w3, b3, loss) of blocks [ks bc, (ks + 1) bc), summed in order, into the
+// row's block-sum slots.
+__global__ __launch_bounds__(256) void k_mlp_wgrad(const bf16_t* XT, const bf16_t* dz1T, const bf16_t* h1T,
+                                                   const bf16_t* dz2T, int32_t K, int32_t Kc, const float* part,
+                                                   int32_t blocks, int32_t bc, float* wpart)
 {
-    const int k = blockIdx.x, lane = threadIdx.x;
-    float v = 0.f;
-    for (int b = lane; b < blocks; b += 64) v += part[(int64_t)b * kPart + k];
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    if (lane == 0) psum[k] = v;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int ks = blockIdx.y;
+    const int kb0 = ks * Kc, kb1 = min(K, (ks + 1) * Kc);   // Kc and K: multiples of 32
+    float* out = wpart + (int64_t)ks * kWRow;
+    if (blockIdx.x == 0) {
+        wgrad_tile<4, 4>(h1T, dz2T, K, kb0, kb1, 64 * (wid >> 1), 64 * (wid & 1), out + oW2, lane);
+    } else if (blockIdx.x == 1) {
+        wgrad_tile<2, 2>(XT, dz1T, K, kb0, kb1, 0, 32 * wid, out + oW1, lane);
+    } else {
+        const int b0 = ks * bc, b1 = min(blocks, (ks + 1) * bc);
+        for (int k = threadIdx.x; k < kPart; k += 256) {
+            float s = 0.f;
+            for (int b = b0; b < b1; ++b) s += part[(int64_t)b * kPart + k];
+            out[ob2 + k] = s;
+        }
+    }
 }
 
 struct UpdateArgs {
@@ -359,9 +423,8 @@ struct UpdateArgs {
     float* m;                // Adam first moments
     float* v;                // Adam second moments
     float* grads;            // the assembled gradient [kParams]
-    const float* wpart;      // weight-gradient partials [nks][ob2]
+    const float* wpart;      // partial rows [nks][kWRow]
     int32_t nks;
-    const float* psum;       // [kPart] summed workgroup partials
     int32_t apply;           // 0: only assemble the gradient
     float lr, beta1, beta2, eps;
     float bc1, bc2;          // 1 - beta^t
@@ -371,29 +434,56 @@ struct UpdateArgs {
     float* loss_out;         // loss of this step, or null
 };
 
-__global__ __launch_bounds__(256) void k_mlp_update(const UpdateArgs u)
+// Gradient assembly and Adam: 64 parameters per workgroup, sixteen threads
+// per parameter, thread q summing the partial rows q, q + 16, ... in eight
+// interleaved running sums joined in a fixed order, the sixteen sums then
+// added in a fixed order.  Index kParams is the loss.
+constexpr int kUpdSlices = 16;
+
+__device__ inline float strided_sum(const float* base, int64_t stride, int count, int q)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p == 0 && u.loss_out) *u.loss_out = u.psum[3 * kH + 1];
-    if (p >= kParams) return;
-    float g;
-    if ((p >= oW1 && p < ob1) || (p >= oW2 && p < ob2)) {
-        g = 0.f;
-        for (int k = 0; k < u.nks; ++k) g += u.wpart[(int64_t)k * ob2 + p];
-        u.grads[p] = g;
-    } else {
-        int k;
-        if (p < oW2)
-            k = p - ob1;               // db1
+    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int k = q, j = 0;
+    for (; k + 7 * kUpdSlices < count; k += 8 * kUpdSlices)
+#pragma unroll
+        for (int t = 0; t < 8; ++t) acc[t] += base[(int64_t)(k + t * kUpdSlices) * stride];
+    for (; k < count; k += kUpdSlices, ++j) acc[j & 7] += base[(int64_t)k * stride];
+    return ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+}
+
+__global__ __launch_bounds__(1024) void k_mlp_update(const UpdateArgs u)
+{
+    __shared__ float red[kUpdSlices][64];
+    const int c = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int p = blockIdx.x * 64 + c;
+    float s = 0.f;
+    if (p <= kParams) {
+        int col;
+        if ((p >= oW1 && p < ob1) || (p >= oW2 && p < ob2))
+            col = p;
+        else if (p == kParams)
+            col = ob2 + 3 * kH + 1;        // loss
+        else if (p < oW2)
+            col = ob2 + (p - ob1);         // db1
         else if (p < ow3)
-            k = kH + (p - ob2);        // db2
+            col = ob2 + kH + (p - ob2);    // db2
         else if (p < ob3)
-            k = 2 * kH + (p - ow3);    // dw3
+            col = ob2 + 2 * kH + (p - ow3); // dw3
         else
-            k = 3 * kH;                // db3
-        g = u.psum[k];
-        u.grads[p] = g;
+            col = ob2 + 3 * kH;            // db3
+        s = strided_sum(u.wpart + col, kWRow, u.nks, q);
     }
+    red[q][c] = s;
+    __syncthreads();
+    if (q != 0 || p > kParams) return;
+    float g = 0.f;
+#pragma unroll
+    for (int t = 0; t < kUpdSlices; ++t) g += red[t][c];
+    if (p == kParams) {
+        if (u.loss_out) *u.loss_out = g;
+        return;
+    }
+    u.grads[p] = g;
     if (!u.apply) return;
     const float m = u.beta1 * u.m[p] + (1.0f - u.beta1) * g;
     const float v = u.beta2 * u.v[p] + (1.0f - u.beta2) * g * g;
@@ -425,18 +515,6 @@ __global__ __launch_bounds__(256) void k_mlp_bf16_copies(const float* P, bf16_t*
     }
 }
 
-// Philox-drawn rows of one training step: idx[r] = floor(u * N).
-__global__ __launch_bounds__(256) void k_mlp_sample_rows(uint32_t k0, uint32_t k1, uint32_t step, int64_t N,
-                                                         int32_t R, int64_t* idx)
-{
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= R) return;
-    uint32_t c0 = (uint32_t)r, c1 = step, c2 = 0x5EEDu, c3 = 0xA11CEu;
-    Philox::block(c0, c1, c2, c3, k0, k1);
-    const uint64_t x = ((uint64_t)c0 << 32) | c1;
-    idx[r] = (int64_t)(((unsigned __int128)x * (uint64_t)N) >> 64);
-}
-
 }  // namespace mcinv
 
 using namespace mcinv;
@@ -462,7 +540,6 @@ struct mcinv_mlp {
     // step buffers
     int32_t Rcap = 0;
     float* wpart = nullptr;  // [ks][ob2]
-    float* psum = nullptr;   // [kPart]
     int64_t* idx = nullptr;
     bf16_t* XT = nullptr;
     bf16_t* h1T = nullptr;
@@ -501,8 +578,12 @@ mcinv_status merr(mcinv_mlp* m, mcinv_status code, const std::string& msg)
                         std::string(#expr) + ": " + hipGetErrorString(e_));                     \
     } while (0)
 
-// Row splits of the weight-gradient GEMMs: about 512 rows each, at most 64.
-int32_t ks_of(int32_t R) { return std::max(1, std::min(64, R / 512)); }
+#ifndef MCINV_MLP_WGRAD_ROWS
+#define MCINV_MLP_WGRAD_ROWS 256
+#endif
+// Row splits of the weight-gradient GEMMs: about MCINV_MLP_WGRAD_ROWS rows
+// each, at most 512.
+int32_t ks_of(int32_t R) { return std::max(1, std::min(512, R / MCINV_MLP_WGRAD_ROWS)); }
 int32_t kc_of(int32_t R)
 {
     const int32_t ks = ks_of(R);
@@ -521,7 +602,7 @@ mcinv_status ensure_step(mcinv_mlp* m, int32_t R)
     mfree(m->part);
     mfree(m->wpart);
     MHIP(m, hipMalloc((void**)&m->idx, sizeof(int64_t) * R));
-    MHIP(m, hipMalloc((void**)&m->wpart, sizeof(float) * ob2 * (size_t)ks_of(R)));
+    MHIP(m, hipMalloc((void**)&m->wpart, sizeof(float) * kWRow * (size_t)ks_of(R)));
     MHIP(m, hipMalloc((void**)&m->XT, sizeof(bf16_t) * kF * (size_t)R));
     MHIP(m, hipMalloc((void**)&m->h1T, sizeof(bf16_t) * kH * (size_t)R));
     MHIP(m, hipMalloc((void**)&m->dz2T, sizeof(bf16_t) * kH * (size_t)R));
@@ -543,17 +624,23 @@ MlpArgs base_args(mcinv_mlp* m)
     return a;
 }
 
-// One forward/backward over R rows (idx on device) and the gradient assembly;
-// with `apply`, the Adam step.
-mcinv_status run_step(mcinv_mlp* m, int32_t R, bool apply, float lr, float* loss_dev)
+// One forward/backward over R rows and the gradient assembly; with `apply`,
+// the Adam step.  The rows: drawn from Philox (key = seed, counter word 1 =
+// the step about to be taken) with `draw`, else the list in m->idx.
+mcinv_status run_step(mcinv_mlp* m, int32_t R, bool apply, float lr, float* loss_dev, bool draw = false,
+                      uint64_t seed = 0)
 {
     MlpArgs a = base_args(m);
     a.X = m->X;
     a.y = m->y;
     a.w = m->w;
     a.idx = m->idx;
+    a.draw = draw ? 1 : 0;
+    a.key0 = (uint32_t)(seed & 0xffffffffu);
+    a.key1 = (uint32_t)(seed >> 32);
+    a.step = (uint32_t)(m->t + 1);
+    a.N = m->N;
     a.R = R;
-    a.backward = 1;
     a.XT = m->XT;
     a.h1T = m->h1T;
     a.dz2T = m->dz2T;
@@ -561,10 +648,11 @@ mcinv_status run_step(mcinv_mlp* m, int32_t R, bool apply, float lr, float* loss
     a.part = m->part;
     a.inv_denom = 1.0f / (float)R;
     const int blocks = R / 64;
-    k_mlp_fwd_bwd<<<dim3(blocks), dim3(256), 0, m->stream>>>(a);
+    k_mlp_fwd_bwd<true><<<dim3(blocks), dim3(256), 0, m->stream>>>(a);
     MHIP(m, hipGetLastError());
-    const int32_t kc = kc_of(R), nks = (R + kc - 1) / kc;
-    k_mlp_wgrad<<<dim3(20, nks), dim3(256), 0, m->stream>>>(m->XT, m->dz1T, m->h1T, m->dz2T, R, kc, m->wpart);
+    const int32_t kc = kc_of(R), nks = (R + kc - 1) / kc, bc = (blocks + nks - 1) / nks;
+    k_mlp_wgrad<<<dim3(3, nks), dim3(256), 0, m->stream>>>(m->XT, m->dz1T, m->h1T, m->dz2T, R, kc, m->part, blocks,
+                                                          bc, m->wpart);
     MHIP(m, hipGetLastError());
     UpdateArgs u{};
     u.P = m->P;
@@ -573,9 +661,6 @@ mcinv_status run_step(mcinv_mlp* m, int32_t R, bool apply, float lr, float* loss
     u.grads = m->grads;
     u.wpart = m->wpart;
     u.nks = nks;
-    k_mlp_reduce_parts<<<dim3(kPart), dim3(64), 0, m->stream>>>(m->part, blocks, m->psum);
-    MHIP(m, hipGetLastError());
-    u.psum = m->psum;
     u.apply = apply ? 1 : 0;
     u.lr = lr;
     u.beta1 = 0.9f;
@@ -592,7 +677,7 @@ mcinv_status run_step(mcinv_mlp* m, int32_t R, bool apply, float lr, float* loss
     u.W2T = m->W2T;
     u.W2 = m->W2;
     u.loss_out = loss_dev;
-    k_mlp_update<<<dim3((kParams + 255) / 256), dim3(256), 0, m->stream>>>(u);
+    k_mlp_update<<<dim3((kParams + 1 + 63) / 64), dim3(64 * kUpdSlices), 0, m->stream>>>(u);
     MHIP(m, hipGetLastError());
     return MCINV_OK;
 }
@@ -611,9 +696,8 @@ mcinv_status mlp_predict_device(mcinv_mlp* m, const float* dX, int64_t N, float*
         a.idx = nullptr;
         a.row0 = r0;
         a.R = (int32_t)std::min<int64_t>(chunk, N - r0);
-        a.backward = 0;
         a.out = dout + r0;
-        k_mlp_fwd_bwd<<<dim3((unsigned)((a.R + 63) / 64)), dim3(256), 0, m->stream>>>(a);
+        k_mlp_fwd_bwd<false><<<dim3((unsigned)((a.R + 63) / 64)), dim3(256), 0, m->stream>>>(a);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
@@ -650,8 +734,7 @@ try {
         hipMalloc((void**)&m->W2, sizeof(bf16_t) * kH * kH) != hipSuccess ||
         hipMalloc((void**)&m->mean, sizeof(float) * kF) != hipSuccess ||
         hipMalloc((void**)&m->inv_std, sizeof(float) * kF) != hipSuccess ||
-        hipMalloc((void**)&m->loss, sizeof(float) * 1) != hipSuccess ||
-        hipMalloc((void**)&m->psum, sizeof(float) * kPart) != hipSuccess)
+        hipMalloc((void**)&m->loss, sizeof(float) * 1) != hipSuccess)
         return fail_alloc();
     std::vector<float> zero(kParams, 0.0f), one(kF, 1.0f);
     if (hipMemcpy(m->P, zero.data(), sizeof(float) * kParams, hipMemcpyHostToDevice) != hipSuccess ||
@@ -681,7 +764,6 @@ void mcinv_mlp_destroy(mcinv_mlp* m)
     mfree(m->mean);
     mfree(m->inv_std);
     mfree(m->loss);
-    mfree(m->psum);
     mfree(m->X);
     mfree(m->y);
     mfree(m->w);
@@ -845,10 +927,7 @@ try {
     } dloss;
     if (loss_history && steps > 0) MHIP(m, hipMalloc((void**)&dloss.p, sizeof(float) * steps));
     for (int64_t s = 0; s < steps; ++s) {
-        k_mlp_sample_rows<<<dim3((batch_rows + 255) / 256), dim3(256), 0, m->stream>>>(
-            (uint32_t)(seed & 0xffffffffu), (uint32_t)(seed >> 32), (uint32_t)(m->t + 1), m->N, batch_rows, m->idx);
-        MHIP(m, hipGetLastError());
-        const mcinv_status st = run_step(m, batch_rows, true, lr, dloss.p ? dloss.p + s : nullptr);
+        const mcinv_status st = run_step(m, batch_rows, true, lr, dloss.p ? dloss.p + s : nullptr, true, seed);
         if (st != MCINV_OK) return st;
     }
     if (dloss.p)
