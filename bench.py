@@ -72,7 +72,7 @@ def profiled_traffic(workload):
 
 
 BURN_TOL = 5e-5   # coupling tolerance of the paper's numerical tests
-ORDER_NAMES = ("natural", "XCD-contiguous", "XCD runs of 16 row blocks")
+ORDER_NAMES = ("natural", "XCD-contiguous", "XCD runs of 16 row blocks", "pair tiles fastest")
 
 
 def tuned_order(pkg, m, P, G, dtype, hermitian=False):

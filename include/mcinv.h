@@ -106,7 +106,8 @@ typedef struct {
                               next tiles start (cache residency); 0 = automatic   */
     int32_t  xcd_order;    /* sweep workgroup order: 0 natural (round-robin over the
                               8 XCDs), 1 contiguous (tile, row block) ranges per XCD,
-                              2 runs of 16 consecutive row blocks per XCD;
+                              2 runs of 16 consecutive row blocks per XCD, 3 the
+                              pair tiles of a row block one after another;
                               mcinv_tune_launch picks the fastest                 */
     int32_t  hermitian;    /* nonzero: C is hermitian with a positive diagonal
                               (checked by mcinv_load_csr, EINVAL otherwise); then
@@ -241,10 +242,10 @@ mcinv_status mcinv_burn_in_coupled(mcinv_ctx* ctx, double tol, int64_t max_sweep
                                    double* diff_z, double* diff_w);
 
 /* Time sweeps_per_trial burn-in sweeps (after one warm-up sweep) under each
- * workgroup order (mcinv_config.xcd_order 0, 1, 2) and keep the fastest.  The
- * chains advance as in mcinv_burn_in (3 + 3 sweeps_per_trial sweeps; the
+ * workgroup order (mcinv_config.xcd_order 0 .. 3) and keep the fastest.  The
+ * chains advance as in mcinv_burn_in (4 + 4 sweeps_per_trial sweeps; the
  * order never changes the arithmetic, so results do not depend on it).
- * ms_orders[3] (may be NULL): ms per sweep of each order; xcd_order may be NULL. */
+ * ms_orders[4] (may be NULL): ms per sweep of each order; xcd_order may be NULL. */
 mcinv_status mcinv_tune_launch(mcinv_ctx* ctx, int32_t sweeps_per_trial, int32_t* xcd_order, double* ms_orders);
 
 /* Noiseless sweeps from x_i = i (Algorithm 1's second start) on C x = 0 and

@@ -353,7 +353,7 @@ def mcinv_get_permutation(ctx, n):
 
 def mcinv_tune_launch(ctx, sweeps_per_trial=2):
     o = ctypes.c_int32(0)
-    ms = np.zeros(3, dtype=np.float64)
+    ms = np.zeros(4, dtype=np.float64)
     _check(ctx, lib().mcinv_tune_launch(ctx, int(sweeps_per_trial), ctypes.byref(o), _ptr(ms)))
     return o.value, ms
 

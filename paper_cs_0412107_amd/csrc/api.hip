@@ -41,6 +41,7 @@ thread_local std::string g_error;
 constexpr int64_t kSlotsSmallG = 64;     // time batches when there are < 16 groups
 constexpr int64_t kSmallLaunchRows = 4096;  // a colour launch below this many row-waves is "small"
 constexpr double kGuardThreshold = 1e30;
+constexpr int kLaunchOrders = 4;       // workgroup orders mcinv_tune_launch compares
 
 }  // namespace
 
@@ -593,7 +594,7 @@ try {
     if (cfg->moments == MCINV_MOMENTS_BF16X3 && cfg->sweep_dtype != MCINV_R32)
         return fail(nullptr, MCINV_EINVAL, "bf16x3 block moments need a real fp32 sweep");
     if (cfg->n_pairs < 1 || cfg->n_pairs > (int64_t)1 << 30) return fail(nullptr, MCINV_EINVAL, "n_pairs out of range");
-    if (cfg->xcd_order < 0 || cfg->xcd_order > 2) return fail(nullptr, MCINV_EINVAL, "xcd_order must be 0, 1 or 2");
+    if (cfg->xcd_order < 0 || cfg->xcd_order > 3) return fail(nullptr, MCINV_EINVAL, "xcd_order must be 0 .. 3");
     if (cfg->stores < 0 || cfg->stores > 2) return fail(nullptr, MCINV_EINVAL, "stores must be 0, 1 or 2");
     if (cfg->pair_offset < 0 || cfg->pair_offset % 4 != 0 || cfg->pair_offset + cfg->n_pairs > ((int64_t)1 << 34))
         return fail(nullptr, MCINV_EINVAL, "pair_offset must be a non-negative multiple of 4 (pairs below 2^34)");
@@ -859,9 +860,9 @@ try {
     hipEvent_t e0, e1;
     HIP_TRY(c, hipEventCreate(&e0));
     HIP_TRY(c, hipEventCreate(&e1));
-    double ms[3] = {0.0, 0.0, 0.0};
+    double ms[kLaunchOrders] = {};
     mcinv_status s = MCINV_OK;
-    for (int order = 0; order < 3 && s == MCINV_OK; ++order) {
+    for (int order = 0; order < kLaunchOrders && s == MCINV_OK; ++order) {
         c->cfg.xcd_order = order;
         // every sweep draws its own noise (counter = sweep index), as in burn-in
         if ((s = dispatch_sweeps(c, 1, false)) != MCINV_OK) break;
@@ -879,12 +880,12 @@ try {
     (void)hipEventDestroy(e1);
     if (s != MCINV_OK) return s;
     int best = 0;
-    for (int order = 1; order < 3; ++order)
+    for (int order = 1; order < kLaunchOrders; ++order)
         if (ms[order] < ms[best]) best = order;
     c->cfg.xcd_order = best;
     if (xcd_order) *xcd_order = best;
     if (ms_orders)
-        for (int order = 0; order < 3; ++order) ms_orders[order] = ms[order];
+        for (int order = 0; order < kLaunchOrders; ++order) ms_orders[order] = ms[order];
     return check_flag(c);
 } catch (...) {
     return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { fail(c, s_, m_); });

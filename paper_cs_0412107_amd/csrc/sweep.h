@@ -33,7 +33,7 @@ struct SweepArgs {
     int32_t* flag;           // divergence flag (bit 0)
     typename Real<V>::type thresh;
     int32_t xcd_order;       // 0: natural workgroup order; 1: contiguous tile ranges per XCD;
-                             // 2: runs of 16 consecutive row blocks per XCD
+                             // 2: runs of 16 consecutive row blocks per XCD; 3: pair tiles fastest
     int32_t nt_stores;       // nonzero: store new state rows non-temporally
 };
 

@@ -98,7 +98,15 @@ __global__ __launch_bounds__(256) void k_sweep(const SweepArgs<V> a)
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     uint32_t bx = blockIdx.x, by = blockIdx.y;
-    if (a.xcd_order == 2) {
+    if (a.xcd_order == 3) {
+        // pair tiles fastest: the tiles of one row block are dispatched one
+        // after another, so the slices of a neighbour row are fetched
+        // together (one contiguous run of the row's pairs) rather than one
+        // tile at a time across the whole launch
+        const uint32_t lin = blockIdx.x + gridDim.x * blockIdx.y;
+        by = lin % gridDim.y;
+        bx = lin / gridDim.y;
+    } else if (a.xcd_order == 2) {
         // XCD x takes runs of 16 consecutive row blocks of a tile: workgroups
         // k, k + 8, ... (one XCD) sweep neighbouring rows, whose neighbour
         // slices then share that XCD's L2 (pays off on lattice-like patterns)

@@ -277,3 +277,33 @@ def test_stop_rule_needs_long_time_batches(mats):
         z = np.concatenate(z)
         assert np.max(np.abs(z)) < 4.5
         assert 0.5 <= np.mean(z ** 2) <= 1.6
+
+
+def test_surrogate_labels_against_oracle(mats):
+    """mcinv_batch_read_labels: the surrogate's training targets c_ii (C^-1)_ii
+    and their errors |c_ii| SE_i, formed in the library from the batched
+    diagonal estimates, against the oracle's estimates of the same chains
+    (same seed, stream_id = matrix index, all 64 pairs) scaled by c_ii here."""
+    print_case(test="batch_labels")
+    sub = [mats[0], mats[4], mats[9]]
+    P, G, seed, burn, S = 64, 16, 55, 20, 40
+    with mc.BatchSampler(sub, pairs=P, groups=G, seed=seed) as b:
+        b.burn_in(burn)
+        b.request(diag=True, expected_samples=S)
+        b.sample(S)
+        for j, m in enumerate(sub):
+            y, y_se = b.labels(j)
+            ora = oracle.Run(m, seed=seed, pairs=P, groups=G, stream=j)
+            ora.burn_in(burn)
+            ora.request(S, diag=True, trace=False)
+            ora.sample(S)
+            est, se = ora.diag()
+            rows = np.repeat(np.arange(m.n), np.diff(m.row_ptr))
+            on = np.asarray(m.col) == rows
+            cii = np.zeros(m.n)
+            cii[rows[on]] = np.asarray(m.val)[on]
+            np.testing.assert_allclose(y, cii * est.real, rtol=2e-5, atol=0)
+            np.testing.assert_allclose(y_se, np.abs(cii) * se, rtol=2e-4, atol=0)
+            # and the library's own estimates, scaled: the same numbers bit for bit
+            d, dse = b.diag(j)
+            assert np.array_equal(y, cii * d) and np.array_equal(y_se, np.abs(cii) * dse)
