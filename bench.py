@@ -347,6 +347,8 @@ def lattice_form(pkg, torch, gen, steps=20, check=2):
             "nonzero_updates_per_s": 2.0 * m.nnz * P / (ms / 1e3), "ms_per_step": ms,
             "roofline": {"bound": "hbm", "achieved": B / (sweep_ms / 1e3) / 1e9, "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": B / (sweep_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                         "traffic": profiled_traffic("lattice"),
+                         "algorithmic_bytes_per_launch": B / launches, "avg_launch_ms": sweep_ms / launches,
                          "algorithmic_bytes_per_sweep": B, "sweep_kernel_ms": sweep_ms,
                          "launches_per_sweep": launches,
                          "kernel": "k_sweep<Cx<float>, true, false> (all colour launches of one sweep)"},

@@ -632,3 +632,60 @@ def test_lattice_full_size_exact():
     z = np.abs(d - dex) / se
     assert np.mean(z) < 1.5 and np.max(z) < 6.0
     assert abs(t - trex) < 5 * tse
+
+
+def test_random_phase_lattice_full_size_sampled_pairs():
+    """The random-phase 16^4 lattice in the benchmark's launch configuration
+    (complex64 sweeps, 1024 pairs in 32 groups, the workgroup order the launch
+    tuner picks): sampled pair columns against the oracle, then the trace
+    against a dense-free check (the mean of the diagonal estimates times n)."""
+    w = gen.WORKLOADS["lattice"]
+    mo = oracle_matrix(gen.lattice(w["L"], k=w["k"], seed=w["seed"]), "c64")
+    P, G, seed = w["pairs"], w["groups"], w["noise_seed"]
+    pids = np.array([0, 1, 255, 256, 1023])
+    print_case(test="lattice_random_full", n=mo.n, P=P)
+    ora = oracle.Run(mo, seed=seed, pairs=P, groups=G, pair_ids=pids)
+    with mc.Sampler(mo, pairs=P, groups=G, dtype="c64", seed=seed) as s:
+        order, _ = s.tune_launch(1)
+        k = s.info()["sweeps_done"]
+        s.burn_in(1)
+        ora.burn_in(k + 1)
+        for which, ref in ((0, ora.z), (1, ora.w)):
+            assert rel_err(s.state(which)[:, pids], ref) <= 1e-5, (order, which)
+        s.request(diag=True, trace=True)
+        s.sample(10)
+        d, _ = s.diag()
+        t, _ = s.trace()
+    # both moments are sums of the same z_i conj(w_i): the trace is the sum of the diagonal
+    np.testing.assert_allclose(np.sum(d), t, rtol=1e-10)
+
+
+def test_dirac_case2_full_size_to_paper_tolerance():
+    """The paper's second free Wilson-Dirac case (Sec. 3.2, Tables 3 and 5):
+    20^4 lattice (rank 640000), K = 0.1, complex64 sweeps, 1024 chain pairs,
+    coupled burn-in to 5e-5, sampling until the Geyer standard error of the
+    trace is below 1e-5 of its value; sampled pairs against the oracle first,
+    then the estimate within 5 errors of the closed form."""
+    from oracle import theory
+    w = gen.WORKLOADS["dirac"]
+    m = oracle_matrix(gen.dirac(20, w["K"]), "c64")
+    assert m.n == 640000 and m.nnz == 8960000
+    exact = theory.dirac_free_trace(20, w["K"])
+    P, G, seed = w["pairs"], w["groups"], w["noise_seed"]
+    pids = np.array([0, 511, 1023])
+    print_case(test="dirac20_full", n=m.n, P=P)
+    ora = oracle.Run(m, seed=seed, pairs=P, pair_ids=pids)
+    with mc.Sampler(m, pairs=P, groups=G, dtype="c64", seed=seed) as s:
+        s.burn_in(2)
+        ora.burn_in(2)
+        assert rel_err(s.state(0)[:, pids], ora.z) <= 1e-5
+        assert rel_err(s.state(1)[:, pids], ora.w) <= 1e-5
+        N, _, _ = s.burn_in_coupled(5e-5, 500)
+        assert N < 100
+        s.request(diag=False, trace=True)
+        done, ach = s.sample_until_trace(w["rel_se"], 2000, 20)
+        st = s.trace_stats()
+    assert ach <= w["rel_se"] and st["se"] <= w["rel_se"] * abs(st["mean"])
+    assert abs(st["mean"].real - exact) <= 5 * st["se"]
+    # Geyer's quantities are consistent: SE^2 = gamma_0 / N_eff
+    assert abs(st["se"] ** 2 - st["var"] / st["n_eff"]) <= 1e-9 * st["se"] ** 2
