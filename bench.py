@@ -299,7 +299,8 @@ def dirac_form(pkg, torch, gen, N):
         return {"seconds": t, "burn_in": nb, "sample_sweeps": done, "rel_se": ach,
                 "estimate": [est.real, est.imag], "se": se, "z_score": z, "within_5se": abs(z) <= 5.0,
                 "variance_series": st["var"], "effective_length_series": st["n_eff"],
-                "variance_per_pair": st["var"] * P, "effective_length_pair_sweeps": st["n_eff"] * P,
+                "variance_per_pair": st["var"] * P, "variance_per_pair_re": st["var_re"] * P,
+                "variance_per_pair_im": st["var_im"] * P, "effective_length_pair_sweeps": st["n_eff"] * P,
                 "ms_per_sweep": ms}
 
     out = {"workload": f"free Wilson-Dirac {N}^4 (n={m.n}, nnz={m.nnz}), K={w['K']}, {P} pairs, complex64",

@@ -203,10 +203,11 @@ mcinv_status mcinv_read_estimates(mcinv_ctx* ctx, uint32_t quantity, double* est
 
 /* The quantities the paper's Tables 2, 4 and 5 report for a trace (Sec. 2.3,
  * Sec. 3): Geyer's initial positive sequence on the per-sweep series x_k =
- * (1/P) sum_p t_p^(k) of MCINV_REQ_TRACE or MCINV_REQ_QTRACE.  stats[7]:
+ * (1/P) sum_p t_p^(k) of MCINV_REQ_TRACE or MCINV_REQ_QTRACE.  stats[9]:
  * mean (re, im; im 0 for a real C), gamma_0 (the series' variance, summed
  * over re and im), sigma^2 = -gamma_0 + 2 sum_m Gamma_m, the effective length
- * S gamma_0 / sigma^2, the standard error sqrt(sigma^2 / S), and S.  The
+ * S gamma_0 / sigma^2, the standard error sqrt(sigma^2 / S), S, and gamma_0
+ * of the real and of the imaginary part separately.  The
  * series averages P chain pairs, so gamma_0 P and (effective length) P are
  * the single-pair figures the tables print.  ESTATE: not requested or no
  * samples. */

@@ -300,10 +300,10 @@ def mcinv_read_estimates(ctx, quantity, count, is_complex):
 def mcinv_read_trace_stats(ctx, quantity):
     """Geyer statistics of the trace series: dict of mean, variance (gamma_0),
     sigma2, n_eff, se and samples."""
-    st = np.empty(7, dtype=np.float64)
+    st = np.empty(9, dtype=np.float64)
     _check(ctx, lib().mcinv_read_trace_stats(ctx, quantity, _ptr(st)))
     return {"mean": complex(st[0], st[1]), "var": float(st[2]), "sigma2": float(st[3]), "n_eff": float(st[4]),
-            "se": float(st[5]), "samples": int(st[6])}
+            "se": float(st[5]), "samples": int(st[6]), "var_re": float(st[7]), "var_im": float(st[8])}
 
 
 def mcinv_read_state(ctx, which, n, P, sweep_dtype):

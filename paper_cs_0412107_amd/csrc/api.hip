@@ -1026,7 +1026,7 @@ try {
     if (c->samples < 1) return fail(c, MCINV_ESTATE, "no samples yet");
     const double* series = quantity == MCINV_REQ_TRACE ? c->d_series : c->d_qseries;
     HIP_TRY(c, launch_geyer(series, c->samples, c->comps, 1.0 / (double)c->P, c->d_geyer, c->stream));
-    double g[6];
+    double g[8];
     HIP_TRY(c, hipMemcpyAsync(g, c->d_geyer, sizeof(g), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     stats[0] = g[0];                 // mean, real part
@@ -1036,6 +1036,8 @@ try {
     stats[4] = g[4];                 // effective length S gamma_0 / sigma^2
     stats[5] = g[5];                 // standard error sqrt(sigma^2 / S)
     stats[6] = (double)c->samples;   // S
+    stats[7] = g[6];                 // gamma_0 of the real part
+    stats[8] = g[7];                 // gamma_0 of the imaginary part
     return MCINV_OK;
 } catch (...) {
     return mcinv::exception_status([&](mcinv_status s_, const std::string& m_) { fail(c, s_, m_); });

@@ -644,7 +644,7 @@ __global__ __launch_bounds__(1024) void k_geyer(const double* x, int64_t S, int 
                                                 double* out)
 {
     __shared__ double lds[1024];
-    double g0_tot = 0.0, sig_tot = 0.0, mean[2] = {0.0, 0.0};
+    double g0_tot = 0.0, sig_tot = 0.0, mean[2] = {0.0, 0.0}, g0c[2] = {0.0, 0.0};
     for (int c = 0; c < comps; ++c) {
         double s = 0.0;
         for (int64_t k = threadIdx.x; k < S; k += 1024) s += x[k * comps + c] * scale;
@@ -664,6 +664,7 @@ __global__ __launch_bounds__(1024) void k_geyer(const double* x, int64_t S, int 
             sig2 += 2.0 * pair_sum;
         }
         if (!(sig2 > 0.0)) sig2 = g0;
+        g0c[c] = g0;
         g0_tot += g0;
         sig_tot += sig2;
     }
@@ -674,6 +675,8 @@ __global__ __launch_bounds__(1024) void k_geyer(const double* x, int64_t S, int 
         out[3] = sig_tot;
         out[4] = sig_tot > 0.0 ? (double)S * g0_tot / sig_tot : __builtin_nan("");
         out[5] = S >= 2 ? sqrt(sig_tot / (double)S) : __builtin_nan("");
+        out[6] = g0c[0];   // gamma_0 of the real part
+        out[7] = g0c[1];   // and of the imaginary part (0 for a real series)
     }
 }
 

@@ -687,5 +687,6 @@ def test_dirac_case2_full_size_to_paper_tolerance():
         st = s.trace_stats()
     assert ach <= w["rel_se"] and st["se"] <= w["rel_se"] * abs(st["mean"])
     assert abs(st["mean"].real - exact) <= 5 * st["se"]
-    # Geyer's quantities are consistent: SE^2 = gamma_0 / N_eff
+    # Geyer's quantities are consistent: SE^2 = gamma_0 / N_eff, gamma_0 = re + im parts
     assert abs(st["se"] ** 2 - st["var"] / st["n_eff"]) <= 1e-9 * st["se"] ** 2
+    assert abs(st["var_re"] + st["var_im"] - st["var"]) <= 1e-12 * st["var"]
