@@ -4,19 +4,19 @@
 // (C^-1)_ii from the 32 local features of row i.
 //
 // Kernels
-//   k_mlp_fwd_bwd : one wave = 16 rows.  Layer 1 and 2 products on
-//                   v_mfma_f32_16x16x32_bf16 (A = activations, B = weights
-//                   from global), GELU in fp32, output layer in fp32.  The
-//                   training instance (BWD): the weighted-MSE gradient flows back through
-//                   layer 3 (fp32), layer 2 (dgrad on MFMA) and both GELUs;
-//                   activations and deltas go out transposed as bf16 for the
-//                   weight gradients, bias / w3 partial sums per workgroup.
-//   k_mlp_wgrad   : dW1 = X^T dz1, dW2 = h1^T dz2 over the step's rows
-//                   (the whole 128 x 128 or 32 x 128 output per workgroup,
-//                   one sub-tile per wave, the rows split over workgroups).
-//   k_mlp_update  : gradient assembly (every partial summed in a fixed
+//   k_mlp_train   : one training step's gradient, fused: a persistent
+//                   workgroup per compute unit (eight waves, 16 rows each per
+//                   128-row tile) runs the forward layers, the weighted-MSE
+//                   gradient back through layer 3 (fp32), layer 2 (dgrad) and
+//                   both GELUs, and accumulates dW1 = Xn^T dz1 and dW2 =
+//                   h1^T dz2 over its tiles in registers (the tiles' operands
+//                   pass through LDS); bias, w3, b3 and loss sums per wave.
+//                   Products on v_mfma_f32_16x16x32_bf16 (bf16 operands, fp32
+//                   accumulation); the step's rows are drawn from Philox
+//                   inside the kernel.  One partial row per workgroup.
+//   k_mlp_forward : predictions, one 128-row tile per workgroup.
+//   k_mlp_update  : gradient assembly (the partial rows summed in a fixed
 //                   order), Adam step, bf16 copies of the weights.
-// Training draws each step's rows from Philox inside k_mlp_fwd_bwd.
 // Rounding points (what the oracle reproduces): the normalised features,
 // W1, W2, h1 and dz2 enter MFMA products as bf16 (nearest even); h2, w3, the
 // biases and every elementwise step stay fp32.
@@ -41,7 +41,6 @@ constexpr int kF = 32, kH = 128;
 constexpr int oW1 = 0, ob1 = kF * kH, oW2 = ob1 + kH, ob2 = oW2 + kH * kH, ow3 = ob2 + kH, ob3 = ow3 + kH;
 constexpr int kParams = ob3 + 1;     // 20865
 constexpr int kPart = 3 * kH + 2;    // db1, db2, dw3, db3, loss
-constexpr int kActLd = kH + 8;       // LDS row pitch (bf16) of one wave's activations
 constexpr int kWRow = ob2 + kPart;   // one weight-gradient partial row: W1 | b1 gap | W2 | block sums
 
 typedef unsigned short bf16_t;
@@ -72,33 +71,9 @@ struct MlpArgs {
     const bf16_t* W2;        // [128 in][128 out]
     const float* P;          // fp32 master parameters (biases, w3 read here)
     float* out;              // predictions [R]
-    bf16_t* XT;              // [32][R]
-    bf16_t* h1T;             // [128][R]
-    bf16_t* dz2T;            // [128][R]
-    bf16_t* dz1T;            // [128][R]
-    float* part;             // [blocks][kPart]
+    float* wpart;            // training: one partial row [kWRow] per workgroup
     float inv_denom;         // loss = sum_r w_r (out_r - y_r)^2 * inv_denom
 };
-
-// Write a wave's 16 rows x ncols block (bf16, row-major in LDS) to the
-// transposed buffer dst[col][R] at rows r0w..r0w+15: lane l takes columns
-// l, l + 64, ... and stores each column's 16 values as one 32-byte segment
-// (r0w is a multiple of 16 and R a multiple of 64, so segments are aligned).
-__device__ inline void store_transposed(const bf16_t (*src)[kActLd], int ncols, bf16_t* dst, int64_t R, int64_t r0w,
-                                        int lane)
-{
-    for (int c = lane; c < ncols; c += 64) {
-        u16x8 lo, hi;
-#pragma unroll
-        for (int r = 0; r < 8; ++r) {
-            lo[r] = src[r][c];
-            hi[r] = src[8 + r][c];
-        }
-        uint4* d = reinterpret_cast<uint4*>(dst + (int64_t)c * R + r0w);
-        d[0] = __builtin_bit_cast(uint4, lo);
-        d[1] = __builtin_bit_cast(uint4, hi);
-    }
-}
 
 // GELU (erf form) and its derivative at z: h = z Phi(z) and gp = Phi(z) +
 // z phi(z), with Phi(z) = (1 + erf(z / sqrt 2)) / 2 and phi(z) = exp(-z^2 / 2)
@@ -106,30 +81,24 @@ __device__ inline void store_transposed(const bf16_t (*src)[kActLd], int ncols, 
 template <bool GP>
 __device__ inline void gelu_terms(float z, float& h, float& gp)
 {
+    // GELU(z) = z Phi(z) with 2 Phi(z) = 1 + erf(z / sqrt 2), and
+    // GELU'(z) = Phi(z) + z phi(z).  erfc(|x|) = (a1 t + ... + a5 t^5) e^{-x^2},
+    // t = 1 / (1 + p |x|): Abramowitz & Stegun 7.1.26 (absolute error of erf
+    // at most 1.5e-7).  With x = z / sqrt 2, e^{-x^2} = e^{-z^2/2} also gives
+    // phi, so one hardware exp2 and one reciprocal serve both terms; for z < 0
+    // the small tail Phi(z) = erfc(|x|) / 2 is formed without cancellation.
     constexpr float kRs2 = 0.70710678118654752f, kRs2pi = 0.39894228040143268f;
-    const float e = erff(z * kRs2);
-    h = 0.5f * z * (1.0f + e);
-    gp = GP ? 0.5f * (1.0f + e) + z * expf(-0.5f * z * z) * kRs2pi : 0.0f;
-}
-
-// The four rows 4kg .. 4kg+3 of column c that a lane holds in an MFMA result
-// (bf16) into the transposed buffer dst[c][R] at rows r0w + 4kg .. (8 bytes;
-// r0w is a multiple of 16, so the store is aligned).
-__device__ inline void store_col4(bf16_t* dst, int64_t R, int64_t r0w, int c, int kg, const bf16_t v[4])
-{
-    uint2 w;
-    w.x = (uint32_t)v[0] | ((uint32_t)v[1] << 16);
-    w.y = (uint32_t)v[2] | ((uint32_t)v[3] << 16);
-    *reinterpret_cast<uint2*>(dst + (int64_t)c * R + r0w + 4 * kg) = w;
-}
-
-// Orders a wave's own LDS accesses (each wave works in its private slice of
-// the workgroup's LDS, so no workgroup barrier is needed between its phases).
-__device__ inline void wave_lds_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    constexpr float kHalfLog2e = 0.72134752044448170f;   // log2(e) / 2
+    // the coefficients halved (exact), so that the product is Phi's tail
+    constexpr float kP = 0.3275911f, kA1 = 0.5f * 0.254829592f, kA2 = 0.5f * -0.284496736f,
+                    kA3 = 0.5f * 1.421413741f, kA4 = 0.5f * -1.453152027f, kA5 = 0.5f * 1.061405429f;
+    const float t = __builtin_amdgcn_rcpf(fmaf(kP * kRs2, fabsf(z), 1.0f));
+    const float poly = t * fmaf(t, fmaf(t, fmaf(t, fmaf(t, kA5, kA4), kA3), kA2), kA1);
+    const float g = __builtin_amdgcn_exp2f(-kHalfLog2e * z * z);   // e^{-z^2/2}
+    const float q = poly * g;                                      // erfc(|z| / sqrt 2) / 2
+    const float cdf = z < 0.0f ? q : 1.0f - q;                     // Phi(z)
+    h = z * cdf;
+    gp = GP ? fmaf(z * kRs2pi, g, cdf) : 0.0f;
 }
 
 // Row of the training data for step row r: the caller's list, a contiguous
@@ -146,275 +115,425 @@ __device__ inline int64_t mlp_row(const MlpArgs& a, int64_t r)
     return a.idx ? a.idx[r] : a.row0 + r;
 }
 
-#ifndef MCINV_MLP_MIN_BLOCKS
-#define MCINV_MLP_MIN_BLOCKS 2   // workgroups per CU the register budget is sized for
-#endif
-template <bool BWD>
-__global__ __launch_bounds__(256, MCINV_MLP_MIN_BLOCKS) void k_mlp_fwd_bwd(const MlpArgs a)
+// Shared pieces of the forward and training kernels.
+//
+// Every product is taken transposed (hidden units on the M side of
+// v_mfma_f32_16x16x32_bf16, a wave's 16 rows on N), so a product's result
+// fragment -- lane (row r, group g) holding units 16t + 4g + v of row r -- is
+// the next product's B operand as it stands: in the K step of 32 units
+// covering tiles 2c and 2c + 1, lane group g holds units 32c + 4g .. 4g + 3
+// and 32c + 16 + 4g .. + 3.  The weight rows in LDS carry their K units in
+// that order (the 4-unit block b of a K step at position frag_block(b)).
+//
+// LDS arrays of 128 bf16 per row keep 16-byte chunk c of row r at chunk
+// c ^ (r & 15), so that the 16 rows one fragment access touches fall in
+// different banks; W1^T (32 per row) keeps chunk c at c ^ ((r >> 2) & 3).
+constexpr int kMlpWaves = 8;
+constexpr int kMlpRows = 16 * kMlpWaves;   // rows per tile (one workgroup)
+// small vectors in LDS: feature mean and 1/std, b1, b2, w3, b3
+constexpr int pMean = 0, pInv = kF, pB1 = 2 * kF, pB2 = pB1 + kH, pW3 = pB2 + kH, pB3 = pW3 + kH;
+constexpr int kPb = pB3 + 1;
+constexpr int kPartLd = (kPart + 3) / 4 * 4;
+
+__device__ inline int frag_block(int b) { return b < 4 ? 2 * b : 2 * (b - 4) + 1; }
+
+template <typename T>
+__device__ inline T* sw128(T* base, int r, int col)
 {
-    // act (wave-private): the normalised features (written out transposed
-    // for the weight gradients), then h1 (bf16) as layer 2's A operand, then
-    // dz2 (bf16) as the dgrad A operand.  h1, dz2 and dz1 also go straight
-    // from the MFMA result layout to their transposed buffers.  gelu'(z1)
-    // and layer 2's GELU values stay in registers for the backward pass.
-    __shared__ __align__(16) bf16_t act[4][16][kActLd];
-    __shared__ float part[4][kPart];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    return base + r * kH + ((((col >> 3) ^ (r & 15)) << 3) | (col & 7));
+}
+template <typename T>
+__device__ inline T* sw32(T* base, int r, int col)
+{
+    return base + r * kF + ((((col >> 3) ^ ((r >> 2) & 3)) << 3) | (col & 7));
+}
+
+__device__ inline bf16x8 lds_bf16x8(const bf16_t* p)
+{
+    return __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(p));
+}
+
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
+
+// two values to bf16 (nearest even) in one register, lo first
+__device__ inline uint32_t pack_bf16(float lo, float hi)
+{
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((f32x2_t{lo, hi}), bf16x2_t));
+}
+
+template <int CTRL>
+__device__ inline uint32_t dpp_u32(uint32_t x)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xF, 0xF, true);
+}
+
+template <int CTRL>
+__device__ inline float dpp_f32(float x)
+{
+    return __builtin_bit_cast(float, dpp_u32<CTRL>(__builtin_bit_cast(uint32_t, x)));
+}
+
+// Sums over the 16 lanes of a row of four values x[0..3] at once: lane b of
+// each quad (b = lane & 3) gets the total of x[b].  Within the quad each lane
+// hands two values to lane b ^ 2 and keeps the pair sums of x[2 (b >> 1)],
+// x[2 (b >> 1) + 1], then one to lane b ^ 1; the quads' sums are then added
+// across the row (row_ror 8, then row_ror 4, so that every lane of the row
+// with the same b ends with the same bits: both steps pair commutatively).
+__device__ inline float row16_sum4(float x0, float x1, float x2, float x3, int b)
+{
+    const bool hi = (b & 2) != 0, odd = (b & 1) != 0;
+    const float y0 = (hi ? x2 : x0) + dpp_f32<0x4E>(hi ? x0 : x2);   // quad_perm [2, 3, 0, 1]
+    const float y1 = (hi ? x3 : x1) + dpp_f32<0x4E>(hi ? x1 : x3);
+    const float z = (odd ? y1 : y0) + dpp_f32<0xB1>(odd ? y0 : y1);   // quad_perm [1, 0, 3, 2]
+    const float t = z + dpp_f32<0x128>(z);                            // row_ror 8
+    return t + dpp_f32<0x124>(t);                                     // row_ror 4
+}
+
+// 4 x 4 transpose within a quad of lanes: lane b holds, for its row, units
+// 0..3 as bf16 pairs (p01, p23); afterwards it holds unit b of the quad's rows
+// 0..3 as (q01, q23).  The pairs first cross between lanes b and b ^ 2 (two
+// units of two rows each), then single values between b and b ^ 1.
+__device__ inline void quad_transpose(uint32_t p01, uint32_t p23, int b, uint32_t& q01, uint32_t& q23)
+{
+    const bool hi = (b & 2) != 0;
+    const uint32_t y = dpp_u32<0x4E>(hi ? p01 : p23);
+    const uint32_t A = hi ? y : p01, B = hi ? p23 : y;
+    const uint32_t Ap = dpp_u32<0xB1>(A), Bp = dpp_u32<0xB1>(B);
+    const uint32_t sel = (b & 1) ? 0x03020706u : 0x05040100u;
+    q01 = __builtin_amdgcn_perm(Ap, A, sel);
+    q23 = __builtin_amdgcn_perm(Bp, B, sel);
+}
+
+// The lane's four units (bf16 pairs p) of its row into a swizzled [unit][128
+// rows] LDS array: after the quad transpose, unit urow (the caller's unit of
+// quad lane b) of rows rcol .. rcol + 3 as one 8-byte write.
+__device__ inline void put_transposed(bf16_t* base, int urow, int rcol, uint32_t p01, uint32_t p23, int b)
+{
+    uint32_t q01, q23;
+    quad_transpose(p01, p23, b, q01, q23);
+    *reinterpret_cast<uint2*>(sw128(base, urow, rcol)) = make_uint2(q01, q23);
+}
+
+// W1^T, W2^T (forward) and, for training, W2 (dgrad) from their global bf16
+// copies into LDS (swizzled, K units in fragment order), with the small
+// vectors.
+template <bool TRAIN>
+__device__ inline void stage_weights(const MlpArgs& a, bf16_t* w1t, bf16_t* w2p, bf16_t* w2q, float* pb)
+{
+    for (int t = threadIdx.x; t < kH * (kF / 8); t += blockDim.x) {
+        const int r = t >> 2, c = t & 3;
+        *reinterpret_cast<uint4*>(sw32(w1t, r, 8 * c)) = *reinterpret_cast<const uint4*>(a.W1T + r * kF + 8 * c);
+    }
+    for (int t = threadIdx.x; t < kH * (kH / 8); t += blockDim.x) {
+        const int r = t >> 4, c8 = t & 15;
+        const int col0 = 32 * (c8 >> 2), b = 2 * (c8 & 3);
+        const uint4 g = *reinterpret_cast<const uint4*>(a.W2T + r * kH + 8 * c8);
+        *reinterpret_cast<uint2*>(sw128(w2p, r, col0 + 4 * frag_block(b))) = make_uint2(g.x, g.y);
+        *reinterpret_cast<uint2*>(sw128(w2p, r, col0 + 4 * frag_block(b + 1))) = make_uint2(g.z, g.w);
+        if (TRAIN) {
+            const uint4 h = *reinterpret_cast<const uint4*>(a.W2 + r * kH + 8 * c8);
+            *reinterpret_cast<uint2*>(sw128(w2q, r, col0 + 4 * frag_block(b))) = make_uint2(h.x, h.y);
+            *reinterpret_cast<uint2*>(sw128(w2q, r, col0 + 4 * frag_block(b + 1))) = make_uint2(h.z, h.w);
+        }
+    }
+    for (int t = threadIdx.x; t < kPb; t += blockDim.x) {
+        float v;
+        if (t < pInv)
+            v = a.mean[t - pMean];
+        else if (t < pB1)
+            v = a.inv_std[t - pInv];
+        else if (t < pB2)
+            v = a.P[ob1 + t - pB1];
+        else if (t < pW3)
+            v = a.P[ob2 + t - pB2];
+        else if (t < pB3)
+            v = a.P[ow3 + t - pW3];
+        else
+            v = a.P[ob3];
+        pb[t] = v;
+    }
+}
+
+// One data row of the call: the lane's eight features (group kg), label and
+// weight.  The loads do not depend on whether the row exists (a row past the
+// end loads row R - 1 of the call and is flagged), so that nothing waits for
+// them before their first use.
+struct RowIn {
+    float4 x0, x1;
+    float y, w;
+    bool ok;
+};
+
+template <bool TRAIN>
+__device__ inline RowIn fetch_row(const MlpArgs& a, int64_t rr, int kg)
+{
+    RowIn d;
+    d.ok = rr < a.R;
+    const int64_t row = mlp_row(a, d.ok ? rr : a.R - 1);
+    const float4* x = reinterpret_cast<const float4*>(a.X + row * kF + 8 * kg);
+    d.x0 = x[0];
+    d.x1 = x[1];
+    d.y = TRAIN ? a.y[row] : 0.f;
+    d.w = TRAIN ? a.w[row] : 0.f;
+    return d;
+}
+
+// (x - mean) / std of features 8kg .. 8kg + 7 as bf16 pairs
+__device__ inline void normalise(const RowIn& in, const float* pb, int kg, uint32_t xp[4])
+{
+    const float xf[8] = {in.x0.x, in.x0.y, in.x0.z, in.x0.w, in.x1.x, in.x1.y, in.x1.z, in.x1.w};
+    const float4 m0 = *reinterpret_cast<const float4*>(pb + pMean + 8 * kg);
+    const float4 m1 = *reinterpret_cast<const float4*>(pb + pMean + 8 * kg + 4);
+    const float4 s0 = *reinterpret_cast<const float4*>(pb + pInv + 8 * kg);
+    const float4 s1 = *reinterpret_cast<const float4*>(pb + pInv + 8 * kg + 4);
+    const float mf[8] = {m0.x, m0.y, m0.z, m0.w, m1.x, m1.y, m1.z, m1.w};
+    const float sf[8] = {s0.x, s0.y, s0.z, s0.w, s1.x, s1.y, s1.z, s1.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+        xp[j] = pack_bf16((xf[2 * j] - mf[2 * j]) * sf[2 * j], (xf[2 * j + 1] - mf[2 * j + 1]) * sf[2 * j + 1]);
+}
+
+// Layer 1, units 16t + 4kg + v of the lane's row: h1 (bf16 pairs) and, for
+// training, gelu'(z1).
+template <bool GP>
+__device__ inline void layer1_tile(const bf16_t* w1t, const float* pb, bf16x8 xb, int t, int i16, int kg,
+                                   uint32_t hp[2], float gp[4])
+{
+    const f32x4 z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lds_bf16x8(sw32(w1t, 16 * t + i16, 8 * kg)), xb,
+                                                           f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+    const float4 b = *reinterpret_cast<const float4*>(pb + pB1 + 16 * t + 4 * kg);
+    const float bias[4] = {b.x, b.y, b.z, b.w};
+    float h[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) gelu_terms<GP>(z[v] + bias[v], h[v], gp[v]);
+    hp[0] = pack_bf16(h[0], h[1]);
+    hp[1] = pack_bf16(h[2], h[3]);
+}
+
+// sum over K of W[16n + i16][K] x act[K] for the lane's row: W in LDS
+// (swizzled, fragment order), act = the previous product's bf16 pairs by tile
+__device__ inline f32x4 hidden_product(const bf16_t* w, const uint32_t (*ap)[2], int n, int i16, int kg)
+{
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const uint4 bq = make_uint4(ap[2 * c][0], ap[2 * c][1], ap[2 * c + 1][0], ap[2 * c + 1][1]);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lds_bf16x8(sw128(w, 16 * n + i16, 32 * c + 8 * kg)),
+                                                      __builtin_bit_cast(bf16x8, bq), acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// ---------------------------------------------------------------------------
+// Forward only: one 128-row tile per workgroup.
+struct FwdLds {
+    bf16_t w1t[kH * kF];
+    bf16_t w2p[kH * kH];
+    float pb[kPb];
+};
+
+__global__ __launch_bounds__(64 * kMlpWaves) void k_mlp_forward(const MlpArgs a)
+{
+    __shared__ __align__(16) FwdLds L;
+    const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int i16 = lane & 15, kg = lane >> 4;
-    const int64_t r0w = (int64_t)blockIdx.x * 64 + wid * 16;
-    const float* P = a.P;
+    const int64_t rr = (int64_t)blockIdx.x * kMlpRows + 16 * wid + i16;
+    const RowIn in = fetch_row<false>(a, rr, kg);
+    stage_weights<false>(a, L.w1t, L.w2p, nullptr, L.pb);
+    __syncthreads();
 
-    // ---- layer 1: A = normalised features (row i16, features 8kg..8kg+7)
-    const int64_t ra = r0w + i16;
-    const bool aok = ra < a.R;
-    const int64_t rowa = aok ? mlp_row(a, ra) : 0;
-    bf16x8 a1;
-    {
-        u16x8 u;
-        const float* x = a.X + rowa * kF + 8 * kg;
+    uint32_t xp[4];
+    normalise(in, L.pb, kg, xp);
+    const bf16x8 xb = __builtin_bit_cast(bf16x8, make_uint4(xp[0], xp[1], xp[2], xp[3]));
+    uint32_t h1p[8][2];
+    float unused[4];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const float xn = aok ? (x[e] - a.mean[8 * kg + e]) * a.inv_std[8 * kg + e] : 0.0f;
-            u[e] = to_bf16(xn);
-            if (BWD) act[wid][i16][8 * kg + e] = u[e];
-        }
-        a1 = __builtin_bit_cast(bf16x8, u);
-    }
-    if (BWD) {   // backward launches cover whole 64-row blocks
-        wave_lds_sync();
-        store_transposed(act[wid], kF, a.XT, a.R, r0w, lane);
-        wave_lds_sync();
-    }
-    // z1 -> h1 = GELU(z1) into LDS (bf16) and h1^T; gelu'(z1) kept in registers
-    float gp1[8][4];
+    for (int t = 0; t < 8; ++t) layer1_tile<false>(L.w1t, L.pb, xb, t, i16, kg, h1p[t], unused);
+    float outp = 0.f;
 #pragma unroll
     for (int n = 0; n < 8; ++n) {
-        const bf16x8 b = load_bf16x8(a.W1T + (16 * n + i16) * kF + 8 * kg);
-        const f32x4 z = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-        const float bias = P[ob1 + 16 * n + i16];
-        bf16_t hb[4];
+        const f32x4 acc = hidden_product(L.w2p, h1p, n, i16, kg);
+        const float4 b2 = *reinterpret_cast<const float4*>(L.pb + pB2 + 16 * n + 4 * kg);
+        const float4 w3 = *reinterpret_cast<const float4*>(L.pb + pW3 + 16 * n + 4 * kg);
+        const float bias[4] = {b2.x, b2.y, b2.z, b2.w}, w3v[4] = {w3.x, w3.y, w3.z, w3.w};
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            float hv, gv;
-            gelu_terms<BWD>(z[v] + bias, hv, gv);
-            hb[v] = to_bf16(hv);
-            act[wid][4 * kg + v][16 * n + i16] = hb[v];
-            gp1[n][v] = gv;
+            float h, g;
+            gelu_terms<false>(acc[v] + bias[v], h, g);
+            outp += h * w3v[v];
         }
-        if (BWD) store_col4(a.h1T, a.R, r0w, 16 * n + i16, kg, hb);
-        __builtin_amdgcn_sched_barrier(0);
     }
-    wave_lds_sync();
+    outp += __shfl_xor(outp, 16);
+    outp += __shfl_xor(outp, 32);
+    if (kg == 0 && rr < a.R) a.out[rr] = outp + L.pb[pB3];
+}
 
-    // ---- layer 2, and layer 3 (fp32) on the fly: out_v for rows r0w + 4kg + v
-    float h2[8][4], gp2[8][4];
-    float out[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int n = 0; n < 8; ++n) {
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const bf16x8 av = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&act[wid][i16][32 * s + 8 * kg]));
-            const bf16x8 b = load_bf16x8(a.W2T + (16 * n + i16) * kH + 32 * s + 8 * kg);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b, acc, 0, 0, 0);
-        }
-        const float bias = P[ob2 + 16 * n + i16];
-        const float w3 = P[ow3 + 16 * n + i16];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            gelu_terms<BWD>(acc[v] + bias, h2[n][v], gp2[n][v]);
-            out[v] += h2[n][v] * w3;
-        }
-        __builtin_amdgcn_sched_barrier(0);
-    }
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        for (int off = 1; off < 16; off <<= 1) out[v] += __shfl_xor(out[v], off);
-        out[v] += P[ob3];
-    }
-    if (!BWD) {
-        if (i16 == 0)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int64_t rd = r0w + 4 * kg + v;
-                if (rd < a.R) a.out[rd] = out[v];
-            }
-        return;
-    }
+// ---------------------------------------------------------------------------
+// One training step's gradient: forward, backward and weight gradients fused.
+//
+// One workgroup per compute unit loops over the step's 128-row tiles (wave w:
+// rows 16w .. 16w + 15).  Per tile: the forward layers, the loss gradient,
+// layer 3 backward and the layer-2 dgrad in registers (as in the forward
+// kernel); the tile's Xn, h1, dz2 and then dz1 go to LDS transposed ([unit]
+// [row], bf16), where the weight-gradient products take them with the rows
+// as K: wave w adds dW2[:, 16w .. 16w + 15] = h1^T dz2 and
+// dW1[:, 16w .. 16w + 15] = Xn^T dz1 to accumulators that stay in registers
+// over all its tiles.  Bias, w3, b3 and loss sums: per wave in LDS (fp32, 16
+// rows at a time).  The next tile's rows are requested while the current one
+// is computed.  At the end the workgroup writes one partial row (dW1 | dW2 |
+// sums) for the update kernel.
+struct TrainLds {
+    bf16_t w1t[kH * kF];
+    bf16_t w2p[kH * kH];
+    bf16_t w2q[kH * kH];
+    bf16_t hT[kH * kMlpRows];   // h1^T of the tile, then dz1^T
+    bf16_t dT[kH * kMlpRows];   // dz2^T
+    bf16_t xT[kF * kMlpRows];   // Xn^T
+    float pb[kPb];
+    float part[kMlpWaves][kPartLd];
+};
 
-    // ---- loss gradient (the rows 4kg + v of this lane's group: their data
-    // rows come from the lanes i16 = 4kg + v that loaded them)
-    float dout[4], lossp = 0.f, db3 = 0.f;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        const int64_t rd = r0w + 4 * kg + v;
-        const int64_t row = __shfl(rowa, 4 * kg + v);
-        float dv = 0.f;
-        if (rd < a.R) {
-            const float diff = out[v] - a.y[row];
-            dv = 2.0f * a.w[row] * diff * a.inv_denom;
-            lossp += a.w[row] * diff * diff * a.inv_denom;
-        }
-        dout[v] = dv;
-        db3 += dv;
-    }
+__global__ __launch_bounds__(64 * kMlpWaves) void k_mlp_train(const MlpArgs a)
+{
+    __shared__ __align__(16) TrainLds L;
+    const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int i16 = lane & 15, kg = lane >> 4, qa = i16 >> 2, qb = i16 & 3;
+    const int r0 = 16 * wid;   // the wave's first row in a tile
+    const int ntiles = (a.R + kMlpRows - 1) / kMlpRows;
+    RowIn cur = fetch_row<true>(a, (int64_t)blockIdx.x * kMlpRows + r0 + i16, kg);
+    for (int k = lane; k < kPartLd; k += 64) L.part[wid][k] = 0.f;
+    stage_weights<true>(a, L.w1t, L.w2p, L.w2q, L.pb);
+    __syncthreads();
+    float* part = L.part[wid];
 
-    // ---- layer 3 backward and layer 2 deltas, written to LDS (bf16); every
-    // lane has finished reading h1 (wave order)
-    float dw3p[8], db2p[8];
-    wave_lds_sync();
+    f32x4 acc2[8], acc1[2];
 #pragma unroll
-    for (int n = 0; n < 8; ++n) {
-        const float w3 = P[ow3 + 16 * n + i16];
-        float s3 = 0.f, s2 = 0.f;
-        bf16_t db[4];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            s3 += h2[n][v] * dout[v];
-            const float d = dout[v] * w3 * gp2[n][v];
-            s2 += d;
-            db[v] = to_bf16(d);
-            act[wid][4 * kg + v][16 * n + i16] = db[v];
-        }
-        store_col4(a.dz2T, a.R, r0w, 16 * n + i16, kg, db);
-        dw3p[n] = s3;
-        db2p[n] = s2;
-    }
-    wave_lds_sync();
+    for (int i = 0; i < 8; ++i) acc2[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+    acc1[0] = acc1[1] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    // ---- dgrad of layer 2: dh1 = dz2 W2^T, then through GELU
-    float db1p[8];
-#pragma unroll
-    for (int n = 0; n < 8; ++n) {
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const bf16x8 av = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&act[wid][i16][32 * s + 8 * kg]));
-            const bf16x8 b = load_bf16x8(a.W2 + (16 * n + i16) * kH + 32 * s + 8 * kg);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, b, acc, 0, 0, 0);
-        }
-        float s1 = 0.f;
-        bf16_t db[4];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const float d = acc[v] * gp1[n][v];
-            s1 += d;
-            db[v] = to_bf16(d);
-        }
-        store_col4(a.dz1T, a.R, r0w, 16 * n + i16, kg, db);
-        db1p[n] = s1;
-        __builtin_amdgcn_sched_barrier(0);
-    }
+    for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        // ---- normalised features (layer 1's B operand; Xn^T to LDS)
+        uint32_t xp[4];
+        normalise(cur, L.pb, kg, xp);
+        put_transposed(L.xT, 8 * kg + qb, r0 + 4 * qa, xp[0], xp[1], qb);
+        put_transposed(L.xT, 8 * kg + 4 + qb, r0 + 4 * qa, xp[2], xp[3], qb);
+        // a row past the end has weight 0: no loss and no gradient
+        const float yv = cur.y, wv = cur.ok ? cur.w : 0.f;
+        if (tile + (int)gridDim.x < ntiles)
+            cur = fetch_row<true>(a, (int64_t)(tile + gridDim.x) * kMlpRows + r0 + i16, kg);
+        const bf16x8 xb = __builtin_bit_cast(bf16x8, make_uint4(xp[0], xp[1], xp[2], xp[3]));
 
-    // ---- per-wave sums over its 16 rows (the 4 row groups kg), then per block
+        // ---- layer 1 (h1^T to LDS)
+        uint32_t h1p[8][2];
+        float gp1[8][4];
 #pragma unroll
-    for (int n = 0; n < 8; ++n) {
-        for (int off = 16; off < 64; off <<= 1) {
-            dw3p[n] += __shfl_xor(dw3p[n], off);
-            db2p[n] += __shfl_xor(db2p[n], off);
-            db1p[n] += __shfl_xor(db1p[n], off);
+        for (int t = 0; t < 8; ++t) {
+            layer1_tile<true>(L.w1t, L.pb, xb, t, i16, kg, h1p[t], gp1[t]);
+            put_transposed(L.hT, 16 * t + 4 * kg + qb, r0 + 4 * qa, h1p[t][0], h1p[t][1], qb);
         }
-    }
-    // db3 and the loss are per row group (lanes of one kg hold identical values)
-    for (int off = 16; off < 64; off <<= 1) {
-        db3 += __shfl_xor(db3, off);
-        lossp += __shfl_xor(lossp, off);
-    }
-    if (kg == 0) {
+
+        // ---- layer 2 and the output (fp32)
+        float h2[8][4], gp2[8][4];
+        float outp = 0.f;
 #pragma unroll
         for (int n = 0; n < 8; ++n) {
-            part[wid][16 * n + i16] = db1p[n];
-            part[wid][kH + 16 * n + i16] = db2p[n];
-            part[wid][2 * kH + 16 * n + i16] = dw3p[n];
+            const f32x4 acc = hidden_product(L.w2p, h1p, n, i16, kg);
+            const float4 b2 = *reinterpret_cast<const float4*>(L.pb + pB2 + 16 * n + 4 * kg);
+            const float4 w3 = *reinterpret_cast<const float4*>(L.pb + pW3 + 16 * n + 4 * kg);
+            const float bias[4] = {b2.x, b2.y, b2.z, b2.w}, w3v[4] = {w3.x, w3.y, w3.z, w3.w};
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                gelu_terms<true>(acc[v] + bias[v], h2[n][v], gp2[n][v]);
+                outp += h2[n][v] * w3v[v];
+            }
         }
-        if (i16 == 0) {
-            part[wid][3 * kH] = db3;
-            part[wid][3 * kH + 1] = lossp;
-        }
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < kPart; k += 256)
-        a.part[(int64_t)blockIdx.x * kPart + k] = ((part[0][k] + part[1][k]) + part[2][k]) + part[3][k];
-}
+        outp += __shfl_xor(outp, 16);
+        outp += __shfl_xor(outp, 32);
+        const float diff = outp + L.pb[pB3] - yv;
+        const float dout = 2.0f * wv * diff * a.inv_denom;
+        const float lossp = wv * diff * diff * a.inv_denom;
 
-// dW (M x 128) = L Rt^T over a chunk of the step's K rows: L is [M][K], Rt
-// is [128][K] (bf16, the transposed activations / deltas).  blockIdx.x = 0:
-// dW2 (M = 128: L = h1^T, Rt = dz2^T), 1: dW1 (M = 32: L = X^T, Rt = dz1^T);
-// blockIdx.y = ks covers rows [ks Kc, (ks + 1) Kc).  Each wave owns one
-// output sub-tile (dW2: 64 x 64, waves in a 2 x 2 grid; dW1: 32 x 32, waves
-// side by side) over the whole chunk, so every L and Rt element of the chunk
-// is read once per workgroup; the partial tile goes to wpart[ks][W1 | b1
-// gap | W2] and the update kernel sums the ks partials in a fixed order.
-template <int TI, int TJ>
-__device__ inline void wgrad_tile(const bf16_t* L, const bf16_t* Rt, int64_t K, int kb0, int kb1, int r0, int c0,
-                                  float* out, int lane)
-{
-    const int i16 = lane & 15, kg = lane >> 4;
-    f32x4 acc[TI][TJ];
+        // ---- layer 3 backward, layer 2 deltas (dz2^T to LDS), b2 and w3 sums
+        uint32_t dz2p[8][2];
 #pragma unroll
-    for (int i = 0; i < TI; ++i)
+        for (int n = 0; n < 8; ++n) {
+            const float4 w3 = *reinterpret_cast<const float4*>(L.pb + pW3 + 16 * n + 4 * kg);
+            const float w3v[4] = {w3.x, w3.y, w3.z, w3.w};
+            float d[4];
 #pragma unroll
-        for (int j = 0; j < TJ; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const bf16_t* La[TI];
-    const bf16_t* Rb[TJ];
-#pragma unroll
-    for (int i = 0; i < TI; ++i) La[i] = L + (int64_t)(r0 + 16 * i + i16) * K + 8 * kg;
-#pragma unroll
-    for (int j = 0; j < TJ; ++j) Rb[j] = Rt + (int64_t)(c0 + 16 * j + i16) * K + 8 * kg;
-    // the next k step's fragments are loaded while this one's MFMAs run
-    bf16x8 av[TI], bv[TJ];
-    if (kb0 < kb1) {
-#pragma unroll
-        for (int i = 0; i < TI; ++i) av[i] = load_bf16x8(La[i] + kb0);
-#pragma unroll
-        for (int j = 0; j < TJ; ++j) bv[j] = load_bf16x8(Rb[j] + kb0);
-    }
-    for (int kb = kb0; kb < kb1; kb += 32) {
-        bf16x8 an[TI], bn[TJ];
-        const int kn = kb + 32 < kb1 ? kb + 32 : kb;
-#pragma unroll
-        for (int i = 0; i < TI; ++i) an[i] = load_bf16x8(La[i] + kn);
-#pragma unroll
-        for (int j = 0; j < TJ; ++j) bn[j] = load_bf16x8(Rb[j] + kn);
-#pragma unroll
-        for (int i = 0; i < TI; ++i)
-#pragma unroll
-            for (int j = 0; j < TJ; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[j], acc[i][j], 0, 0, 0);
-#pragma unroll
-        for (int i = 0; i < TI; ++i) av[i] = an[i];
-#pragma unroll
-        for (int j = 0; j < TJ; ++j) bv[j] = bn[j];
-    }
-#pragma unroll
-    for (int i = 0; i < TI; ++i)
-#pragma unroll
-        for (int j = 0; j < TJ; ++j)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) out[(r0 + 16 * i + 4 * kg + v) * kH + c0 + 16 * j + i16] = acc[i][j][v];
-}
-
-// blockIdx.x = 2: the forward/backward workgroups' partial sums (biases,
-// w3, b3, loss) of blocks [ks bc, (ks + 1) bc), summed in order, into the
-// row's block-sum slots.
-__global__ __launch_bounds__(256) void k_mlp_wgrad(const bf16_t* XT, const bf16_t* dz1T, const bf16_t* h1T,
-                                                   const bf16_t* dz2T, int32_t K, int32_t Kc, const float* part,
-                                                   int32_t blocks, int32_t bc, float* wpart)
-{
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int ks = blockIdx.y;
-    const int kb0 = ks * Kc, kb1 = min(K, (ks + 1) * Kc);   // Kc and K: multiples of 32
-    float* out = wpart + (int64_t)ks * kWRow;
-    if (blockIdx.x == 0) {
-        wgrad_tile<4, 4>(h1T, dz2T, K, kb0, kb1, 64 * (wid >> 1), 64 * (wid & 1), out + oW2, lane);
-    } else if (blockIdx.x == 1) {
-        wgrad_tile<2, 2>(XT, dz1T, K, kb0, kb1, 0, 32 * wid, out + oW1, lane);
-    } else {
-        const int b0 = ks * bc, b1 = min(blocks, (ks + 1) * bc);
-        for (int k = threadIdx.x; k < kPart; k += 256) {
-            float s = 0.f;
-            for (int b = b0; b < b1; ++b) s += part[(int64_t)b * kPart + k];
-            out[ob2 + k] = s;
+            for (int v = 0; v < 4; ++v) d[v] = dout * w3v[v] * gp2[n][v];
+            dz2p[n][0] = pack_bf16(d[0], d[1]);
+            dz2p[n][1] = pack_bf16(d[2], d[3]);
+            put_transposed(L.dT, 16 * n + 4 * kg + qb, r0 + 4 * qa, dz2p[n][0], dz2p[n][1], qb);
+            // unit 16n + 4kg + qb's sums (the row's four quads write the same value)
+            part[kH + 16 * n + 4 * kg + qb] += row16_sum4(d[0], d[1], d[2], d[3], qb);
+            part[2 * kH + 16 * n + 4 * kg + qb] +=
+                row16_sum4(h2[n][0] * dout, h2[n][1] * dout, h2[n][2] * dout, h2[n][3] * dout, qb);
         }
+
+        // ---- dgrad of layer 2 (dh1^T = W2 dz2^T) through GELU; b1 sums
+        uint32_t dz1p[8][2];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const f32x4 acc = hidden_product(L.w2q, dz2p, t, i16, kg);
+            float d[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) d[v] = acc[v] * gp1[t][v];
+            dz1p[t][0] = pack_bf16(d[0], d[1]);
+            dz1p[t][1] = pack_bf16(d[2], d[3]);
+            part[16 * t + 4 * kg + qb] += row16_sum4(d[0], d[1], d[2], d[3], qb);
+        }
+        // b3 and the loss (quad lanes 0 and 1; lanes 2 and 3 add zeros to the
+        // padding after them)
+        part[3 * kH + qb] += row16_sum4(dout, lossp, 0.f, 0.f, qb);
+        __syncthreads();
+
+        // ---- dW2[:, 16w ..] += h1^T dz2 over the tile's 128 rows
+        {
+            bf16x8 bq[4];
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) bq[ks] = lds_bf16x8(sw128(L.dT, r0 + i16, 32 * ks + 8 * kg));
+#pragma unroll
+            for (int it = 0; it < 8; ++it)
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks)
+                    acc2[it] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        lds_bf16x8(sw128(L.hT, 16 * it + i16, 32 * ks + 8 * kg)), bq[ks], acc2[it], 0, 0, 0);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 8; ++t) put_transposed(L.hT, 16 * t + 4 * kg + qb, r0 + 4 * qa, dz1p[t][0], dz1p[t][1], qb);
+        __syncthreads();
+
+        // ---- dW1[:, 16w ..] += Xn^T dz1
+#pragma unroll
+        for (int ks = 0; ks < 4; ++ks) {
+            const bf16x8 bq = lds_bf16x8(sw128(L.hT, r0 + i16, 32 * ks + 8 * kg));
+#pragma unroll
+            for (int ft = 0; ft < 2; ++ft)
+                acc1[ft] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    lds_bf16x8(sw128(L.xT, 16 * ft + i16, 32 * ks + 8 * kg)), bq, acc1[ft], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+
+    // ---- the workgroup's partial row: lane (o = 16w + i16, kg) holds rows
+    // 16it + 4kg + v of dW2 and 16ft + 4kg + v of dW1
+    float* dst = a.wpart + (int64_t)blockIdx.x * kWRow;
+#pragma unroll
+    for (int it = 0; it < 8; ++it)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dst[oW2 + (16 * it + 4 * kg + v) * kH + r0 + i16] = acc2[it][v];
+#pragma unroll
+    for (int ft = 0; ft < 2; ++ft)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dst[oW1 + (16 * ft + 4 * kg + v) * kH + r0 + i16] = acc1[ft][v];
+    for (int k = threadIdx.x; k < kPart; k += blockDim.x) {
+        float t = L.part[0][k];
+#pragma unroll
+        for (int w = 1; w < kMlpWaves; ++w) t += L.part[w][k];
+        dst[ob2 + k] = t;
     }
 }
 
@@ -435,20 +554,27 @@ struct UpdateArgs {
 };
 
 // Gradient assembly and Adam: 64 parameters per workgroup, sixteen threads
-// per parameter, thread q summing the partial rows q, q + 16, ... in eight
-// interleaved running sums joined in a fixed order, the sixteen sums then
+// per parameter, thread q summing the partial rows q, q + 16, ... in sixteen
+// interleaved running sums (all its loads in flight at once for up to 256
+// rows) joined pairwise in a fixed order, the sixteen threads' sums then
 // added in a fixed order.  Index kParams is the loss.
 constexpr int kUpdSlices = 16;
 
 __device__ inline float strided_sum(const float* base, int64_t stride, int count, int q)
 {
-    float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    int k = q, j = 0;
-    for (; k + 7 * kUpdSlices < count; k += 8 * kUpdSlices)
+    float acc[16];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) acc[t] += base[(int64_t)(k + t * kUpdSlices) * stride];
-    for (; k < count; k += kUpdSlices, ++j) acc[j & 7] += base[(int64_t)k * stride];
-    return ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+    for (int j = 0; j < 16; ++j) acc[j] = 0.f;
+    int k = q;
+    for (; k + 15 * kUpdSlices < count; k += 16 * kUpdSlices)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[j] += base[(int64_t)(k + j * kUpdSlices) * stride];
+    for (int j = 0; k < count; k += kUpdSlices, ++j) acc[j] += base[(int64_t)k * stride];
+#pragma unroll
+    for (int h = 8; h >= 1; h >>= 1)
+#pragma unroll
+        for (int j = 0; j < h; ++j) acc[j] += acc[j + h];
+    return acc[0];
 }
 
 __global__ __launch_bounds__(1024) void k_mlp_update(const UpdateArgs u)
@@ -539,13 +665,9 @@ struct mcinv_mlp {
     int64_t N = 0;
     // step buffers
     int32_t Rcap = 0;
-    float* wpart = nullptr;  // [ks][ob2]
+    int32_t cus = 0;         // compute units: training workgroups per step (at most)
+    float* wpart = nullptr;  // [cus][kWRow]
     int64_t* idx = nullptr;
-    bf16_t* XT = nullptr;
-    bf16_t* h1T = nullptr;
-    bf16_t* dz2T = nullptr;
-    bf16_t* dz1T = nullptr;
-    float* part = nullptr;
     float* loss = nullptr;
     std::string err;
 };
@@ -578,36 +700,12 @@ mcinv_status merr(mcinv_mlp* m, mcinv_status code, const std::string& msg)
                         std::string(#expr) + ": " + hipGetErrorString(e_));                     \
     } while (0)
 
-#ifndef MCINV_MLP_WGRAD_ROWS
-#define MCINV_MLP_WGRAD_ROWS 256
-#endif
-// Row splits of the weight-gradient GEMMs: about MCINV_MLP_WGRAD_ROWS rows
-// each, at most 512.
-int32_t ks_of(int32_t R) { return std::max(1, std::min(512, R / MCINV_MLP_WGRAD_ROWS)); }
-int32_t kc_of(int32_t R)
-{
-    const int32_t ks = ks_of(R);
-    return ((R + ks - 1) / ks + 31) / 32 * 32;
-}
-
 mcinv_status ensure_step(mcinv_mlp* m, int32_t R)
 {
     if (R <= m->Rcap) return MCINV_OK;
     m->Rcap = 0;   // until every buffer below is allocated again
     mfree(m->idx);
-    mfree(m->XT);
-    mfree(m->h1T);
-    mfree(m->dz2T);
-    mfree(m->dz1T);
-    mfree(m->part);
-    mfree(m->wpart);
     MHIP(m, hipMalloc((void**)&m->idx, sizeof(int64_t) * R));
-    MHIP(m, hipMalloc((void**)&m->wpart, sizeof(float) * kWRow * (size_t)ks_of(R)));
-    MHIP(m, hipMalloc((void**)&m->XT, sizeof(bf16_t) * kF * (size_t)R));
-    MHIP(m, hipMalloc((void**)&m->h1T, sizeof(bf16_t) * kH * (size_t)R));
-    MHIP(m, hipMalloc((void**)&m->dz2T, sizeof(bf16_t) * kH * (size_t)R));
-    MHIP(m, hipMalloc((void**)&m->dz1T, sizeof(bf16_t) * kH * (size_t)R));
-    MHIP(m, hipMalloc((void**)&m->part, sizeof(float) * kPart * (size_t)((R + 63) / 64)));
     m->Rcap = R;
     return MCINV_OK;
 }
@@ -641,18 +739,10 @@ mcinv_status run_step(mcinv_mlp* m, int32_t R, bool apply, float lr, float* loss
     a.step = (uint32_t)(m->t + 1);
     a.N = m->N;
     a.R = R;
-    a.XT = m->XT;
-    a.h1T = m->h1T;
-    a.dz2T = m->dz2T;
-    a.dz1T = m->dz1T;
-    a.part = m->part;
+    a.wpart = m->wpart;
     a.inv_denom = 1.0f / (float)R;
-    const int blocks = R / 64;
-    k_mlp_fwd_bwd<true><<<dim3(blocks), dim3(256), 0, m->stream>>>(a);
-    MHIP(m, hipGetLastError());
-    const int32_t kc = kc_of(R), nks = (R + kc - 1) / kc, bc = (blocks + nks - 1) / nks;
-    k_mlp_wgrad<<<dim3(3, nks), dim3(256), 0, m->stream>>>(m->XT, m->dz1T, m->h1T, m->dz2T, R, kc, m->part, blocks,
-                                                          bc, m->wpart);
+    const int32_t nks = std::min((R + kMlpRows - 1) / kMlpRows, m->cus);
+    k_mlp_train<<<dim3(nks), dim3(64 * kMlpWaves), 0, m->stream>>>(a);
     MHIP(m, hipGetLastError());
     UpdateArgs u{};
     u.P = m->P;
@@ -697,7 +787,7 @@ mcinv_status mlp_predict_device(mcinv_mlp* m, const float* dX, int64_t N, float*
         a.row0 = r0;
         a.R = (int32_t)std::min<int64_t>(chunk, N - r0);
         a.out = dout + r0;
-        k_mlp_fwd_bwd<false><<<dim3((unsigned)((a.R + 63) / 64)), dim3(256), 0, m->stream>>>(a);
+        k_mlp_forward<<<dim3((unsigned)((a.R + kMlpRows - 1) / kMlpRows)), dim3(64 * kMlpWaves), 0, m->stream>>>(a);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
@@ -725,7 +815,10 @@ try {
         return merr(nullptr, MCINV_ENOMEM, "device allocation failed");
     };
     if (hipStreamCreate(&m->stream) != hipSuccess) return fail_alloc();
-    if (hipMalloc((void**)&m->P, sizeof(float) * kParams) != hipSuccess ||
+    if (hipDeviceGetAttribute(&m->cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || m->cus < 1)
+        return merr(nullptr, MCINV_EDEVICE, "cannot read the device's compute unit count");
+    if (hipMalloc((void**)&m->wpart, sizeof(float) * kWRow * (size_t)m->cus) != hipSuccess ||
+        hipMalloc((void**)&m->P, sizeof(float) * kParams) != hipSuccess ||
         hipMalloc((void**)&m->m, sizeof(float) * kParams) != hipSuccess ||
         hipMalloc((void**)&m->v, sizeof(float) * kParams) != hipSuccess ||
         hipMalloc((void**)&m->grads, sizeof(float) * kParams) != hipSuccess ||
@@ -768,11 +861,6 @@ void mcinv_mlp_destroy(mcinv_mlp* m)
     mfree(m->y);
     mfree(m->w);
     mfree(m->idx);
-    mfree(m->XT);
-    mfree(m->h1T);
-    mfree(m->dz2T);
-    mfree(m->dz1T);
-    mfree(m->part);
     mfree(m->wpart);
     if (m->stream) (void)hipStreamDestroy(m->stream);
     delete m;
