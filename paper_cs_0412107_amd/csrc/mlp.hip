@@ -553,12 +553,12 @@ struct UpdateArgs {
     float* loss_out;         // loss of this step, or null
 };
 
-// Gradient assembly and Adam: 64 parameters per workgroup, sixteen threads
-// per parameter, thread q summing the partial rows q, q + 16, ... in sixteen
-// interleaved running sums (all its loads in flight at once for up to 256
-// rows) joined pairwise in a fixed order, the sixteen threads' sums then
-// added in a fixed order.  Index kParams is the loss.
-constexpr int kUpdSlices = 16;
+// Gradient assembly and Adam: 128 parameters per workgroup (one round of
+// workgroups over the device), eight threads per parameter, thread q summing
+// the partial rows q, q + 8, ... in sixteen interleaved running sums joined
+// pairwise in a fixed order, the eight threads' sums then added in a fixed
+// order.  Index kParams is the loss.
+constexpr int kUpdParams = 128, kUpdSlices = 8;
 
 __device__ inline float strided_sum(const float* base, int64_t stride, int count, int q)
 {
@@ -579,9 +579,9 @@ __device__ inline float strided_sum(const float* base, int64_t stride, int count
 
 __global__ __launch_bounds__(1024) void k_mlp_update(const UpdateArgs u)
 {
-    __shared__ float red[kUpdSlices][64];
-    const int c = threadIdx.x & 63, q = threadIdx.x >> 6;
-    const int p = blockIdx.x * 64 + c;
+    __shared__ float red[kUpdSlices][kUpdParams];
+    const int c = threadIdx.x % kUpdParams, q = threadIdx.x / kUpdParams;
+    const int p = blockIdx.x * kUpdParams + c;
     float s = 0.f;
     if (p <= kParams) {
         int col;
@@ -767,7 +767,7 @@ mcinv_status run_step(mcinv_mlp* m, int32_t R, bool apply, float lr, float* loss
     u.W2T = m->W2T;
     u.W2 = m->W2;
     u.loss_out = loss_dev;
-    k_mlp_update<<<dim3((kParams + 1 + 63) / 64), dim3(64 * kUpdSlices), 0, m->stream>>>(u);
+    k_mlp_update<<<dim3((kParams + kUpdParams) / kUpdParams), dim3(kUpdParams * kUpdSlices), 0, m->stream>>>(u);
     MHIP(m, hipGetLastError());
     return MCINV_OK;
 }
