@@ -555,23 +555,24 @@ struct UpdateArgs {
 
 // Gradient assembly and Adam: 128 parameters per workgroup (one round of
 // workgroups over the device), eight threads per parameter, thread q summing
-// the partial rows q, q + 8, ... in sixteen interleaved running sums joined
-// pairwise in a fixed order, the eight threads' sums then added in a fixed
-// order.  Index kParams is the loss.
-constexpr int kUpdParams = 128, kUpdSlices = 8;
+// the partial rows q, q + 8, ... in 32 interleaved running sums (all its
+// loads in flight at once for up to 256 partial rows) joined pairwise in a
+// fixed order, the eight threads' sums then added in a fixed order.  Index
+// kParams is the loss.
+constexpr int kUpdParams = 128, kUpdSlices = 8, kUpdAcc = 32;
 
 __device__ inline float strided_sum(const float* base, int64_t stride, int count, int q)
 {
-    float acc[16];
+    float acc[kUpdAcc];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) acc[j] = 0.f;
+    for (int j = 0; j < kUpdAcc; ++j) acc[j] = 0.f;
     int k = q;
-    for (; k + 15 * kUpdSlices < count; k += 16 * kUpdSlices)
+    for (; k + (kUpdAcc - 1) * kUpdSlices < count; k += kUpdAcc * kUpdSlices)
 #pragma unroll
-        for (int j = 0; j < 16; ++j) acc[j] += base[(int64_t)(k + j * kUpdSlices) * stride];
+        for (int j = 0; j < kUpdAcc; ++j) acc[j] += base[(int64_t)(k + j * kUpdSlices) * stride];
     for (int j = 0; k < count; k += kUpdSlices, ++j) acc[j] += base[(int64_t)k * stride];
 #pragma unroll
-    for (int h = 8; h >= 1; h >>= 1)
+    for (int h = kUpdAcc / 2; h >= 1; h >>= 1)
 #pragma unroll
         for (int j = 0; j < h; ++j) acc[j] += acc[j + h];
     return acc[0];
