@@ -18,8 +18,10 @@
 //   k_mlp_update  : gradient assembly (the partial rows summed in a fixed
 //                   order), Adam step, bf16 copies of the weights.
 // Rounding points (what the oracle reproduces): the normalised features,
-// W1, W2, h1 and dz2 enter MFMA products as bf16 (nearest even); h2, w3, the
-// biases and every elementwise step stay fp32.
+// W1, W2, h1, dz2 and dz1 enter MFMA products as bf16 (nearest even); h2,
+// w3, the biases and every elementwise step stay fp32.  GELU and its
+// derivative use an erf approximation with absolute error at most 1.5e-7
+// (gelu_terms), far below the bf16 rounding that follows.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -47,12 +49,6 @@ typedef unsigned short bf16_t;
 
 // round to nearest even (one v_cvt_pk_bf16_f32 on gfx950)
 __device__ inline bf16_t to_bf16(float x) { return __builtin_bit_cast(bf16_t, (__bf16)x); }
-
-__device__ inline bf16x8 load_bf16x8(const bf16_t* p)
-{
-    const uint4 u = *reinterpret_cast<const uint4*>(p);
-    return __builtin_bit_cast(bf16x8, u);
-}
 
 struct MlpArgs {
     const float* X;          // raw features [N][32]
