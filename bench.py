@@ -392,13 +392,18 @@ def qtrace_form(pkg, torch, gen, w, steps=20):
 MLP_FLOP_PER_ROW_STEP = 2 * (32 * 128 + 128 * 128 + 128) + 2 * (2 * 128 + 2 * 128 * 128 + 32 * 128)
 
 
-def surrogate_form(pkg, torch, gen, n_train, n_val, rel_label=0.005, rel=0.01, steps=2000, batch=65536):
+def surrogate_form(pkg, torch, gen, n_train, n_val, rel_label=0.005, rel=0.01, steps=2000, batch=65536,
+                   noise=None):
     """Learned-surrogate workload: pedigree matrices with random generator
     parameters (n = 2e4) labelled by the batched sampler to rel_label, 32
     features per row, the network trained on the labelled rows, a gate fitted
     on validation matrices, then a held-out matrix (n = 1e6): surrogate plus
-    sampler fallback versus the plain sampler to 1% on every row."""
+    sampler fallback versus the plain sampler to 1% on every row.  Every
+    sampler of the form (labels, fallback rows, the plain comparison) draws
+    the same noise law: Z2 by default (Sec. 1's preferred law, which on these
+    diagonal-dominant matrices needs fewer sweeps)."""
     from paper_cs_0412107_amd import surrogate as sur
+    noise = pkg.MCINV_NOISE_RADEMACHER if noise is None else noise
     w = gen.WORKLOADS["surrogate"]
     qs = gen.surrogate_params(n_train + n_val + 1, seed=w["seed"])
 
@@ -412,7 +417,8 @@ def surrogate_form(pkg, torch, gen, n_train, n_val, rel_label=0.005, rel=0.01, s
     bw = gen.WORKLOADS["batched"]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    b = pkg.BatchSampler(mats, pairs=bw["pairs"], groups=bw["groups"], seed=w["noise_seed"], use_torch_stream=True)
+    b = pkg.BatchSampler(mats, pairs=bw["pairs"], groups=bw["groups"], seed=w["noise_seed"], noise=noise,
+                         use_torch_stream=True)
     b.autotune(1)
     b.burn_in_coupled(BURN_TOL, 10000)
     b.request(diag=True)
@@ -459,9 +465,9 @@ def surrogate_form(pkg, torch, gen, n_train, n_val, rel_label=0.005, rel=0.01, s
 
     m = make(qs[-1], w["eval_n"])
     P, G = 1024, 16
-    plain = time_to_1pct(pkg, torch, m, P, G, w["noise_seed"] + 1, "f32", "fp64", "coupled", rel=rel)
+    plain = time_to_1pct(pkg, torch, m, P, G, w["noise_seed"] + 1, "f32", "fp64", "coupled", rel=rel, noise=noise)
     burn = plain["burn_in"]
-    with pkg.Sampler(m, pairs=P, groups=G, dtype="f32", seed=w["noise_seed"] + 1) as s:
+    with pkg.Sampler(m, pairs=P, groups=G, dtype="f32", seed=w["noise_seed"] + 1, noise=noise) as s:
         s.burn_in(burn)
         s.request(diag=True, trace=False)
         s.sample(plain["sample_sweeps"])
@@ -470,7 +476,7 @@ def surrogate_form(pkg, torch, gen, n_train, n_val, rel_label=0.005, rel=0.01, s
     t0 = time.perf_counter()
     est, src, info = sur.estimate_diag(
         m, net, gate, lambda mm: pkg.Sampler(mm, pairs=P, groups=G, dtype="f32", seed=w["noise_seed"] + 1,
-                                             use_torch_stream=True),
+                                             noise=noise, use_torch_stream=True),
         rel_se=rel, max_sweeps=20000, check_every=10, burn_in="coupled")
     torch.cuda.synchronize()
     t_sur = time.perf_counter() - t0
@@ -489,6 +495,7 @@ def surrogate_form(pkg, torch, gen, n_train, n_val, rel_label=0.005, rel=0.01, s
     return {
         "workload": f"{n_train} train + {n_val} validation pedigree matrices (n={w['train_n']}, random "
                     f"dominance 1.2-2.0, lambda 0-0.5, founders 2-20%), held-out n={m.n}",
+        "noise": "Z2 (Rademacher)" if noise == pkg.MCINV_NOISE_RADEMACHER else "normal",
         "labels": {"seconds": t_label, "sample_sweeps": lab_sweeps, "max_rel_se": lab_ach,
                    "rows": int(sum(x.n for x in mats)), "form": "batched sampler, 64 pairs per matrix, each matrix stopped at its own 0.5%"},
         "features": {"seconds": t_feat, "rows": int(sum(x.n for x in mats)),
