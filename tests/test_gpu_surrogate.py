@@ -119,7 +119,10 @@ def test_fit_normalization_and_weights_match_oracle():
     np.testing.assert_allclose(mc.mcinv_mlp_label_weights(se, 1e-6), S.label_weights(se, 1e-6), rtol=1e-6)
 
 
-@pytest.mark.parametrize("R", [256, 64])
+# 41024 rows: 321 tiles of 128 rows, so workgroups run two tiles each (the
+# persistent loop, its next-tile prefetch and sums across tiles) and the last
+# tile is half empty
+@pytest.mark.parametrize("R", [256, 64, 41024])
 def test_gradients_match_oracle(R):
     print_case(test="mlp_gradients", R=R)
     p, X, y, w, mean, inv = _net_case(13, 1000)
@@ -139,13 +142,14 @@ def test_gradients_match_oracle(R):
     assert abs(loss - rloss) <= 1e-4 * rloss
 
 
-def test_adam_steps_match_oracle():
+@pytest.mark.parametrize("R", [128, 41024])
+def test_adam_steps_match_oracle(R):
     """Three Adam steps on Philox-drawn batches.  The first Adam step moves each
     weight by about lr * sign(g), so weights whose gradient is near zero may move
     either way: those are checked against Adam's step bound only."""
-    print_case(test="mlp_train")
+    print_case(test="mlp_train", R=R)
     p, X, y, w, mean, inv = _net_case(14, 777)
-    steps, R, lr, seed = 3, 128, 1e-3, 0xC0FFEE
+    steps, lr, seed = 3, 1e-3, 0xC0FFEE
     p0 = S.flatten(p).astype(np.float32)
     with sur.Network(params=p0) as net:
         net.set_data(X, y, w, normalize=False)
