@@ -700,7 +700,7 @@ mcinv_status merr(mcinv_mlp* m, mcinv_status code, const std::string& msg)
 mcinv_status ensure_step(mcinv_mlp* m, int32_t R)
 {
     if (R <= m->Rcap) return MCINV_OK;
-    m->Rcap = 0;   // until every buffer below is allocated again
+    m->Rcap = 0;   // until the row list is allocated again
     mfree(m->idx);
     MHIP(m, hipMalloc((void**)&m->idx, sizeof(int64_t) * R));
     m->Rcap = R;
@@ -719,9 +719,11 @@ MlpArgs base_args(mcinv_mlp* m)
     return a;
 }
 
-// One forward/backward over R rows and the gradient assembly; with `apply`,
-// the Adam step.  The rows: drawn from Philox (key = seed, counter word 1 =
-// the step about to be taken) with `draw`, else the list in m->idx.
+// One training step over R rows: the fused kernel (one partial row per
+// workgroup, at most one workgroup per compute unit), then the gradient
+// assembly and, with `apply`, the Adam step.  The rows: drawn from Philox
+// (key = seed, counter word 1 = the step about to be taken) with `draw`,
+// else the list in m->idx.
 mcinv_status run_step(mcinv_mlp* m, int32_t R, bool apply, float lr, float* loss_dev, bool draw = false,
                       uint64_t seed = 0)
 {
