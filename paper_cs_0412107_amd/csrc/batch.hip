@@ -35,7 +35,15 @@ struct alignas(16) Quad4 {
     float v[4];
 };
 
-__device__ inline void batch_rows(const BatchArgs& a, const BItem& it, int64_t sweep, int64_t sample)
+// The rows of an item are consecutive positions, so their merged entries
+// form one contiguous range; up to kBatchLdsEnt of them (16 KB) are staged in
+// LDS once per item and every lane of a row reads its entries from there.
+constexpr int kBatchLdsEnt = 1024;
+
+// eb + (rr.begin - e0) is row rr's first entry (eb: the item's staged
+// entries with e0 their first index, or the global array with e0 = 0)
+__device__ inline void batch_rows_from(const BatchArgs& a, const BItem& it, int64_t sweep, int64_t sample,
+                                       const Entry<float>* eb, int64_t e0)
 {
     constexpr int U = MCINV_GATHER_U4;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -53,7 +61,7 @@ __device__ inline void batch_rows(const BatchArgs& a, const BItem& it, int64_t s
         if (q >= it.row_end) continue;  // whole rows (groups never span rows)
         const RowRec rr = a.rows[q];
         float az[4] = {0.f, 0.f, 0.f, 0.f}, aw[4] = {0.f, 0.f, 0.f, 0.f};
-        const Entry<float>* e = a.ent + rr.begin;
+        const Entry<float>* e = eb + (rr.begin - e0);
         for (int b = 0; b < rr.count; b += U) {
             Quad4 xs[U], ys[U];
             float us[U], vs[U];
@@ -99,6 +107,25 @@ __device__ inline void batch_rows(const BatchArgs& a, const BItem& it, int64_t s
             for (int off = 1; off < lgb; off <<= 1) pr += __shfl_xor(pr, off);
             if ((lr & (lgb - 1)) == 0) a.diag[(slot * a.nrows + q) * a.G + lr / lgb] += pr;
         }
+    }
+}
+
+// Called by every thread of the workgroup (the staging ends in a barrier);
+// both schedules also separate consecutive items by a barrier, so the staged
+// entries are not replaced while a wave still reads them.
+__device__ inline void batch_rows(const BatchArgs& a, const BItem& it, int64_t sweep, int64_t sample)
+{
+    __shared__ Entry<float> s_ent[kBatchLdsEnt];
+    if (it.row_end <= it.row_begin) return;   // no rows (the same for the whole workgroup)
+    const int64_t e0 = a.rows[it.row_begin].begin;
+    const RowRec last = a.rows[it.row_end - 1];
+    const int64_t ne = last.begin + last.count - e0;
+    if (ne <= kBatchLdsEnt) {
+        for (int64_t k = threadIdx.x; k < ne; k += blockDim.x) s_ent[k] = a.ent[e0 + k];
+        __syncthreads();
+        batch_rows_from(a, it, sweep, sample, s_ent, e0);
+    } else {
+        batch_rows_from(a, it, sweep, sample, a.ent, 0);
     }
 }
 
