@@ -45,6 +45,27 @@ def test_batched_states_equal_single_path(mats, schedule, noise):
                     assert np.array_equal(b.state(m, which), s.state(which)), (m, which)
 
 
+def test_batched_hub_row_states_equal_single_path():
+    """A merged row of ~2500 entries: the item holding it exceeds the entries
+    staged in LDS per item and reads them from global memory, while the other
+    items of the same launches are staged; both schedules must still give the
+    single path's chains bit for bit."""
+    from test_gpu_parity import _matrix
+    hub = gen.round_values(_matrix("hub2500"), np.float32)
+    mats = [gen.round_values(gen.pedigree(900, seed=701), np.float32), hub,
+            gen.round_values(gen.pedigree(1700, seed=702), np.float32)]
+    P, G, seed = 64, 16, 0x5151
+    for schedule in (0, 1):
+        print_case(test="batch_hub_states", schedule=schedule)
+        with mc.BatchSampler(mats, pairs=P, groups=G, seed=seed, rows_per_item=16, grab=2, schedule=schedule) as b:
+            b.burn_in(3)
+            for m in range(len(mats)):
+                with mc.Sampler(mats[m], pairs=P, groups=G, dtype="f32", seed=seed, stream_id=m) as s:
+                    s.burn_in(3)
+                    for which in (0, 1):
+                        assert np.array_equal(b.state(m, which), s.state(which)), (schedule, m, which)
+
+
 def test_batched_matches_oracle(mats):
     P, G, seed = 64, 16, 11
     m = 5
