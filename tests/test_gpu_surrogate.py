@@ -121,8 +121,8 @@ def test_fit_normalization_and_weights_match_oracle():
 
 # 41024 rows: 321 tiles of 128 rows, so workgroups run two tiles each (the
 # persistent loop, its next-tile prefetch and sums across tiles) and the last
-# tile is half empty
-@pytest.mark.parametrize("R", [256, 64, 41024])
+# tile is half empty; 262144 rows: eight tiles per workgroup
+@pytest.mark.parametrize("R", [256, 64, 41024, 262144])
 def test_gradients_match_oracle(R):
     print_case(test="mlp_gradients", R=R)
     p, X, y, w, mean, inv = _net_case(13, 1000)
