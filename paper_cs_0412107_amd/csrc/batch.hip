@@ -1,9 +1,11 @@
 // Batched form: hundreds of matrices of uneven size, each with P chain pairs,
-// swept by ONE persistent launch (Sec. 2 eqs 4-5 for every matrix; moments of
-// eq 1/C).
+// swept together (Sec. 2 eqs 4-5 for every matrix; moments of eq 1/C) by one
+// persistent launch per call or by a graph of phase launches; the autotuner
+// keeps the faster (the phased graph, on the pedigree batches measured).
 //
-// Work items are (sweep, colour, matrix, chunk of rows) plus, when sampling
-// with a requested block, one block-moment item per (sweep, matrix).  Items
+// Persistent schedule.  Work items are (sweep, colour, matrix, chunk of
+// rows) plus, when sampling with a requested block, one block-moment item
+// per (sweep, matrix).  Items
 // are numbered sweep-major, then colour, then matrix, and workgroups take
 // them in increasing order from a device counter (a few at a time).  A
 // matrix's items of one phase may start only when all of its items of the
@@ -14,8 +16,9 @@
 // handed out earlier, so the oldest unfinished item can always run; a wait
 // that exceeds its bound sets an error flag and every workgroup exits.
 //
-// A second, phased schedule runs the same item code with one launch per
-// phase instead (see k_batch_rows); the host times both and keeps the faster.
+// Phased schedule: the same item code with one launch per phase (see
+// k_batch_rows).  Either way a row item first stages its rows' merged entries
+// in LDS (batch_rows).
 //
 // Lane layout: a row's P pairs are spread over P/4 lanes (4 pairs each, one
 // Philox block per lane); a wave holds 256/P rows.  The gather, noise and
