@@ -486,11 +486,13 @@ mcinv_status mcinv_features_noalloc(int32_t device, int64_t n, int64_t nnz, cons
  *   w3[128], b3.
  * Features are normalised as (x - mean) * inv_std before the first layer.
  * Products run on the matrix cores with bf16 operands (round to nearest even:
- * the normalised features, W1, W2, the first hidden activations and the
- * second layer's deltas) and fp32 accumulation; everything else is fp32.
+ * the normalised features, W1, W2, the first hidden activations and both
+ * hidden layers' deltas) and fp32 accumulation; everything else is fp32, the
+ * GELU through an erf approximation with absolute error at most 1.5e-7.
  * Training minimises sum_r w_r (out_r - y_r)^2 / R over batches of R rows
  * with Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected) on fp32
- * master weights.  Zero-initialised parameters until set. */
+ * master weights; every sum runs in a fixed order, so training is
+ * reproducible on one device.  Zero-initialised parameters until set. */
 #define MCINV_MLP_PARAMS 20865
 typedef struct mcinv_mlp mcinv_mlp;
 
