@@ -174,6 +174,23 @@ def test_adam_steps_match_oracle(R):
     assert np.mean(diff <= 0.05 * lr) >= 0.99, np.mean(diff <= 0.05 * lr)
 
 
+def test_training_is_reproducible():
+    """Every sum of a training step runs in a fixed order: two runs from the same
+    parameters and seed end with the same bits."""
+    print_case(test="mlp_train_repeat")
+    p, X, y, w, mean, inv = _net_case(15, 3000)
+    p0 = S.flatten(p).astype(np.float32)
+    out = []
+    for _ in range(2):
+        with sur.Network(params=p0) as net:
+            net.set_data(X, y, w, normalize=False)
+            net.set_normalization(mean, inv)
+            hist = net.train(4, 41024, 1e-3, 77)
+            out.append((np.asarray(hist), net.params()))
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+
+
 def test_train_errors():
     with sur.Network() as net:
         with pytest.raises(mc.McinvError) as ei:
